@@ -1,0 +1,502 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics,
+independent of the oracle's own code paths (brute-force searches, independent
+textbook routines, closed forms, invariants).  CPU only."""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+import oracle as O
+from paper_2107_05200_amd import meshgen as mg
+
+
+def rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+# ----------------------------------------------------------------------------
+# scalar roots
+# ----------------------------------------------------------------------------
+
+def _fs(p, energy):
+    # per-eigenvalue defining function on S+: SD 1/2(p^2 + p^-2), SG 1/2 p^2 - log p
+    return 0.5 * (p * p + 1.0 / (p * p)) if energy == O.SD else 0.5 * p * p - np.log(p)
+
+
+def _brute_min(q, w, mu, energy):
+    """Minimise phi(p) = w f(p) + mu/2 (p - q)^2 over p > 0 by a log grid and a
+    golden-section refinement in log p (no use of the stationarity equation)."""
+    # mu/2 (p-q)^2 without its constant mu q^2/2, so that large |q| does not
+    # swamp the resolution of the search
+    phi = lambda p: w * _fs(p, energy) + 0.5 * mu * p * p - mu * q * p
+    grid = np.exp(np.linspace(math.log(1e-6), math.log(1e4), 200001))
+    k = int(np.argmin(phi(grid)))
+    a = math.log(grid[max(k - 2, 0)])
+    b = math.log(grid[min(k + 2, grid.size - 1)])
+    g = (math.sqrt(5) - 1) / 2
+    c, d = b - g * (b - a), a + g * (b - a)
+    for _ in range(200):
+        if phi(math.exp(c)) < phi(math.exp(d)):
+            b = d
+        else:
+            a = c
+        c, d = b - g * (b - a), a + g * (b - a)
+    return math.exp(0.5 * (a + b))
+
+
+@pytest.mark.parametrize("energy", [O.SD, O.SG])
+def test_pin1_root_matches_brute_force_minimisation(energy):
+    r = rng(1)
+    qs = np.concatenate([r.uniform(-30, 30, 20), [-1e3, -5.0, -1e-3, 0.0, 1e-3, 1.0, 3.0, 1e3]])
+    for q in qs:
+        ratio = 10 ** r.uniform(-3, 3)  # w / mu in [1e-3, 1e3]
+        w, mu = ratio, 1.0
+        p_ref = _brute_min(q, w, mu, energy)
+        p = (O.root_sd if energy == O.SD else O.root_sg)(np.array([q]), w, mu)[0]
+        # the objective is flat at its minimum: a direct search resolves p to ~sqrt(eps)
+        assert abs(p - p_ref) <= 2e-7 * p_ref, (q, w, mu, p, p_ref)
+
+
+@pytest.mark.parametrize("energy", [O.SD, O.SG])
+def test_pin2_root_polynomial_residual(energy):
+    r = rng(2)
+    q = np.concatenate([r.uniform(-1e3, 1e3, 500), r.uniform(-2, 2, 500)])
+    w = 10 ** r.uniform(-3, 3, q.size)
+    mu = np.ones_like(q)
+    if energy == O.SG:
+        p = O.root_sg(q, w, mu)
+        terms = np.abs((w + mu) * p * p) + np.abs(mu * q * p) + w
+        res = (w + mu) * p * p - mu * q * p - w          # supplement eq. peqfsgpluggedin
+        assert np.all(np.abs(res) <= 4e-15 * terms)
+    else:
+        p = O.root_sd(q, w, mu)
+        terms = np.abs((w + mu) * p ** 4) + np.abs(mu * q * p ** 3) + w
+        res = (w + mu) * p ** 4 - mu * q * p ** 3 - w    # supplement eq. peqfsdpluggedin
+        assert np.all(np.abs(res) <= 1e-14 * terms)
+    assert np.all(p > 0)
+
+
+@pytest.mark.parametrize("energy", [O.SD, O.SG])
+def test_root_special_values(energy):
+    # q = 1 (the identity) is the root for every w, mu; the SG quadratic formula
+    # written out independently for a few values
+    w = np.array([1e-3, 0.1, 1.0, 7.0, 1e3])
+    f = O.root_sd if energy == O.SD else O.root_sg
+    assert np.allclose(f(np.ones(5), w, 1.0), 1.0, rtol=1e-15, atol=0)
+    if energy == O.SG:
+        from decimal import Decimal, getcontext
+        getcontext().prec = 50
+        for q in [-3.0, 0.5, 4.0]:
+            for ww in w:
+                Q, W = Decimal(q), Decimal(float(ww))
+                exact = float((Q + (Q * Q + 4 * W * (W + 1)).sqrt()) / (2 * (W + 1)))
+                assert abs(f(np.array([q]), ww, 1.0)[0] - exact) <= 1e-14 * exact
+
+
+# ----------------------------------------------------------------------------
+# matrix P-step and U-step
+# ----------------------------------------------------------------------------
+
+def _direct_pstep(S, w, mu, energy):
+    """Minimise w f(P) + mu/2 |P - S|^2 over P = L L^T with a general optimizer."""
+    d = S.shape[0]
+    il = np.tril_indices(d)
+
+    def obj(v):
+        Lm = np.zeros((d, d))
+        Lm[il] = v
+        P = Lm @ Lm.T
+        det = np.linalg.det(P)
+        if det <= 0:
+            return 1e30
+        if energy == O.SD:
+            f = 0.5 * (np.sum(P * P) + np.sum(np.linalg.inv(P) ** 2))
+        else:
+            f = 0.5 * np.sum(P * P) - math.log(det)
+        return w * f + 0.5 * mu * np.sum((P - S) ** 2)
+
+    v0 = np.eye(d)[il]
+    res = minimize(obj, v0, method="BFGS", options={"gtol": 1e-12, "maxiter": 10000})
+    res = minimize(obj, res.x, method="Nelder-Mead",
+                   options={"xatol": 1e-12, "fatol": 1e-16, "maxiter": 40000})
+    Lm = np.zeros((d, d))
+    Lm[il] = res.x
+    return Lm @ Lm.T
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("energy", [O.SD, O.SG])
+def test_pin3_matrix_pstep(d, energy):
+    r = rng(3 + d)
+    for trial in range(4):
+        A = r.normal(size=(d, d))
+        S = 0.5 * (A + A.T) + (1.5 if trial % 2 == 0 else 0.0) * np.eye(d)
+        w, mu = 1.0, 10 ** r.uniform(-1, 1)
+        P, p = O.p_step(S[None], np.array([w]), np.array([mu]), energy)
+        P = P[0]
+        P_ref = _direct_pstep(S, w, mu, energy)
+        assert np.allclose(P, P.T, atol=1e-14)
+        assert np.all(np.linalg.eigvalsh(P) > 0)
+        assert np.linalg.norm(P - P_ref) <= 1e-5 * max(1.0, np.linalg.norm(P_ref))
+        # stationarity w grad f(P) + mu P = mu S  (eq. rootfindinginp)
+        Pi = np.linalg.inv(P)
+        grad = P - Pi @ Pi @ Pi if energy == O.SD else P - Pi
+        assert np.linalg.norm(w * grad + mu * P - mu * S) <= 1e-12 * max(1.0, mu * np.linalg.norm(S))
+
+
+def test_pin4_rot2_brute_force_angle():
+    r = rng(4)
+    Q = r.normal(size=(50, 2, 2))
+    U = O.rot2(Q, np.tile(np.eye(2), (50, 1, 1)))
+    phis = np.linspace(0, 2 * np.pi, 720001)
+    for i in range(50):
+        val = np.cos(phis) * (Q[i, 0, 0] + Q[i, 1, 1]) + np.sin(phis) * (Q[i, 1, 0] - Q[i, 0, 1])
+        k = int(np.argmax(val))
+        a, b = phis[k] - 1e-5, phis[k] + 1e-5
+        f = lambda t: -(np.cos(t) * (Q[i, 0, 0] + Q[i, 1, 1]) + np.sin(t) * (Q[i, 1, 0] - Q[i, 0, 1]))
+        g = (math.sqrt(5) - 1) / 2
+        for _ in range(100):
+            c, d = b - g * (b - a), a + g * (b - a)
+            if f(c) < f(d):
+                b = d
+            else:
+                a = c
+        phi = 0.5 * (a + b)
+        phi_or = math.atan2(U[i, 1, 0], U[i, 0, 0])
+        dphi = (phi_or - phi + np.pi) % (2 * np.pi) - np.pi
+        assert abs(dphi) < 1e-7
+        assert abs(np.linalg.det(U[i]) - 1) < 1e-14
+
+
+def _quat_rot(qv):
+    w, x, y, z = qv
+    return np.array([
+        [w * w + x * x - y * y - z * z, 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), w * w - x * x + y * y - z * z, 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), w * w - x * x - y * y + z * z]])
+
+
+def _horn(Q):
+    """Rotation maximising tr(R^T Q) as the top eigenvector of the symmetric 4x4
+    matrix of the quadratic form q -> tr(R(q)^T Q) (Horn / Davenport); built by
+    polarisation, no SVD."""
+    f = lambda qv: np.sum(_quat_rot(qv) * Q)
+    E = np.eye(4)
+    N = np.empty((4, 4))
+    for a in range(4):
+        for b in range(4):
+            N[a, b] = 0.25 * (f(E[a] + E[b]) - f(E[a] - E[b]))
+    ev, V = np.linalg.eigh(N)
+    return _quat_rot(V[:, -1]), ev
+
+
+def test_pin5_rot3_against_quaternion_method():
+    r = rng(5)
+    Q = r.normal(size=(200, 3, 3))
+    # orthogonal inputs of both signs of det: det = -1 gives a tie (a circle of optima)
+    Q[:50] = np.linalg.qr(r.normal(size=(50, 3, 3)))[0]
+    Q[:25, :, 2] *= -1.0
+    U = O.rot3(Q)
+    checked = 0
+    for i in range(Q.shape[0]):
+        R, ev = _horn(Q[i])
+        assert abs(np.linalg.det(U[i]) - 1) < 1e-12
+        # the optimal value is the top eigenvalue of the quaternion form, ties or not
+        assert abs(np.sum(U[i] * Q[i]) - ev[-1]) < 1e-10 * max(1.0, abs(ev[-1]))
+        H = U[i].T @ Q[i]
+        assert np.allclose(H, H.T, atol=1e-10)  # U^T Q symmetric at the optimum
+        if ev[-1] - ev[-2] > 1e-6 * max(1.0, abs(ev[-1])):  # unique optimum
+            assert np.abs(U[i] - R).max() < 1e-9
+            checked += 1
+    assert checked > 160
+
+
+# ----------------------------------------------------------------------------
+# discretisation
+# ----------------------------------------------------------------------------
+
+def test_pin7_D_exactness_and_weights():
+    r = rng(7)
+    # planar triangles (d_in = d = 2) and tets: affine maps reproduced exactly
+    w2 = mg.hex_disk(6)
+    ring, tt, T = w2
+    phi = 2 * np.pi * tt / np.maximum(6 * ring, 1)
+    V = np.stack([ring * np.cos(phi), ring * np.sin(phi)], 1) / 6.0
+    V = V + r.normal(scale=0.01, size=V.shape)
+    for (VV, TT) in [(V, T), mg.kuhn_cube(3)]:
+        d = TT.shape[1] - 1
+        B, w = O.element_geometry(VV, TT)
+        G = O.gradient_operator(B, TT, VV.shape[0])
+        A = r.normal(size=(d, d))
+        t = r.normal(size=d)
+        J = O.jacobians(G, VV @ A + t, d)
+        assert np.abs(J - A).max() < 1e-11
+        assert np.abs(G @ np.ones(VV.shape[0])).max() < 1e-11
+        e = VV[TT[:, 1:]] - VV[TT[:, [0]]]
+        if d == 2:
+            area = 0.5 * np.abs(e[:, 0, 0] * e[:, 1, 1] - e[:, 0, 1] * e[:, 1, 0])
+        else:
+            area = np.abs(np.einsum("mi,mi->m", e[:, 0], np.cross(e[:, 1], e[:, 2]))) / 6.0
+        assert np.allclose(w, area, rtol=1e-13)
+    # intrinsic gradient on a surface: a flat mesh tilted in 3D, mapped to its
+    # own in-plane coordinates, has rotation Jacobians; areas are 1/2|e1 x e2|
+    wk = mg.height_field_uv(grid=6)
+    R3 = np.linalg.qr(r.normal(size=(3, 3)))[0]
+    flat = np.concatenate([wk.V[:, :2], np.zeros((wk.n, 1))], 1)
+    B, w = O.element_geometry(flat @ R3.T, wk.T)
+    G = O.gradient_operator(B, wk.T, wk.n)
+    J = O.jacobians(G, wk.V[:, :2], 2)
+    assert np.abs(np.einsum("mji,mjk->mik", J, J) - np.eye(2)).max() < 1e-12
+    assert np.abs(np.linalg.det(J) - 1).max() < 1e-12
+    e = wk.V[wk.T[:, 1:]] - wk.V[wk.T[:, [0]]]
+    _, w3 = O.element_geometry(wk.V, wk.T)
+    assert np.allclose(w3, 0.5 * np.linalg.norm(np.cross(e[:, 0], e[:, 1]), axis=1), rtol=1e-13)
+
+
+def _cot(a, b, c):
+    u, v = b - a, c - a
+    return np.dot(u, v) / abs(u[0] * v[1] - u[1] * v[0])
+
+
+def test_pin8_global_matrix_is_scaled_cotangent_laplacian():
+    r = rng(8)
+    ring, tt, T = mg.hex_disk(4)
+    phi = 2 * np.pi * tt / np.maximum(6 * ring, 1)
+    V = np.stack([ring * np.cos(phi), ring * np.sin(phi)], 1) / 4.0 + r.normal(scale=0.02, size=(ring.size, 2))
+    rho = 10.0
+    B, w = O.element_geometry(V, T)
+    L = O.global_matrix(O.gradient_operator(B, T, V.shape[0]), rho * w, 2).toarray()
+    assert np.abs(L - L.T).max() < 1e-12
+    assert np.abs(L.sum(1)).max() < 1e-11
+    C = np.zeros_like(L)
+    for t in T:
+        for k in range(3):
+            i, j, o = t[k], t[(k + 1) % 3], t[(k + 2) % 3]
+            c = _cot(V[o], V[i], V[j])  # angle opposite edge (i, j)
+            C[i, j] += -0.5 * rho * c
+            C[j, i] += -0.5 * rho * c
+    off = ~np.eye(L.shape[0], dtype=bool)
+    assert np.abs(L[off] - C[off]).max() < 1e-11
+    # 3D: the stiffness matrix annihilates affine functions at interior vertices
+    V3, T3 = mg.kuhn_cube(4)
+    V3 = V3 + r.normal(scale=0.01, size=V3.shape)
+    B3, w3 = O.element_geometry(V3, T3)
+    L3 = O.global_matrix(O.gradient_operator(B3, T3, V3.shape[0]), rho * w3, 3)
+    interior = np.all((mg.kuhn_cube(4)[0] > 0) & (mg.kuhn_cube(4)[0] < 1), axis=1)
+    aff = V3 @ r.normal(size=(3, 3)) + 1.0
+    assert np.abs((L3 @ aff)[interior]).max() < 1e-10
+
+
+# ----------------------------------------------------------------------------
+# W-step, init and the iteration
+# ----------------------------------------------------------------------------
+
+def _random_state(s, r, scale=0.3):
+    d = s.d
+    U = O.rotation_step(np.eye(d) + scale * r.normal(size=(s.m, d, d)), np.tile(np.eye(d), (s.m, 1, 1)))
+    A = r.normal(size=(s.m, d, d)) * scale
+    P = np.eye(d) + 0.5 * (A + np.transpose(A, (0, 2, 1)))
+    P = np.einsum("mij,mkj->mik", P, P)  # SPD
+    Lam = scale * r.normal(size=(s.m, d, d))
+    return U, P, Lam
+
+
+def test_pin9_wstep_is_weighted_least_squares():
+    r = rng(9)
+    wk = mg.height_field_uv(grid=7)
+    s = O.OracleSolver(wk.V, wk.T, wk.energy, wk.rho, wk.pinned_idx, wk.pinned_pos)
+    s.init(wk.x0)
+    U, P, Lam = _random_state(s, r)
+    x = s.w_step(U, P, Lam)
+    # independent: dense weighted least squares over the free vertices
+    Y = U @ P - Lam
+    G = s.G.toarray()
+    sw = np.sqrt(np.repeat(s.mu, s.d))
+    free = s.free
+    Gf, Gc = G[:, free], G[:, s.pins]
+    rhs = (Y.reshape(-1, s.d) - Gc @ s.pin_pos) * sw[:, None]
+    xf = np.linalg.lstsq(Gf * sw[:, None], rhs, rcond=None)[0]
+    assert np.abs(x[free] - xf).max() < 1e-10
+    assert np.allclose(x[s.pins], s.pin_pos)
+    # normal equations residual
+    b = (s.G.T @ (s.mu[:, None, None] * Y).reshape(-1, s.d))[free] - s.L_FC @ s.pin_pos
+    res = s.L_FF @ x[free] - b
+    assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("energy", [O.SD, O.SG])
+def test_polar_init_rules(energy):
+    r = rng(10)
+    for d in (2, 3):
+        J = r.normal(size=(300, d, d))
+        U, P, flipped = O.polar_init(J, energy)
+        eps = O.init_epsilon(energy)
+        assert np.allclose(np.linalg.det(U), 1.0, atol=1e-12)
+        assert np.array_equal(flipped, np.linalg.det(J) <= 0)
+        ev = np.linalg.eigvalsh(P)
+        assert np.all(ev >= eps * (1 - 1e-12))
+        ok = ~flipped & (np.linalg.svd(J, compute_uv=False).min(axis=1) > eps)
+        assert np.abs(U[ok] @ P[ok] - J[ok]).max() < 1e-12
+        assert np.allclose(P[flipped], eps * np.eye(d), atol=1e-15)
+    assert math.isclose(O.init_epsilon(O.SG), 2.0 ** -13)
+    assert math.isclose(O.init_epsilon(O.SD), 2.0 ** -6.5)
+
+
+@pytest.mark.parametrize("energy", [O.SD, O.SG])
+def test_pin6_identity_fixed_point(energy):
+    for wk in (mg.flat_grid(6, energy=energy), mg.twisted_cube(3, twist_deg=0.0, lift=0.0, energy=energy)):
+        s = O.OracleSolver(wk.V, wk.T, energy, wk.rho, wk.pinned_idx, wk.pinned_pos)
+        s.init(wk.x0)
+        s.iterate(3)
+        d = s.d
+        assert np.abs(s.x - wk.V).max() < 1e-13
+        assert np.abs(s.U - np.eye(d)).max() < 1e-13
+        assert np.abs(s.P - np.eye(d)).max() < 1e-13
+        assert np.abs(s.Lam).max() < 1e-13
+        E = s.history.col("E_P")[-1] / s.w.sum()
+        # f_SD(I) = d (with the paper's 1/2), i.e. 4 per triangle and 6 per tet
+        # without it; f_SG(I) = d/2
+        if energy == O.SD:
+            assert abs(2 * E - 2 * d) < 1e-12 and abs(E - d) < 1e-12
+        else:
+            assert abs(E - d / 2) < 1e-12
+
+
+def _phi(s, x, U, P, Lam):
+    J = O.jacobians(s.G, x, s.d)
+    p = np.linalg.eigvalsh(P)
+    R = J - U @ P + Lam
+    return np.sum(s.w * O.energy_of_spd_eigs(p, s.energy)
+                  + 0.5 * s.mu * (np.sum(R * R, axis=(1, 2)) - np.sum(Lam * Lam, axis=(1, 2))))
+
+
+@pytest.mark.parametrize("energy", [O.SD, O.SG])
+@pytest.mark.parametrize("dims", [2, 3])
+def test_algorithm1_substeps_by_brute_force(energy, dims):
+    """One oracle iteration from a random state on a tiny mesh; each sub-step is
+    checked as the argmin Algorithm 1 says it is, by independent searches."""
+    r = rng(11)
+    wk = mg.height_field_uv(grid=3, energy=energy) if dims == 2 else \
+        mg.twisted_cube(1, energy=energy)
+    s = O.OracleSolver(wk.V, wk.T, energy, wk.rho, wk.pinned_idx, wk.pinned_pos)
+    s.init(wk.x0)
+    U0, P0, L0 = _random_state(s, r)
+    s.set_state(wk.x0, U0, P0, L0)
+    s.iterate(1)
+    x1, U1, P1, L1 = s.x, s.U, s.P, s.Lam
+    # W: minimiser of Phi(., U0, P0, L0) -- gradient wrt free coordinates vanishes
+    h = 1e-6
+    for v in s.free[:4]:
+        for k in range(s.d):
+            xp, xm = x1.copy(), x1.copy()
+            xp[v, k] += h
+            xm[v, k] -= h
+            g = (_phi(s, xp, U0, P0, L0) - _phi(s, xm, U0, P0, L0)) / (2 * h)
+            assert abs(g) < 1e-6 * max(1.0, s.mu.max())
+    J1 = O.jacobians(s.G, x1, s.d)
+    # U: minimiser of the per-element term over rotations (with P0, L0, h = 0)
+    for i in range(s.m):
+        target = J1[i] + L0[i]
+        f = lambda Rm: np.sum((target - Rm @ P0[i]) ** 2)
+        if s.d == 2:
+            best = min(f(np.array([[math.cos(t), -math.sin(t)], [math.sin(t), math.cos(t)]]))
+                       for t in np.linspace(0, 2 * np.pi, 20001))
+        else:
+            qs = r.normal(size=(20000, 4))
+            qs /= np.linalg.norm(qs, axis=1)[:, None]
+            best = min(f(_quat_rot(q)) for q in qs)
+        assert f(U1[i]) <= best + 1e-9
+    # P: minimiser of w f(P) + mu/2 |J1 - U1 P + L0|^2 (eq. optimizinginp)
+    for i in range(min(s.m, 3)):
+        S = 0.5 * (U1[i].T @ (J1[i] + L0[i]) + (J1[i] + L0[i]).T @ U1[i])
+        Pr = _direct_pstep(S, s.w[i], s.mu[i], energy)
+        assert np.linalg.norm(P1[i] - Pr) <= 1e-5 * np.linalg.norm(Pr)
+    # Lambda: eq. lambdaupdate
+    assert np.abs(L1 - (L0 + J1 - U1 @ P1)).max() < 1e-13
+
+
+def test_pin10_step_identities_and_flip_free_UP():
+    wk = mg.height_field_uv(grid=12)
+    s = O.OracleSolver(wk.V, wk.T, wk.energy, wk.rho, wk.pinned_idx, wk.pinned_pos)
+    s.init(wk.x0)
+    for _ in range(15):
+        L_old = s.Lam.copy()
+        x_old = s.x.copy()
+        s.iterate(1)
+        e_prim = s.history.col("e_prim")[-1]
+        assert abs(np.linalg.norm(s.Lam - L_old) - e_prim) <= 1e-12 * max(1.0, e_prim)
+        assert np.all(np.linalg.det(s.U @ s.P) > 0)
+        # e_dual of eq. primaldualerror and E_P = sum w f(P) from their definitions
+        dJ = O.jacobians(s.G, s.x - x_old, s.d)
+        e_dual = math.sqrt(np.sum(s.mu[:, None, None] ** 2 * dJ ** 2))
+        assert abs(s.history.col("e_dual")[-1] - e_dual) <= 1e-12 * e_dual
+        E_P = np.sum(s.w * O.energy_density(s.P, s.energy))
+        assert abs(s.history.col("E_P")[-1] - E_P) <= 1e-12 * E_P
+
+
+@pytest.mark.parametrize("energy", [O.SD, O.SG])
+def test_pin11_kkt(energy):
+    wk = mg.height_field_uv(grid=5, sigma=0.01, energy=energy)
+    s = O.OracleSolver(wk.V, wk.T, energy, wk.rho, wk.pinned_idx, wk.pinned_pos)
+    s.init(wk.x0)
+    for it in range(3000):
+        s.iterate(1)
+        if it < 5 or it % 500 == 0:
+            # first KKT line, symmetric part: exact after every P-step
+            p, Qs = np.linalg.eigh(s.P)
+            g = p - p ** -3 if energy == O.SD else p - 1 / p
+            gradf = np.einsum("mij,mj,mkj->mik", Qs, g, Qs)
+            UL = np.transpose(s.U, (0, 2, 1)) @ s.Lam
+            symUL = 0.5 * (UL + np.transpose(UL, (0, 2, 1)))
+            assert np.abs(s.w[:, None, None] * gradf - s.mu[:, None, None] * symUL).max() < 1e-12
+    UL = np.transpose(s.U, (0, 2, 1)) @ s.Lam
+    skew = 0.5 * (UL - np.transpose(UL, (0, 2, 1)))
+    assert np.abs(skew).max() < 1e-6
+    assert s.history.col("e_prim")[-1] < 1e-6
+    # second KKT line (eq. kkt): mu Lam P^T lies in the normal cone of SO(d) at U,
+    # i.e. U^T Lam P^T is symmetric.  Reading: the "argmin" restatement of that
+    # line is a stationarity condition; at many elements U is its maximiser.
+    ULP = np.transpose(s.U, (0, 2, 1)) @ s.Lam @ np.transpose(s.P, (0, 2, 1))
+    assert np.abs(ULP - np.transpose(ULP, (0, 2, 1))).max() < 1e-6
+    # third line: J = U P
+    J = O.jacobians(s.G, s.x, s.d)
+    assert np.abs(J - s.U @ s.P).max() < 1e-6
+
+
+def test_pin12_rotation_equivariance():
+    r = rng(12)
+    wk = mg.height_field_uv(grid=10)
+    a = 0.7
+    R = np.array([[math.cos(a), -math.sin(a)], [math.sin(a), math.cos(a)]])
+    s1 = O.OracleSolver(wk.V, wk.T, wk.energy, wk.rho, wk.pinned_idx, wk.pinned_pos)
+    s2 = O.OracleSolver(wk.V, wk.T, wk.energy, wk.rho, wk.pinned_idx, wk.pinned_pos @ R.T)
+    s1.init(wk.x0)
+    s2.init(wk.x0 @ R.T)
+    s1.iterate(20)
+    s2.iterate(20)
+    assert np.abs(s2.x - s1.x @ R.T).max() < 1e-10
+    assert np.abs(np.linalg.eigvalsh(s2.P) - np.linalg.eigvalsh(s1.P)).max() < 1e-10
+    h1, h2 = s1.history.array(), s2.history.array()
+    assert np.allclose(h1[:, :5], h2[:, :5], rtol=1e-9, atol=1e-12)
+    # moving the source rigidly leaves the map unchanged
+    R3 = np.linalg.qr(r.normal(size=(3, 3)))[0]
+    s3 = O.OracleSolver(wk.V @ R3.T + 0.3, wk.T, wk.energy, wk.rho, wk.pinned_idx, wk.pinned_pos)
+    s3.init(wk.x0)
+    s3.iterate(20)
+    assert np.abs(s3.x - s1.x).max() < 1e-10
+
+
+def test_pin13_residual_decrease_on_height_field():
+    wk = mg.height_field_uv()  # 32 x 32 grid, sigma 0.02, SD, rho 10
+    s = O.OracleSolver(wk.V, wk.T, wk.energy, wk.rho, wk.pinned_idx, wk.pinned_pos)
+    s.init(wk.x0)
+    s.iterate(200)
+    ep, ed = s.history.col("e_prim"), s.history.col("e_dual")
+    assert ep[-1] <= 0.1 * ep[0] and ed[-1] <= 0.1 * ed[0]
+    win_p = [ep[i:i + 10].min() for i in range(0, 200, 10)]
+    win_d = [ed[i:i + 10].min() for i in range(0, 200, 10)]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(win_p, win_p[1:]))
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(win_d, win_d[1:]))
+    assert s.history.col("flips")[-1] == 0
+    assert math.isfinite(s.history.col("E_map")[-1])

@@ -1,0 +1,200 @@
+"""Benchmark of the flip-free ADMM iteration on one MI355X.
+
+Default workload: the twisted tet cube, 64^3 cells x 6 Kuhn tets
+(1,572,864 tets, 274,625 vertices), symmetric Dirichlet, rho = 10, float32
+element steps and float64 factor / solve / sums.  One "step" is one full
+ADMM iteration (W-step right-hand side, both triangular solves, fused
+U/P/Lambda step, residual reduction) with all inputs resident in HBM.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "ADMM iters/s + local-step elems/s at 1.5M tets; fwd+bwd s/iter vs plain"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def local_step_bytes_per_element(d: int, prec: int, n: int, m: int, h_mode: int = 0) -> float:
+    """Unique HBM bytes of one fused local step per element (implemented layout):
+    reads T (d+1 int32), B (d^2), w, U, P (sym), Lambda (d^2); writes U, P,
+    Lambda, corner vectors ((d+1) d) and |grad f(P)|^2; plus the two float64
+    maps (W^k, W^{k-1}) read once per vertex."""
+    r = prec // 8
+    nU = 2 if d == 2 else 9
+    nP = 3 if d == 2 else 6
+    reads = 4 * (d + 1) + r * (d * d + 1 + nU + nP + d * d) + (r if h_mode else 0)
+    writes = r * (nU + nP + d * d + (d + 1) * d + 1)
+    maps = 2 * 8 * d * n / m
+    return reads + writes + maps
+
+
+def wrhs_bytes(d: int, prec: int, m: int, nF: int, n: int) -> float:
+    """W-step right-hand side: CSR row pointers and (d+1) m incidence entries,
+    the corner vectors once, the float64 result and the pinned-row copy."""
+    r = prec // 8
+    return 4 * (nF + 1) + 4 * (d + 1) * m + r * (d + 1) * d * m + 8 * d * nF + 8 * d * (n - nF)
+
+
+def cpu_baseline(w, state, n_sample: int, passes: int):
+    """The FP64 oracle's element steps (U, P, Lambda steps and diagnostics) on a
+    sample of the workload's elements at the GPU's current state."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+
+    rng = np.random.default_rng(0)
+    start = int(rng.integers(0, max(1, w.m - n_sample)))
+    sel = np.arange(start, min(w.m, start + n_sample))
+    T = w.T[sel]
+    verts, Tl = np.unique(T, return_inverse=True)
+    Tl = Tl.reshape(T.shape).astype(np.int32)
+    x = state["map"].cpu().numpy()[verts]
+    U = state["U"].cpu().numpy().astype(np.float64)[sel]
+    P = state["P"].cpu().numpy().astype(np.float64)[sel]
+    L = state["Lam"].cpu().numpy().astype(np.float64)[sel]
+    with threadpool_limits(limits=1):
+        sub = O.OracleSolver(w.V[verts], Tl, w.energy, w.rho, np.array([0]), x[:1])
+        times = []
+        for _ in range(passes):
+            sub.set_state(x, U, 0.5 * (P + np.transpose(P, (0, 2, 1))), L)
+            t0 = time.perf_counter()
+            sub.local_steps(x)
+            times.append(time.perf_counter() - t0)
+    t = min(times)
+    return {"value": len(sel) / t, "unit": "local-step elems/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(sel)} contiguous elements of the {w.m:,}-element workload at the GPU state "
+                      f"after the timed run; oracle element steps (U, P, Lambda, diagnostics), best of "
+                      f"{passes} passes, 1 thread; the oracle's sparse LU does not factor this L_FF "
+                      f"within the benchmark budget, so no oracle iteration rate",
+            "host_cpu": _cpu_name(), "host_nproc": os.cpu_count()}
+
+
+def _cpu_name():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cube", type=int, default=64, help="cells per side of the tet cube")
+    ap.add_argument("--precision", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=200000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2107_05200_amd import binding, meshgen
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    w = meshgen.twisted_cube(args.cube)
+    log(f"workload {w.name}: m={w.m} n={w.n} pins={len(w.pinned_idx)} ({time.perf_counter() - t0:.1f}s)")
+    t0 = time.perf_counter()
+    s = binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=args.precision)
+    setup_s = time.perf_counter() - t0
+    info = s.info()
+    log(f"setup {setup_s:.1f}s: factor nnz {info['factor_nnz']:.3e}, levels {info['n_levels']}, "
+        f"numeric {info['t_numeric']:.1f}s, device {info['device_bytes'] / 2**30:.2f} GiB")
+    stream = torch.cuda.current_stream()
+    s.init(w.x0)
+    s.iterate(args.warmup)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} done")
+
+    # timed region: K iterations with per-phase HIP events on the solver's stream
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ph = s.iterate_profiled(args.steps, stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    K = args.steps
+    ms_per_step = ph["total"] / K
+    log(f"timed {K} iterations: {ph['total']:.2f} ms events, {wall * 1e3:.2f} ms wall; phases {ph}")
+    hist = s.history()
+    log(f"last history record: {dict(zip(binding.HIST_NAMES, hist[-1].tolist()))}")
+
+    d, m, n, nF = w.d, w.m, w.n, info["n_free"]
+    solve_ms = (ph["solve_fwd"] + ph["solve_bwd"]) / K
+    local_ms = ph["local"] / K
+    solve_bytes = 2.0 * 8.0 * info["factor_nnz"]  # each factor entry read once per pass
+    lb = local_step_bytes_per_element(d, args.precision, n, m)
+    local_bytes = lb * m
+    solve_gbs = solve_bytes / (solve_ms * 1e-3) / 1e9
+    local_gbs = local_bytes / (local_ms * 1e-3) / 1e9
+    dominant = "solve" if solve_ms >= local_ms else "local"
+    roof_solve = {"bound": "hbm", "achieved": round(solve_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(solve_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "kernel": "k_solve_fwd + k_solve_bwd (one W-step solve, all levels)",
+                  "algorithmic_bytes": solve_bytes, "ms_per_launch": round(solve_ms, 5)}
+    roof_local = {"bound": "hbm", "achieved": round(local_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(local_gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_local",
+                  "algorithmic_bytes": local_bytes, "bytes_per_element": round(lb, 2),
+                  "ms_per_launch": round(local_ms, 5)}
+    out = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms_per_step, 2),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 element steps + f64 solve" if args.precision == 32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"twisted tet cube {args.cube}^3 x 6 Kuhn tets ({m:,} tets, {n:,} vertices), "
+                               f"symmetric Dirichlet, rho=10, bottom fixed, top 45deg twist + 0.3 lift",
+                   "elements": m, "vertices": n, "free_vertices": nF, "precision": args.precision},
+        "local_step_elems_per_s": round(m / (local_ms * 1e-3), 1),
+        "fwd_bwd_s_per_iter_vs_plain": None,
+        "phase_ms_per_iter": {k: round(v / K, 5) for k, v in ph.items() if k != "total"},
+        "setup_s": round(setup_s, 2),
+        "factor": {"nnz": info["factor_nnz"], "levels": info["n_levels"], "numeric_s": round(info["t_numeric"], 2)},
+        "roofline": roof_solve if dominant == "solve" else roof_local,
+        "roofline_local_step": roof_local,
+        "roofline_solve": roof_solve,
+        "wrhs_gbs": round(wrhs_bytes(d, args.precision, m, nF, n) / (ph["wrhs"] / K * 1e-3) / 1e9, 1),
+    }
+    if not args.no_cpu_baseline:
+        st = s.get_state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(w, st, args.cpu_sample, 3)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.0f} elems/s ({time.perf_counter() - t0:.1f}s)")
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * ffd.h -- C ABI of the MI355X (gfx950) flip-free ADMM solver.
+ *
+ * The solver runs the three-block ADMM of Stein, Li & Solomon, "A Splitting
+ * Scheme for Flip-Free Distortion Energies" (Algorithm 1 with the fixed
+ * penalties of the loop of Algorithm 2): the W-step (eq. solvinginw, a solve
+ * with the fixed matrix L = G^T M G factored once), the U-step (Procrustes,
+ * eqs. proximalfunctionu / optimizationinudecoupled), the P-step (eqs.
+ * optimizinginp / rootfindinginp with the per-eigenvalue roots of the
+ * supplement) and the Lambda-step (eq. lambdaupdate), with the primal and
+ * dual residuals of eq. primaldualerror.
+ *
+ * Conventions
+ *  - Status: every call returns ffd_status (0 = OK, < 0 = error) and leaves
+ *    the handle unchanged on error; ffd_last_error() gives a thread-local
+ *    message.  Numerical trouble (flipped Jacobians, non-finite values) is not
+ *    an error: it is recorded in the history.
+ *  - Ownership: host inputs are copied by ffd_create; the caller keeps them.
+ *    Device buffers passed to the other calls belong to the caller and must
+ *    hold the documented number of elements.  The handle owns its own device
+ *    and host memory and frees it in ffd_destroy.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Every call after ffd_create only enqueues work on that stream
+ *    (no host synchronisation) except ffd_get_history, which synchronises.
+ *  - Layouts: the map (W of the paper) is n x d row-major float64 in the
+ *    caller's vertex order.  Element arrays (U, P, Lambda, W_el = U P) are
+ *    m x d x d row-major in the caller's element order, float32 when the
+ *    handle was created with precision 32 and float64 with precision 64.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef FFD_H
+#define FFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ffd_ctx* ffd_handle;
+
+typedef enum {
+  FFD_SYMMETRIC_DIRICHLET = 0, /* f(X) = 1/2 (|X|^2 + |X^-1|^2)   (Table 1)                    */
+  FFD_SYMMETRIC_GRADIENT = 1   /* f(X) = 1/2 |X|^2 - log det X    (eq. symmetricgradient...)   */
+} ffd_energy;
+
+typedef enum {
+  FFD_OK = 0,
+  FFD_ERR_INVALID_ARG = -1,        /* bad sizes, indices, options or NULL pointers              */
+  FFD_ERR_DEGENERATE_ELEMENT = -2, /* an element with zero (or non-finite) area / volume         */
+  FFD_ERR_SINGULAR_SYSTEM = -3,    /* a connected component without a pin: L_FF is singular     */
+  FFD_ERR_NOT_FINITE = -4,         /* NaN / Inf in V or pinned positions                          */
+  FFD_ERR_DEVICE = -5,             /* a HIP runtime call failed                                   */
+  FFD_ERR_OUT_OF_MEMORY = -6,
+  FFD_ERR_STATE = -7               /* call out of order (e.g. ffd_iterate before ffd_init)        */
+} ffd_status;
+
+/* One mesh (Section "Preliminaries"): n source vertices V (n x dim_in,
+ * row-major float64) and m elements T (m x (simplex_dim+1), int32).  The
+ * output dimension equals simplex_dim (square Jacobians, Def. "Piecewise
+ * constant Jacobian"); dim_in = 3 with simplex_dim = 2 is a UV map of a surface
+ * (intrinsic gradient, supplement "Computing the Jacobian Map"). */
+typedef struct {
+  int32_t simplex_dim; /* d: 2 = triangles, 3 = tetrahedra          */
+  int32_t dim_in;      /* d or (3 when d == 2)                       */
+  int64_t n_vertices;
+  int64_t n_elements;
+  const double* V;     /* host, n_vertices x dim_in                  */
+  const int32_t* T;    /* host, n_elements x (d + 1)                 */
+} ffd_mesh;
+
+/* Options.  mu_i = rho * w_i with w_i the element area / volume (the
+ * penalties of eq. augmentedlagrangian, fixed: no rescaling).  Pins are the
+ * linear constraints A W = b of eq. solvinginw restricted to fixed vertices;
+ * with no pins and auto_pin = 1 vertex 0 is fixed at its initial position (the
+ * W-step text fixes the first vertex when there are no constraints). */
+typedef struct {
+  int32_t energy;            /* ffd_energy                                                   */
+  double rho;                /* > 0                                                           */
+  int32_t h_mode;            /* proximal weight of eq. proximalfunctionu: 0 = off (h = 0)     */
+  int32_t precision;         /* 32 or 64: arithmetic of the element steps; the factor, the
+                                W-step right-hand side, the map and all sums are float64      */
+  int64_t n_pinned;
+  const int32_t* pinned_idx; /* host, n_pinned distinct vertex indices                        */
+  const double* pinned_pos;  /* host, n_pinned x d row-major, may be NULL (then taken from the
+                                initial map in ffd_init)                                      */
+  int32_t auto_pin;          /* 1: pin vertex 0 when n_pinned == 0                             */
+  int32_t leaf_size;         /* nested-dissection leaf size, 0 = automatic                    */
+} ffd_options;
+
+/* Set-up statistics (filled by ffd_create / ffd_get_info). */
+typedef struct {
+  int64_t n_free, n_pinned;
+  int64_t factor_nnz;       /* nonzeros of the Cholesky factor of L_FF                         */
+  int64_t panel_entries;    /* float64 entries of one copy of the solve panels                 */
+  int32_t n_nodes, n_levels;
+  double t_geometry, t_order, t_symbolic, t_numeric, t_upload; /* seconds                       */
+  double factor_flops;
+  int64_t device_bytes;     /* device memory owned by the handle                              */
+} ffd_info;
+
+/* History record per iteration (FFD_HIST_FIELDS float64):
+ *  0 e_prim   sqrt(sum_i |J_i - U_i P_i|^2)                  (eq. primaldualerror)
+ *  1 e_dual   sqrt(sum_i mu_i^2 |J_i^k - J_i^{k-1}|^2)       (eq. primaldualerror)
+ *  2 E_P      sum_i w_i f(P_i)
+ *  3 E_map    sum_i w_i f(J_i), +inf if any det J_i <= 0     (eq. genericdeformationenergy)
+ *  4 Phi      augmented Lagrangian at (W^k, U^k, P^k, Lambda^k) (eq. augmentedlagrangian)
+ *  5 flips    number of elements with det J_i <= 0
+ *  6 nonfinite number of elements whose Lambda is not finite
+ *  7 norm_GW  |G W^k|                                         (eq. primaldualthresholds)
+ *  8 norm_P   |P^k|                                           (eq. primaldualthresholds)
+ *  9 norm_GtLam  |G^T Lambda^k| -- not computed on the device: NaN
+ * J_i = (G W^k)_i.  Iterations are numbered from 1 after ffd_init. */
+#define FFD_HIST_FIELDS 10
+
+/* Host set-up: geometry (B_i, w_i), L = G^T M G, pin elimination, nested
+ * dissection, FP64 multifrontal Cholesky of L_FF, then upload to the current
+ * HIP device.  Synchronous.  On success *out is a new handle. */
+ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* out);
+
+/* Host-only analysis: runs the set-up of ffd_create (geometry, global
+ * matrix, ordering, factorisation) without touching a device and returns its
+ * statistics; *selfcheck_residual (may be NULL) receives |L_FF x - b| / |b| of
+ * a host solve with the factor panels for a fixed right-hand side.  For
+ * checking inputs and the factorisation on machines without a GPU. */
+ffd_status ffd_analyze(const ffd_mesh* mesh, const ffd_options* opt, ffd_info* info,
+                       double* selfcheck_residual);
+
+/* Statistics of a created handle. */
+ffd_status ffd_get_info(ffd_handle h, ffd_info* info);
+
+/* Initialisation (Section "Implementation", "Initializing U, P, Lambda"):
+ * U0, P0 from the SVD of J0 = G map0 with the flip and epsilon rules;
+ * Lambda0 = 0.  map0 (device, n x d float64) is W^0 as given: the pins act
+ * through the W-step of the first iteration; when no pinned positions were
+ * given they are taken from map0. */
+ffd_status ffd_init(ffd_handle h, const double* map0_dev, void* stream);
+
+/* Replace the pinned positions (device, n_pinned x d float64, in the order of
+ * options.pinned_idx).  Takes effect at the next W-step. */
+ffd_status ffd_set_pins(ffd_handle h, const double* pinned_pos_dev, void* stream);
+
+/* Run n_iter iterations of Algorithm 1, appending n_iter history records. */
+ffd_status ffd_iterate(ffd_handle h, int32_t n_iter, void* stream);
+
+/* As ffd_iterate, with a HIP event recorded on `stream` between the phases
+ * of every iteration; on return (after synchronising the stream)
+ * phase_ms_host[0..4] hold the summed milliseconds of the phases
+ *   0 W-step right-hand side, 1 forward triangular solve, 2 backward
+ *   triangular solve, 3 fused U/P/Lambda step, 4 history reduction,
+ * and phase_ms_host[5] the total from the first to the last event. */
+#define FFD_PROFILE_FIELDS 6
+ffd_status ffd_iterate_profiled(ffd_handle h, int32_t n_iter, void* stream, double* phase_ms_host);
+
+/* Copy the state out; any pointer may be NULL.  map: n x d float64; Wel, U,
+ * P, Lambda: m x d x d in the handle's precision. */
+ffd_status ffd_get_state(ffd_handle h, double* map_dev, void* Wel_dev, void* U_dev, void* P_dev,
+                         void* Lambda_dev, void* stream);
+
+/* Overwrite the state (resume or teacher forcing): map is W^k (n x d
+ * float64, used as W^{k-1} by the dual residual of the next iteration); U,
+ * P (symmetric; the mean of P and P^T is used), Lambda: m x d x d in the
+ * handle's precision.  The next W-step right-hand side is rebuilt from them.
+ * The iteration counter becomes k; history records before k are undefined. */
+ffd_status ffd_set_state(ffd_handle h, const double* map_dev, const void* U_dev, const void* P_dev,
+                         const void* Lambda_dev, int64_t k, void* stream);
+
+/* Copy history records [first, first + count) to host memory
+ * (count x FFD_HIST_FIELDS float64).  Synchronises the handle's last stream. */
+ffd_status ffd_get_history(ffd_handle h, int64_t first, int64_t count, double* out_host);
+
+/* Number of completed iterations since ffd_init. */
+ffd_status ffd_get_iteration(ffd_handle h, int64_t* k);
+
+/* Solve L_FF x = b for the free vertices with the handle's factor (the
+ * back-substitution of the W-step).  b, x: device, n_free x d float64 in the
+ * handle's internal free-vertex order (see ffd_get_vertex_order). */
+ffd_status ffd_solve(ffd_handle h, const double* b_dev, double* x_dev, void* stream);
+
+/* Internal vertex order: order_host[j] = caller index of internal vertex j
+ * (free vertices first, then the pins in options order). */
+ffd_status ffd_get_vertex_order(ffd_handle h, int32_t* order_host);
+
+void ffd_destroy(ffd_handle h);
+
+const char* ffd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFD_H */

@@ -324,22 +324,25 @@ class OracleSolver:
         else:
             self.auto_pinned = False
         self.pins = pins
-        self.pin_pos = None if self.auto_pinned else np.asarray(pinned_pos, dtype=np.float64).reshape(-1, self.d)
+        self.pin_pos = None if (self.auto_pinned or pinned_pos is None) else \
+            np.asarray(pinned_pos, dtype=np.float64).reshape(-1, self.d)
         self.free = np.setdiff1d(np.arange(self.n), pins)
         self.L_FF = self.L[self.free][:, self.free].tocsc()
         self.L_FC = self.L[self.free][:, pins].tocsr()
-        self._lu = spla.splu(self.L_FF)
+        self._lu = None  # factorised at the first W-step (once: mu is fixed)
         self.k = 0
         self.history = History()
 
     # -- state ---------------------------------------------------------------
     def init(self, x0):
-        """Polar initialisation of U, P; Lambda0 = 0 (Algorithm 2, first lines)."""
+        """Polar initialisation of U, P from the caller's W^0 as given; Lambda0 = 0
+        (Algorithm 2, first lines).  Reading: the constraints are imposed by the
+        W-step (eq. solvinginw), not on W^0 -- a deformation starts from the
+        identity map with the handles still at rest (caption of the 3D
+        deformation figure).  Without given pin positions they are taken from W^0."""
         x0 = np.asarray(x0, dtype=np.float64).reshape(self.n, self.d).copy()
-        if self.auto_pinned:
+        if self.pin_pos is None:
             self.pin_pos = x0[self.pins].copy()
-        else:
-            x0[self.pins] = self.pin_pos
         self.x = x0
         self.x_prev = x0.copy()
         J0 = jacobians(self.G, self.x, self.d)
@@ -377,6 +380,8 @@ class OracleSolver:
         r = self.mu[:, None, None] * (U @ P - Lam)
         rhs = np.asarray(self.G.T @ r.reshape(self.m * self.d, self.d))
         b = rhs[self.free] - self.L_FC @ self.pin_pos
+        if self._lu is None:
+            self._lu = spla.splu(self.L_FF)
         x = np.empty((self.n, self.d))
         x[self.pins] = self.pin_pos
         x[self.free] = self._lu.solve(b)
@@ -386,23 +391,28 @@ class OracleSolver:
         """Algorithm 1: W, then U (with P^{k-1}, Lam^{k-1}), then P (with U^k,
         Lam^{k-1}), then Lam; diagnostics of eq. primaldualerror afterwards."""
         for _ in range(n_iter):
-            x_new = self.w_step(self.U, self.P, self.Lam)
-            J = jacobians(self.G, x_new, self.d)
-            J_prev = jacobians(self.G, self.x, self.d)
-            A = J + self.Lam
-            Q = A @ self.P + (self.h / self.mu)[:, None, None] * self.U
-            U = rotation_step(Q, self.U)
-            At = np.transpose(U, (0, 2, 1)) @ A
-            S = 0.5 * (At + np.transpose(At, (0, 2, 1)))
-            P, p = p_step(S, self.w, self.mu, self.energy)
-            UP = U @ P
-            Lam = self.Lam + J - UP
-            self.x_prev, self.x = self.x, x_new
-            self.U, self.P, self.Lam = U, P, Lam
-            self.k += 1
-            self.history.rows.append(self._diagnostics(J, J_prev, UP, p))
-            if self.h_mode == 1:
-                self.h = self._prox_h(self.P)
+            self.local_steps(self.w_step(self.U, self.P, self.Lam))
+        return self
+
+    def local_steps(self, x_new):
+        """The element-wise part of one iteration given W^k = x_new: U-step,
+        P-step, Lambda-step and the diagnostics; advances the state."""
+        J = jacobians(self.G, x_new, self.d)
+        J_prev = jacobians(self.G, self.x, self.d)
+        A = J + self.Lam
+        Q = A @ self.P + (self.h / self.mu)[:, None, None] * self.U
+        U = rotation_step(Q, self.U)
+        At = np.transpose(U, (0, 2, 1)) @ A
+        S = 0.5 * (At + np.transpose(At, (0, 2, 1)))
+        P, p = p_step(S, self.w, self.mu, self.energy)
+        UP = U @ P
+        Lam = self.Lam + J - UP
+        self.x_prev, self.x = self.x, x_new
+        self.U, self.P, self.Lam = U, P, Lam
+        self.k += 1
+        self.history.rows.append(self._diagnostics(J, J_prev, UP, p))
+        if self.h_mode == 1:
+            self.h = self._prox_h(self.P)
         return self
 
     def _diagnostics(self, J, J_prev, UP, p):

@@ -1,0 +1,257 @@
+"""Thin ctypes binding of libffd.so (include/ffd.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch provides device memory (tensors passed by ``data_ptr()``) and streams
+(``torch.cuda.current_stream().cuda_stream``).  A missing library is an error,
+never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libffd.so")
+HIST_FIELDS = 10
+HIST_NAMES = ("e_prim", "e_dual", "E_P", "E_map", "Phi", "flips", "nonfinite",
+              "norm_GW", "norm_P", "norm_GtLam")
+
+STATUS = {0: "FFD_OK", -1: "FFD_ERR_INVALID_ARG", -2: "FFD_ERR_DEGENERATE_ELEMENT",
+          -3: "FFD_ERR_SINGULAR_SYSTEM", -4: "FFD_ERR_NOT_FINITE", -5: "FFD_ERR_DEVICE",
+          -6: "FFD_ERR_OUT_OF_MEMORY", -7: "FFD_ERR_STATE"}
+
+
+class FFDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Mesh(C.Structure):
+    _fields_ = [("simplex_dim", C.c_int32), ("dim_in", C.c_int32), ("n_vertices", C.c_int64),
+                ("n_elements", C.c_int64), ("V", C.POINTER(C.c_double)), ("T", C.POINTER(C.c_int32))]
+
+
+class Options(C.Structure):
+    _fields_ = [("energy", C.c_int32), ("rho", C.c_double), ("h_mode", C.c_int32),
+                ("precision", C.c_int32), ("n_pinned", C.c_int64),
+                ("pinned_idx", C.POINTER(C.c_int32)), ("pinned_pos", C.POINTER(C.c_double)),
+                ("auto_pin", C.c_int32), ("leaf_size", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_free", C.c_int64), ("n_pinned", C.c_int64), ("factor_nnz", C.c_int64),
+                ("panel_entries", C.c_int64), ("n_nodes", C.c_int32), ("n_levels", C.c_int32),
+                ("t_geometry", C.c_double), ("t_order", C.c_double), ("t_symbolic", C.c_double),
+                ("t_numeric", C.c_double), ("t_upload", C.c_double), ("factor_flops", C.c_double),
+                ("device_bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+_PROTOS = {
+    "ffd_create": (C.c_int, [C.POINTER(Mesh), C.POINTER(Options), C.POINTER(C.c_void_p)]),
+    "ffd_analyze": (C.c_int, [C.POINTER(Mesh), C.POINTER(Options), C.POINTER(Info), C.POINTER(C.c_double)]),
+    "ffd_get_info": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
+    "ffd_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ffd_set_pins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ffd_iterate": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "ffd_iterate_profiled": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
+    "ffd_get_state": (C.c_int, [C.c_void_p] + [C.c_void_p] * 5 + [C.c_void_p]),
+    "ffd_set_state": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4 + [C.c_int64, C.c_void_p]),
+    "ffd_get_history": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
+    "ffd_get_iteration": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "ffd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ffd_get_vertex_order": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "ffd_destroy": (None, [C.c_void_p]),
+    "ffd_last_error": (C.c_char_p, []),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libffd.so (built in-tree by paper_2107_05200_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2107_05200_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in _PROTOS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise FFDError(st, load().ffd_last_error().decode())
+
+
+def _dptr(t) -> int:
+    return 0 if t is None else t.data_ptr()
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _mesh_struct(V: np.ndarray, T: np.ndarray):
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.int32)
+    ms = Mesh(T.shape[1] - 1, V.shape[1], V.shape[0], T.shape[0],
+              V.ctypes.data_as(C.POINTER(C.c_double)), T.ctypes.data_as(C.POINTER(C.c_int32)))
+    return ms, (V, T)
+
+
+def _options_struct(d, energy, rho, pinned_idx, pinned_pos, precision, h_mode, auto_pin, leaf_size):
+    pi = np.ascontiguousarray(pinned_idx if pinned_idx is not None else np.zeros(0), dtype=np.int32)
+    pp = None if pinned_pos is None else np.ascontiguousarray(pinned_pos, dtype=np.float64).reshape(-1, d)
+    op = Options(int(energy), float(rho), int(h_mode), int(precision), pi.shape[0],
+                 pi.ctypes.data_as(C.POINTER(C.c_int32)) if pi.size else None,
+                 pp.ctypes.data_as(C.POINTER(C.c_double)) if pp is not None and pp.size else None,
+                 int(auto_pin), int(leaf_size))
+    return op, (pi, pp)
+
+
+def analyze(V, T, energy=0, rho=10.0, pinned_idx=None, pinned_pos=None, auto_pin=1, leaf_size=0):
+    """Host-only set-up statistics and factor self-check (no device)."""
+    lib = load()
+    ms, keep1 = _mesh_struct(V, T)
+    op, keep2 = _options_struct(T.shape[1] - 1, energy, rho, pinned_idx, pinned_pos, 32, 0, auto_pin, leaf_size)
+    info = Info()
+    res = C.c_double(-1.0)
+    _check(lib.ffd_analyze(C.byref(ms), C.byref(op), C.byref(info), C.byref(res)))
+    out = info.as_dict()
+    out["selfcheck_residual"] = res.value
+    return out
+
+
+class Solver:
+    """One mesh on the current HIP device.
+
+    precision 32: element steps in float32 (factor, right-hand side, map and
+    sums in float64); precision 64: everything float64."""
+
+    def __init__(self, V, T, energy=0, rho=10.0, pinned_idx=None, pinned_pos=None, precision=32,
+                 h_mode=0, auto_pin=1, leaf_size=0):
+        import torch
+        self.lib = load()
+        V = np.asarray(V)
+        T = np.asarray(T)
+        self.d = T.shape[1] - 1
+        self.n = V.shape[0]
+        self.m = T.shape[0]
+        self.precision = precision
+        self.dtype = torch.float32 if precision == 32 else torch.float64
+        self.n_pinned = 0 if pinned_idx is None else len(pinned_idx)
+        ms, keep1 = _mesh_struct(V, T)
+        op, keep2 = _options_struct(self.d, energy, rho, pinned_idx, pinned_pos, precision, h_mode,
+                                    auto_pin, leaf_size)
+        h = C.c_void_p()
+        _check(self.lib.ffd_create(C.byref(ms), C.byref(op), C.byref(h)))
+        self.h = h
+        if self.n_pinned == 0 and auto_pin:
+            self.n_pinned = 1
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.ffd_destroy(h)
+            self.h = None
+
+    def close(self):
+        self.__del__()
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(self.lib.ffd_get_info(self.h, C.byref(inf)))
+        return inf.as_dict()
+
+    def _dev(self, a, dtype):
+        import torch
+        if isinstance(a, torch.Tensor):
+            return a.to(device=self.device, dtype=dtype).contiguous()
+        return torch.as_tensor(np.asarray(a), dtype=dtype, device=self.device).contiguous()
+
+    def init(self, map0, stream=None):
+        import torch
+        x0 = self._dev(map0, torch.float64).reshape(self.n, self.d)
+        _check(self.lib.ffd_init(self.h, C.c_void_p(x0.data_ptr()), _stream(stream)))
+        self._keep = x0
+        return self
+
+    def set_pins(self, pos, stream=None):
+        import torch
+        p = self._dev(pos, torch.float64).reshape(-1, self.d)
+        _check(self.lib.ffd_set_pins(self.h, C.c_void_p(p.data_ptr()), _stream(stream)))
+        self._keep_pins = p
+
+    def iterate(self, n_iter: int = 1, stream=None):
+        _check(self.lib.ffd_iterate(self.h, int(n_iter), _stream(stream)))
+        return self
+
+    def iterate_profiled(self, n_iter: int, stream=None) -> dict:
+        """Iterate with per-phase HIP events; returns summed milliseconds per phase."""
+        out = (C.c_double * 6)()
+        _check(self.lib.ffd_iterate_profiled(self.h, int(n_iter), _stream(stream), out))
+        names = ("wrhs", "solve_fwd", "solve_bwd", "local", "finalize", "total")
+        return {k: out[i] for i, k in enumerate(names)}
+
+    def get_state(self, stream=None):
+        """Returns dict of device tensors: map (n, d) float64; U, P, Lam, Wel (m, d, d)."""
+        import torch
+        d, m = self.d, self.m
+        out = {"map": torch.empty((self.n, d), dtype=torch.float64, device=self.device)}
+        for k in ("Wel", "U", "P", "Lam"):
+            out[k] = torch.empty((m, d, d), dtype=self.dtype, device=self.device)
+        _check(self.lib.ffd_get_state(self.h, C.c_void_p(out["map"].data_ptr()),
+                                      C.c_void_p(out["Wel"].data_ptr()), C.c_void_p(out["U"].data_ptr()),
+                                      C.c_void_p(out["P"].data_ptr()), C.c_void_p(out["Lam"].data_ptr()),
+                                      _stream(stream)))
+        return out
+
+    def set_state(self, x, U, P, Lam, k: int = 0, stream=None):
+        import torch
+        xs = self._dev(x, torch.float64).reshape(self.n, self.d)
+        Us = self._dev(U, self.dtype).reshape(self.m, self.d, self.d)
+        Ps = self._dev(P, self.dtype).reshape(self.m, self.d, self.d)
+        Ls = self._dev(Lam, self.dtype).reshape(self.m, self.d, self.d)
+        _check(self.lib.ffd_set_state(self.h, C.c_void_p(xs.data_ptr()), C.c_void_p(Us.data_ptr()),
+                                      C.c_void_p(Ps.data_ptr()), C.c_void_p(Ls.data_ptr()), int(k),
+                                      _stream(stream)))
+        self._keep_state = (xs, Us, Ps, Ls)
+
+    def iteration(self) -> int:
+        k = C.c_int64()
+        _check(self.lib.ffd_get_iteration(self.h, C.byref(k)))
+        return k.value
+
+    def history(self, first: int = 0, count: int | None = None) -> np.ndarray:
+        if count is None:
+            count = self.iteration() - first
+        out = np.empty((count, HIST_FIELDS), dtype=np.float64)
+        _check(self.lib.ffd_get_history(self.h, first, count, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def vertex_order(self) -> np.ndarray:
+        o = np.empty(self.n, dtype=np.int32)
+        _check(self.lib.ffd_get_vertex_order(self.h, o.ctypes.data_as(C.POINTER(C.c_int32))))
+        return o
+
+    def solve(self, b, stream=None):
+        """x = L_FF^{-1} b in the internal free-vertex order (n_free, d) float64."""
+        import torch
+        bb = self._dev(b, torch.float64).reshape(-1, self.d)
+        x = torch.zeros((self.n, self.d), dtype=torch.float64, device=self.device)
+        _check(self.lib.ffd_solve(self.h, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()), _stream(stream)))
+        return x[: bb.shape[0]]

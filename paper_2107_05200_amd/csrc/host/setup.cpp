@@ -1,0 +1,721 @@
+// Host setup: geometry, global matrix, ordering and the FP64 factor.
+//
+// Paper passages: the Jacobian / gradient operator G (Def. "Piecewise
+// constant Jacobian" and supplement "Computing the Jacobian Map"); the W-step
+// system L W = G^T r with L = G^T M G, M = diag(mu) (eq. solvinginw), fixed
+// vertices eliminated, and a factorisation computed once and reused by a
+// back-substitution every iteration (Section "Efficient Evaluation &
+// Parallelization").
+//
+// The factorisation is multifrontal over a geometric nested-dissection tree.
+// For each tree node s (columns C, row structure R below) it stores
+//   forward panel  [Linv; -M]   with Linv = L_CC^{-1}, M = L_RC * Linv,
+//   backward panel [Linv^T | -M^T],
+// so both triangular solves become dense matrix-vector products per node with
+// no sequential dependency inside a node (the partitioned-inverse form of a
+// supernodal triangular solve).
+#include "setup.hpp"
+
+#include <omp.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <numeric>
+
+#include "dense.hpp"
+
+namespace ffd {
+
+namespace {
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ----------------------------------------------------------------------------
+// nested dissection on source coordinates
+// ----------------------------------------------------------------------------
+
+struct NDBuilder {
+  const std::vector<int64_t>& adj_ptr;
+  const std::vector<int32_t>& adj;
+  const double* V;
+  int din;
+  int leaf;
+  const std::vector<uint8_t>& is_pinned;
+  std::vector<int32_t> stamp;
+  std::vector<int8_t> side;
+  int32_t cur = 0;
+  // tree (old vertex ids per node)
+  std::vector<std::vector<int32_t>> cols;
+  std::vector<std::vector<int32_t>> kids;
+
+  NDBuilder(const std::vector<int64_t>& ap, const std::vector<int32_t>& a, const double* V_, int din_,
+            int leaf_, const std::vector<uint8_t>& pinned, int64_t n)
+      : adj_ptr(ap), adj(a), V(V_), din(din_), leaf(leaf_), is_pinned(pinned), stamp(n, -1), side(n, 0) {}
+
+  int new_node(std::vector<int32_t>&& c, std::vector<int32_t>&& k) {
+    cols.push_back(std::move(c));
+    kids.push_back(std::move(k));
+    return static_cast<int>(cols.size()) - 1;
+  }
+
+  // returns the roots of the forest built for S
+  std::vector<int32_t> run(std::vector<int32_t>& S) {
+    if (S.empty()) return {};
+    if (static_cast<int>(S.size()) <= leaf) return {new_node(std::move(S), {})};
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int32_t v : S)
+      for (int a = 0; a < din; ++a) {
+        lo[a] = std::min(lo[a], V[static_cast<int64_t>(v) * din + a]);
+        hi[a] = std::max(hi[a], V[static_cast<int64_t>(v) * din + a]);
+      }
+    int ax = 0;
+    for (int a = 1; a < din; ++a)
+      if (hi[a] - lo[a] > hi[ax] - lo[ax]) ax = a;
+    std::vector<double> co(S.size());
+    for (size_t i = 0; i < S.size(); ++i) co[i] = V[static_cast<int64_t>(S[i]) * din + ax];
+    std::vector<double> tmp = co;
+    const size_t k = S.size() / 2;
+    std::nth_element(tmp.begin(), tmp.begin() + k, tmp.end());
+    const double med = tmp[k];
+    const int32_t st = cur++;
+    size_t nleft = 0;
+    for (size_t i = 0; i < S.size(); ++i) nleft += co[i] < med;
+    bool le = false;
+    if (nleft == 0) {  // ties at the minimum: split at <= med instead
+      le = true;
+      for (size_t i = 0; i < S.size(); ++i) nleft += co[i] <= med;
+    }
+    for (size_t i = 0; i < S.size(); ++i) {
+      stamp[S[i]] = st;
+      const bool isleft = le ? co[i] <= med : co[i] < med;
+      side[S[i]] = isleft ? 1 : 2;
+    }
+    if (nleft == 0 || nleft == S.size()) {  // all coordinates equal: split by position
+      for (size_t i = 0; i < S.size(); ++i) side[S[i]] = i < k ? 1 : 2;
+    }
+    std::vector<int32_t> sepL, sepR;
+    for (int32_t v : S) {
+      const int8_t sv = side[v];
+      bool touches = false;
+      for (int64_t e = adj_ptr[v]; e < adj_ptr[v + 1]; ++e) {
+        const int32_t u = adj[e];
+        if (stamp[u] == st && side[u] != sv) {
+          touches = true;
+          break;
+        }
+      }
+      if (touches) (sv == 1 ? sepL : sepR).push_back(v);
+    }
+    const bool useL = sepL.size() <= sepR.size();
+    std::vector<int32_t>& sep = useL ? sepL : sepR;
+    for (int32_t v : sep) side[v] = 3;
+    std::vector<int32_t> L, R;
+    L.reserve(S.size() / 2 + 1);
+    R.reserve(S.size() / 2 + 1);
+    for (int32_t v : S) {
+      if (side[v] == 1) L.push_back(v);
+      else if (side[v] == 2) R.push_back(v);
+    }
+    std::vector<int32_t>().swap(S);
+    std::vector<int32_t> sep_copy = sep;
+    std::vector<int32_t> roots = run(L);
+    std::vector<int32_t> rr = run(R);
+    roots.insert(roots.end(), rr.begin(), rr.end());
+    if (sep_copy.empty()) return roots;
+    return {new_node(std::move(sep_copy), std::move(roots))};
+  }
+};
+
+}  // namespace
+
+int element_geometry(int d, int din, int64_t m, const double* V, int64_t n, const int32_t* T,
+                     std::vector<double>& B, std::vector<double>& w, std::string& err) {
+  B.assign(static_cast<size_t>(m) * d * d, 0.0);
+  w.assign(static_cast<size_t>(m), 0.0);
+  int bad = 0;
+  int64_t bad_elem = -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t* t = T + e * (d + 1);
+    double E[3][3];  // E[j][k]: edge j, source coordinate k
+    for (int j = 0; j < d; ++j)
+      for (int k = 0; k < din; ++k)
+        E[j][k] = V[static_cast<int64_t>(t[j + 1]) * din + k] - V[static_cast<int64_t>(t[0]) * din + k];
+    double Dm[3][3] = {};  // columns are the edges in the element frame
+    if (din == d) {
+      for (int a = 0; a < d; ++a)
+        for (int j = 0; j < d; ++j) Dm[a][j] = E[j][a];
+    } else {  // triangle in 3D: intrinsic frame e1 = edge 1 direction, e2 = n x e1
+      const double l1 = std::sqrt(E[0][0] * E[0][0] + E[0][1] * E[0][1] + E[0][2] * E[0][2]);
+      double e1[3] = {E[0][0] / l1, E[0][1] / l1, E[0][2] / l1};
+      double nn[3] = {E[0][1] * E[1][2] - E[0][2] * E[1][1], E[0][2] * E[1][0] - E[0][0] * E[1][2],
+                      E[0][0] * E[1][1] - E[0][1] * E[1][0]};
+      const double ln = std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+      for (double& x : nn) x /= ln;
+      double e2[3] = {nn[1] * e1[2] - nn[2] * e1[1], nn[2] * e1[0] - nn[0] * e1[2], nn[0] * e1[1] - nn[1] * e1[0]};
+      for (int j = 0; j < 2; ++j) {
+        Dm[0][j] = E[j][0] * e1[0] + E[j][1] * e1[1] + E[j][2] * e1[2];
+        Dm[1][j] = E[j][0] * e2[0] + E[j][1] * e2[1] + E[j][2] * e2[2];
+      }
+    }
+    double det, inv[3][3];
+    if (d == 2) {
+      det = Dm[0][0] * Dm[1][1] - Dm[0][1] * Dm[1][0];
+      inv[0][0] = Dm[1][1] / det;
+      inv[0][1] = -Dm[0][1] / det;
+      inv[1][0] = -Dm[1][0] / det;
+      inv[1][1] = Dm[0][0] / det;
+    } else {
+      const double c00 = Dm[1][1] * Dm[2][2] - Dm[1][2] * Dm[2][1];
+      const double c01 = Dm[1][2] * Dm[2][0] - Dm[1][0] * Dm[2][2];
+      const double c02 = Dm[1][0] * Dm[2][1] - Dm[1][1] * Dm[2][0];
+      det = Dm[0][0] * c00 + Dm[0][1] * c01 + Dm[0][2] * c02;
+      inv[0][0] = c00 / det;
+      inv[1][0] = c01 / det;
+      inv[2][0] = c02 / det;
+      inv[0][1] = (Dm[0][2] * Dm[2][1] - Dm[0][1] * Dm[2][2]) / det;
+      inv[1][1] = (Dm[0][0] * Dm[2][2] - Dm[0][2] * Dm[2][0]) / det;
+      inv[2][1] = (Dm[0][1] * Dm[2][0] - Dm[0][0] * Dm[2][1]) / det;
+      inv[0][2] = (Dm[0][1] * Dm[1][2] - Dm[0][2] * Dm[1][1]) / det;
+      inv[1][2] = (Dm[0][2] * Dm[1][0] - Dm[0][0] * Dm[1][2]) / det;
+      inv[2][2] = (Dm[0][0] * Dm[1][1] - Dm[0][1] * Dm[1][0]) / det;
+    }
+    const double area = std::fabs(det) / (d == 2 ? 2.0 : 6.0);
+    bool ok = std::isfinite(area) && area > 1e-300;
+    for (int a = 0; a < d; ++a)
+      for (int j = 0; j < d; ++j) {
+        const double v = inv[j][a];  // B = Dm^{-T}
+        B[static_cast<size_t>(e) * d * d + a * d + j] = v;
+        ok = ok && std::isfinite(v);
+      }
+    w[e] = area;
+    if (!ok) {
+#pragma omp critical
+      {
+        bad = 1;
+        if (bad_elem < 0 || e < bad_elem) bad_elem = e;
+      }
+    }
+  }
+  (void)n;
+  if (bad) {
+    err = "degenerate element " + std::to_string(bad_elem) + " (zero or non-finite area/volume)";
+    return ERR_DEGENERATE_ELEMENT;
+  }
+  return OK;
+}
+
+int build_setup(const SetupInput& in, Setup& S, std::string& err) {
+  const int d = in.d, din = in.din;
+  const int64_t n = in.n, m = in.m;
+  const int nc = d + 1;
+  if (!(d == 2 || d == 3) || !(din == d || (d == 2 && din == 3))) {
+    err = "unsupported (simplex_dim, dim_in)";
+    return ERR_INVALID_ARG;
+  }
+  if (n <= 0 || m <= 0 || !in.V || !in.T || n > INT32_MAX / 2 || m > INT32_MAX / 4) {
+    err = "empty or oversized mesh";
+    return ERR_INVALID_ARG;
+  }
+  if (!(in.rho > 0) || !std::isfinite(in.rho)) {
+    err = "rho must be positive and finite";
+    return ERR_INVALID_ARG;
+  }
+  for (int64_t i = 0; i < n * din; ++i)
+    if (!std::isfinite(in.V[i])) {
+      err = "non-finite source vertex";
+      return ERR_NOT_FINITE;
+    }
+  for (int64_t i = 0; i < m * nc; ++i)
+    if (in.T[i] < 0 || in.T[i] >= n) {
+      err = "element index out of range";
+      return ERR_INVALID_ARG;
+    }
+  for (int64_t e = 0; e < m; ++e)
+    for (int a = 0; a < nc; ++a)
+      for (int b = a + 1; b < nc; ++b)
+        if (in.T[e * nc + a] == in.T[e * nc + b]) {
+          err = "element " + std::to_string(e) + " repeats a vertex";
+          return ERR_DEGENERATE_ELEMENT;
+        }
+  std::vector<uint8_t> pinned(n, 0);
+  for (int64_t i = 0; i < in.n_pinned; ++i) {
+    const int32_t v = in.pinned_idx[i];
+    if (v < 0 || v >= n || pinned[v]) {
+      err = "pinned index out of range or repeated";
+      return ERR_INVALID_ARG;
+    }
+    pinned[v] = 1;
+  }
+  S.d = d;
+  S.din = din;
+  S.n = n;
+  S.m = m;
+  S.rho = in.rho;
+  S.nC = in.n_pinned;
+  S.nF = n - in.n_pinned;
+
+  double t0 = now();
+  std::vector<double> B0, w0;
+  int st = element_geometry(d, din, m, in.V, n, in.T, B0, w0, err);
+  if (st) return st;
+
+  // vertex -> element incidence
+  std::vector<int64_t> inc_ptr(n + 1, 0);
+  for (int64_t i = 0; i < m * nc; ++i) inc_ptr[in.T[i] + 1]++;
+  for (int64_t v = 0; v < n; ++v) inc_ptr[v + 1] += inc_ptr[v];
+  std::vector<int32_t> inc(m * nc);
+  {
+    std::vector<int64_t> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+    for (int64_t e = 0; e < m; ++e)
+      for (int c = 0; c < nc; ++c) inc[fill[in.T[e * nc + c]]++] = static_cast<int32_t>(e * nc + c);
+  }
+  // L = sum_e mu_e C_e^T C_e in the input numbering (rows include self)
+  std::vector<int64_t> Lptr(n + 1, 0);
+  std::vector<std::vector<int32_t>> rowpat(n);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t v = 0; v < n; ++v) {
+    std::vector<int32_t>& p = rowpat[v];
+    for (int64_t k = inc_ptr[v]; k < inc_ptr[v + 1]; ++k) {
+      const int64_t e = inc[k] / nc;
+      for (int c = 0; c < nc; ++c) p.push_back(in.T[e * nc + c]);
+    }
+    std::sort(p.begin(), p.end());
+    p.erase(std::unique(p.begin(), p.end()), p.end());
+  }
+  for (int64_t v = 0; v < n; ++v) Lptr[v + 1] = Lptr[v] + static_cast<int64_t>(rowpat[v].size());
+  std::vector<int32_t> Lcol(Lptr[n]);
+  std::vector<double> Lval(Lptr[n], 0.0);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t v = 0; v < n; ++v) {
+    std::copy(rowpat[v].begin(), rowpat[v].end(), Lcol.begin() + Lptr[v]);
+    std::vector<int32_t>().swap(rowpat[v]);
+    const int32_t* cb = Lcol.data() + Lptr[v];
+    const int64_t len = Lptr[v + 1] - Lptr[v];
+    for (int64_t k = inc_ptr[v]; k < inc_ptr[v + 1]; ++k) {
+      const int64_t e = inc[k] / nc;
+      const int cv = inc[k] % nc;
+      const double mu = in.rho * w0[e];
+      const double* Be = B0.data() + e * d * d;
+      // C[a][0] = -sum_j B[a][j], C[a][j+1] = B[a][j]
+      double C[3][4];
+      for (int a = 0; a < d; ++a) {
+        double s = 0;
+        for (int j = 0; j < d; ++j) {
+          C[a][j + 1] = Be[a * d + j];
+          s += Be[a * d + j];
+        }
+        C[a][0] = -s;
+      }
+      for (int c2 = 0; c2 < nc; ++c2) {
+        double val = 0;
+        for (int a = 0; a < d; ++a) val += C[a][cv] * C[a][c2];
+        const int32_t u = in.T[e * nc + c2];
+        const int64_t pos = std::lower_bound(cb, cb + len, u) - cb;
+        Lval[Lptr[v] + pos] += mu * val;
+      }
+    }
+  }
+  std::vector<std::vector<int32_t>>().swap(rowpat);
+  S.t_geometry = now() - t0;
+
+  // every connected component needs a pinned vertex (G maps constants to 0)
+  {
+    std::vector<int32_t> comp(n, -1), stack;
+    for (int64_t s0 = 0; s0 < n; ++s0) {
+      if (comp[s0] >= 0) continue;
+      bool has_pin = false;
+      stack.push_back(static_cast<int32_t>(s0));
+      comp[s0] = 1;
+      while (!stack.empty()) {
+        const int32_t v = stack.back();
+        stack.pop_back();
+        has_pin |= pinned[v] != 0;
+        for (int64_t k = Lptr[v]; k < Lptr[v + 1]; ++k)
+          if (comp[Lcol[k]] < 0) {
+            comp[Lcol[k]] = 1;
+            stack.push_back(Lcol[k]);
+          }
+      }
+      if (!has_pin) {
+        err = "a connected component (containing vertex " + std::to_string(s0) +
+              ") has no pinned vertex: the W-step system is singular";
+        return ERR_SINGULAR_SYSTEM;
+      }
+    }
+  }
+
+  // ---- ordering -------------------------------------------------------------
+  t0 = now();
+  std::vector<int64_t> aptr(n + 1, 0);
+  std::vector<int32_t> adjv;
+  adjv.reserve(Lptr[n]);
+  for (int64_t v = 0; v < n; ++v) {
+    for (int64_t k = Lptr[v]; k < Lptr[v + 1]; ++k)
+      if (Lcol[k] != v && !pinned[Lcol[k]]) adjv.push_back(Lcol[k]);
+    aptr[v + 1] = static_cast<int64_t>(adjv.size());
+  }
+  int leaf = in.leaf_size > 0 ? in.leaf_size : (d == 3 ? 48 : 64);
+  NDBuilder nd(aptr, adjv, in.V, din, leaf, pinned, n);
+  std::vector<int32_t> freev;
+  freev.reserve(S.nF);
+  for (int64_t v = 0; v < n; ++v)
+    if (!pinned[v]) freev.push_back(static_cast<int32_t>(v));
+  std::vector<int32_t> roots = nd.run(freev);
+  const int nn = static_cast<int>(nd.cols.size());
+  // postorder numbering
+  S.vnew2old.assign(n, -1);
+  S.vold2new.assign(n, -1);
+  std::vector<int32_t> order;  // nodes in postorder
+  order.reserve(nn);
+  {
+    std::vector<std::pair<int32_t, int>> stk;
+    for (auto it = roots.rbegin(); it != roots.rend(); ++it) stk.push_back({*it, 0});
+    while (!stk.empty()) {
+      auto& top = stk.back();
+      const int32_t s = top.first;
+      if (top.second < static_cast<int>(nd.kids[s].size())) {
+        const int32_t ch = nd.kids[s][top.second++];
+        stk.push_back({ch, 0});
+      } else {
+        order.push_back(s);
+        stk.pop_back();
+      }
+    }
+  }
+  std::vector<int32_t> node_id(nn);  // builder node -> postorder index
+  for (int i = 0; i < nn; ++i) node_id[order[i]] = i;
+  S.nodes.assign(nn, SolveNode());
+  S.children.assign(nn, {});
+  {
+    int32_t next = 0;
+    for (int i = 0; i < nn; ++i) {
+      const int32_t s = order[i];
+      SolveNode& N = S.nodes[i];
+      N.first = next;
+      N.c = static_cast<int32_t>(nd.cols[s].size());
+      for (int32_t v : nd.cols[s]) {
+        S.vnew2old[next] = v;
+        S.vold2new[v] = next;
+        ++next;
+      }
+      for (int32_t ch : nd.kids[s]) S.children[i].push_back(node_id[ch]);
+    }
+    for (int64_t i = 0; i < in.n_pinned; ++i) {
+      S.vnew2old[S.nF + i] = in.pinned_idx[i];
+      S.vold2new[in.pinned_idx[i]] = static_cast<int32_t>(S.nF + i);
+    }
+  }
+  S.t_order = now() - t0;
+
+  // ---- symbolic ---------------------------------------------------------------
+  t0 = now();
+  std::vector<std::vector<int32_t>> strct(nn);
+  for (int i = 0; i < nn; ++i) {
+    SolveNode& N = S.nodes[i];
+    const int32_t last = N.first + N.c - 1;
+    std::vector<int32_t> acc;
+    for (int32_t j = 0; j < N.c; ++j) {
+      const int32_t v = S.vnew2old[N.first + j];
+      for (int64_t k = aptr[v]; k < aptr[v + 1]; ++k) {
+        const int32_t u = S.vold2new[adjv[k]];
+        if (u > last) acc.push_back(u);
+      }
+    }
+    for (int32_t ch : S.children[i])
+      for (int32_t u : strct[ch])
+        if (u > last) acc.push_back(u);
+    std::sort(acc.begin(), acc.end());
+    acc.erase(std::unique(acc.begin(), acc.end()), acc.end());
+    strct[i] = std::move(acc);
+    N.r = static_cast<int32_t>(strct[i].size());
+    int lvl = 0;
+    for (int32_t ch : S.children[i]) lvl = std::max(lvl, S.nodes[ch].level + 1);
+    N.level = lvl;
+  }
+  int64_t pf = 0, uo = 0, so = 0, po = 0;
+  double flops = 0;
+  int64_t fnnz = 0;
+  int nlev = 0;
+  for (int i = 0; i < nn; ++i) {
+    SolveNode& N = S.nodes[i];
+    N.pf = pf;
+    N.pb = pf;
+    N.uoff = uo;
+    N.soff = so;
+    N.poff = po;
+    const double c = N.c, r = N.r;
+    pf += static_cast<int64_t>(N.c + N.r) * N.c;
+    uo += N.r;
+    so += N.r;
+    po += N.c + N.r + 1;
+    flops += c * c * c / 3 + r * c * c + r * r * c + c * c * c / 3 + r * c * c;
+    fnnz += static_cast<int64_t>(N.c) * (N.c + 1) / 2 + static_cast<int64_t>(N.c) * N.r;
+    nlev = std::max(nlev, N.level + 1);
+  }
+  S.panel_entries = pf;
+  S.ubuf_rows = uo;
+  S.factor_flops = flops;
+  S.factor_nnz = fnnz;
+  S.struct_idx.resize(so);
+  for (int i = 0; i < nn; ++i)
+    std::copy(strct[i].begin(), strct[i].end(), S.struct_idx.begin() + S.nodes[i].soff);
+  // forward pull lists: front position p of node s receives update rows of its
+  // children (child update row i -> global index strct[child][i])
+  S.pull_ptr.assign(po, 0);
+  {
+    std::vector<int64_t> cnt(po, 0);
+    for (int i = 0; i < nn; ++i) {
+      const SolveNode& N = S.nodes[i];
+      const int32_t* sb = strct[i].data();
+      for (int32_t ch : S.children[i])
+        for (int32_t g : strct[ch]) {
+          const int64_t p = g < N.first + N.c ? g - N.first
+                                              : N.c + (std::lower_bound(sb, sb + N.r, g) - sb);
+          cnt[N.poff + p]++;
+        }
+    }
+    // pull_ptr[N.poff + p] = start of position p's list; per node c + r + 1 entries
+    int64_t tot = 0;
+    for (int i = 0; i < nn; ++i) {
+      const SolveNode& N = S.nodes[i];
+      for (int64_t p = 0; p <= N.c + N.r; ++p) {
+        const int64_t k = N.poff + p;
+        const int64_t cc = p < N.c + N.r ? cnt[k] : 0;
+        S.pull_ptr[k] = static_cast<int32_t>(tot);
+        tot += cc;
+      }
+    }
+    if (tot > INT32_MAX) {
+      err = "pull list too large";
+      return ERR_OUT_OF_MEMORY;
+    }
+    S.pull_idx.assign(tot, 0);
+    std::vector<int64_t> fill(po);
+    for (int64_t k = 0; k < po; ++k) fill[k] = S.pull_ptr[k];
+    for (int i = 0; i < nn; ++i) {
+      const SolveNode& N = S.nodes[i];
+      const int32_t* sb = strct[i].data();
+      for (int32_t ch : S.children[i]) {
+        const SolveNode& C = S.nodes[ch];
+        for (int32_t q = 0; q < C.r; ++q) {
+          const int32_t g = strct[ch][q];
+          const int64_t p = g < N.first + N.c ? g - N.first
+                                              : N.c + (std::lower_bound(sb, sb + N.r, g) - sb);
+          S.pull_idx[fill[N.poff + p]++] = static_cast<int32_t>(C.uoff + q);
+        }
+      }
+    }
+  }
+  S.level_nodes.assign(nlev, {});
+  for (int i = 0; i < nn; ++i) S.level_nodes[S.nodes[i].level].push_back(i);
+  S.t_symbolic = now() - t0;
+
+  // ---- numeric multifrontal factorisation --------------------------------------
+  t0 = now();
+  S.panel_f.assign(pf, 0.0);
+  S.panel_b.assign(pf, 0.0);
+  std::vector<std::vector<double>> upd(nn);
+  std::vector<int> fail(nn, 0);
+  auto factor_node = [&](int i) {
+    for (int32_t ch : S.children[i])
+      if (fail[ch]) {
+        fail[i] = 1;
+        return;
+      }
+    const SolveNode& N = S.nodes[i];
+    const int c = N.c, r = N.r, nf = c + r;
+    const int32_t* sb = strct[i].data();
+    auto pos = [&](int32_t g) -> int64_t {
+      return g < N.first + c ? g - N.first : c + (std::lower_bound(sb, sb + r, g) - sb);
+    };
+    std::vector<double> F(static_cast<size_t>(nf) * nf, 0.0);
+    for (int j = 0; j < c; ++j) {
+      const int32_t gv = N.first + j;
+      const int32_t v = S.vnew2old[gv];
+      for (int64_t k = Lptr[v]; k < Lptr[v + 1]; ++k) {
+        const int32_t gu = S.vold2new[Lcol[k]];
+        if (gu >= S.nF || gu < gv) continue;
+        F[pos(gu) + static_cast<int64_t>(j) * nf] += Lval[k];
+      }
+    }
+    for (int32_t ch : S.children[i]) {
+      const int rc = S.nodes[ch].r;
+      std::vector<int64_t> rel(rc);
+      for (int q = 0; q < rc; ++q) rel[q] = pos(strct[ch][q]);
+      const std::vector<double>& U = upd[ch];
+      for (int jj = 0; jj < rc; ++jj)
+        for (int ii = jj; ii < rc; ++ii)
+          F[rel[ii] + rel[jj] * nf] += U[ii + static_cast<size_t>(jj) * rc];
+      std::vector<double>().swap(upd[ch]);
+    }
+    if (dense::potrf(c, F.data(), nf)) {
+      fail[i] = 1;
+      return;
+    }
+    if (r > 0) dense::trsm_rlt(r, c, F.data(), nf, F.data() + c, nf);
+    std::vector<double> Linv(static_cast<size_t>(c) * c);
+    dense::trtri(c, F.data(), nf, Linv.data(), c);
+    std::vector<double> M(static_cast<size_t>(r) * c);
+    if (r > 0) {
+      dense::syrk_sub(r, c, F.data() + c, nf, F.data() + c + static_cast<int64_t>(c) * nf, nf);
+      upd[i].assign(static_cast<size_t>(r) * r, 0.0);
+      for (int jj = 0; jj < r; ++jj)
+        for (int ii = jj; ii < r; ++ii)
+          upd[i][ii + static_cast<size_t>(jj) * r] = F[(c + ii) + static_cast<int64_t>(c + jj) * nf];
+      dense::gemm_nn(r, c, c, 1.0, F.data() + c, nf, Linv.data(), c, 0.0, M.data(), r);
+    }
+    double* Pf = S.panel_f.data() + N.pf;
+    double* Pb = S.panel_b.data() + N.pb;
+    for (int j = 0; j < c; ++j) {
+      for (int p = 0; p < c; ++p) Pf[p + static_cast<int64_t>(j) * nf] = p >= j ? Linv[p + static_cast<size_t>(j) * c] : 0.0;
+      for (int q = 0; q < r; ++q) Pf[c + q + static_cast<int64_t>(j) * nf] = -M[q + static_cast<size_t>(j) * r];
+    }
+    for (int p = 0; p < nf; ++p)
+      for (int j = 0; j < c; ++j)
+        Pb[j + static_cast<int64_t>(p) * c] =
+            p < c ? (p >= j ? Linv[p + static_cast<size_t>(j) * c] : 0.0) : -M[(p - c) + static_cast<size_t>(j) * r];
+  };
+  // subtree sizes (work) to split into parallel subtrees and a sequential top
+  std::vector<double> work(nn, 0);
+  for (int i = 0; i < nn; ++i) {
+    const double c = S.nodes[i].c, r = S.nodes[i].r;
+    work[i] = c * c * c + 2 * r * c * c + r * r * c;
+    for (int32_t ch : S.children[i]) work[i] += work[ch];
+  }
+  double total = 0;
+  std::vector<int32_t> parent(nn, -1);
+  for (int i = 0; i < nn; ++i)
+    for (int32_t ch : S.children[i]) parent[ch] = i;
+  for (int i = 0; i < nn; ++i)
+    if (parent[i] < 0) total += work[i];
+  const int nth = std::max(1, omp_get_max_threads());
+  const double cut = total / (8.0 * nth);
+  // a node is in the parallel part if its subtree work is below the cut; the
+  // parallel subtrees are the maximal such subtrees
+  std::vector<uint8_t> small(nn, 0);
+  for (int i = 0; i < nn; ++i) small[i] = work[i] <= cut;
+  std::vector<int32_t> subroots, top;
+  for (int i = 0; i < nn; ++i) {
+    if (small[i] && (parent[i] < 0 || !small[parent[i]])) subroots.push_back(i);
+    if (!small[i]) top.push_back(i);
+  }
+  std::sort(subroots.begin(), subroots.end(), [&](int a, int b) { return work[a] > work[b]; });
+#pragma omp parallel for schedule(dynamic, 1)
+  for (size_t k = 0; k < subroots.size(); ++k) {
+    const int root = subroots[k];
+    // postorder of a subtree is a contiguous index range ending at its root
+    int lo = root;
+    while (!S.children[lo].empty()) lo = *std::min_element(S.children[lo].begin(), S.children[lo].end());
+    for (int i = lo; i <= root; ++i) factor_node(i);
+  }
+  for (int32_t i : top) factor_node(i);  // postorder: children before parents
+  for (int i = 0; i < nn; ++i)
+    if (fail[i]) {
+      err = "the W-step matrix is not positive definite (check the pins)";
+      return ERR_SINGULAR_SYSTEM;
+    }
+  S.t_numeric = now() - t0;
+
+  // ---- element order and device tables -------------------------------------------
+  std::vector<int32_t> key(m);
+  for (int64_t e = 0; e < m; ++e) {
+    int32_t k = INT32_MAX;
+    for (int c = 0; c < nc; ++c) k = std::min(k, S.vold2new[in.T[e * nc + c]]);
+    key[e] = k;
+  }
+  S.enew2old.resize(m);
+  std::iota(S.enew2old.begin(), S.enew2old.end(), 0);
+  std::stable_sort(S.enew2old.begin(), S.enew2old.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  S.B.resize(static_cast<size_t>(m) * d * d);
+  S.w.resize(m);
+  S.T.resize(static_cast<size_t>(m) * nc);
+  for (int64_t e = 0; e < m; ++e) {
+    const int64_t o = S.enew2old[e];
+    std::memcpy(S.B.data() + e * d * d, B0.data() + o * d * d, sizeof(double) * d * d);
+    S.w[e] = w0[o];
+    for (int c = 0; c < nc; ++c) S.T[e * nc + c] = S.vold2new[in.T[o * nc + c]];
+  }
+  S.dt_ptr.assign(S.nF + 1, 0);
+  for (int64_t e = 0; e < m; ++e)
+    for (int c = 0; c < nc; ++c)
+      if (S.T[e * nc + c] < S.nF) S.dt_ptr[S.T[e * nc + c] + 1]++;
+  for (int64_t v = 0; v < S.nF; ++v) S.dt_ptr[v + 1] += S.dt_ptr[v];
+  S.dt_idx.assign(S.dt_ptr[S.nF], 0);
+  {
+    std::vector<int32_t> fill(S.dt_ptr.begin(), S.dt_ptr.end() - 1);
+    for (int64_t e = 0; e < m; ++e)
+      for (int c = 0; c < nc; ++c) {
+        const int32_t v = S.T[e * nc + c];
+        if (v < S.nF) S.dt_idx[fill[v]++] = static_cast<int32_t>(e * nc + c);
+      }
+  }
+  if (in.selfcheck && S.nF > 0) {
+    // solve L_FF x = b with the panels exactly as the device does (forward
+    // pass bottom-up with extend-add pulls, backward pass top-down) and report
+    // the relative residual
+    const int64_t nF = S.nF;
+    std::vector<double> b(nF), y(nF), x(nF), ub(S.ubuf_rows, 0.0);
+    for (int64_t j = 0; j < nF; ++j) b[j] = std::sin(0.37 * j + 1.0) + 0.5 * std::cos(1.3 * j);
+    for (int i = 0; i < nn; ++i) {
+      const SolveNode& N = S.nodes[i];
+      const int c = N.c, r = N.r, nf = c + r;
+      std::vector<double> v(nf, 0.0);
+      for (int p = 0; p < nf; ++p) {
+        double a = p < c ? b[N.first + p] : 0.0;
+        for (int32_t k = S.pull_ptr[N.poff + p]; k < S.pull_ptr[N.poff + p + 1]; ++k) a += ub[S.pull_idx[k]];
+        v[p] = a;
+      }
+      const double* Pf = S.panel_f.data() + N.pf;
+      for (int row = 0; row < nf; ++row) {
+        double a = row < c ? 0.0 : v[row];
+        for (int j = 0; j < c; ++j) a += Pf[row + static_cast<int64_t>(j) * nf] * v[j];
+        if (row < c) y[N.first + row] = a;
+        else ub[N.uoff + row - c] = a;
+      }
+    }
+    for (int i = nn - 1; i >= 0; --i) {
+      const SolveNode& N = S.nodes[i];
+      const int c = N.c, r = N.r, nf = c + r;
+      const double* Pb = S.panel_b.data() + N.pb;
+      for (int j = 0; j < c; ++j) {
+        double a = 0.0;
+        for (int p = 0; p < nf; ++p)
+          a += Pb[j + static_cast<int64_t>(p) * c] * (p < c ? y[N.first + p] : x[S.struct_idx[N.soff + p - c]]);
+        x[N.first + j] = a;
+      }
+    }
+    double rn = 0, bn = 0;
+    for (int64_t j = 0; j < nF; ++j) {
+      const int32_t v = S.vnew2old[j];
+      double a = -b[j];
+      for (int64_t k = Lptr[v]; k < Lptr[v + 1]; ++k) {
+        const int32_t u = S.vold2new[Lcol[k]];
+        if (u < nF) a += Lval[k] * x[u];
+      }
+      rn += a * a;
+      bn += b[j] * b[j];
+    }
+    S.selfcheck_residual = std::sqrt(rn / bn);
+  }
+  S.pin_ptr.assign(S.nF + 1, 0);
+  for (int64_t j = 0; j < S.nF; ++j) {
+    const int32_t v = S.vnew2old[j];
+    for (int64_t k = Lptr[v]; k < Lptr[v + 1]; ++k) {
+      const int32_t u = S.vold2new[Lcol[k]];
+      if (u >= S.nF) {
+        S.pin_col.push_back(static_cast<int32_t>(u - S.nF));
+        S.pin_val.push_back(Lval[k]);
+      }
+    }
+    S.pin_ptr[j + 1] = static_cast<int32_t>(S.pin_col.size());
+  }
+  return OK;
+}
+
+}  // namespace ffd

@@ -1,0 +1,86 @@
+// One-time host setup of the flip-free ADMM solver: element geometry, the
+// global matrix L = G^T M G, pin elimination, nested-dissection ordering and
+// the FP64 multifrontal Cholesky factor of L_FF stored as per-node panels
+// with explicitly inverted diagonal blocks, plus the tables the GPU kernels
+// read (CSR of D^T, level schedule, extend-add pull lists).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ffd {
+
+enum Status : int {
+  OK = 0,
+  ERR_INVALID_ARG = -1,
+  ERR_DEGENERATE_ELEMENT = -2,
+  ERR_SINGULAR_SYSTEM = -3,
+  ERR_NOT_FINITE = -4,
+  ERR_DEVICE = -5,
+  ERR_OUT_OF_MEMORY = -6,
+  ERR_STATE = -7,
+};
+
+struct SetupInput {
+  int d = 2;        // simplex dimension (2 triangles, 3 tets); output dimension == d
+  int din = 2;      // source dimension (d, or 3 with d == 2)
+  int64_t n = 0, m = 0;
+  const double* V = nullptr;     // n x din row-major
+  const int32_t* T = nullptr;    // m x (d+1) row-major
+  double rho = 10.0;             // mu_i = rho * w_i
+  int64_t n_pinned = 0;
+  const int32_t* pinned_idx = nullptr;
+  int leaf_size = 0;             // 0: automatic
+  bool selfcheck = false;        // solve with the panels on the host and record the residual
+};
+
+// One node of the nested-dissection tree; its columns are the contiguous free
+// indices [first, first + c); its row structure below the diagonal block is
+// the sorted list struct_idx[soff .. soff + r).
+struct SolveNode {
+  int32_t first = 0, c = 0, r = 0, level = 0;
+  int64_t pf = 0;    // forward panel [Linv; -M], (c + r) x c column-major, ld = c + r
+  int64_t pb = 0;    // backward panel [Linv^T | -M^T], c x (c + r) column-major, ld = c
+  int64_t uoff = 0;  // first row of this node's update vector in the update buffer
+  int64_t soff = 0;  // offset into struct_idx
+  int64_t poff = 0;  // offset into pull_ptr (c + r + 1 entries)
+};
+
+struct Setup {
+  int d = 0, din = 0;
+  int64_t n = 0, m = 0, nF = 0, nC = 0;
+  double rho = 0;
+  // elements in the device order, vertices in the device numbering
+  std::vector<double> B;        // m x d x d, B_i = Dm_i^{-T}
+  std::vector<double> w;        // m
+  std::vector<int32_t> T;       // m x (d+1)
+  std::vector<int32_t> vnew2old, vold2new, enew2old;
+  // D^T over free rows: entries e*(d+1)+corner, rows ordered by element index
+  std::vector<int32_t> dt_ptr, dt_idx;
+  // L_FC over free rows: pinned slot and value
+  std::vector<int32_t> pin_ptr, pin_col;
+  std::vector<double> pin_val;
+  // factor of L_FF
+  std::vector<SolveNode> nodes;
+  std::vector<std::vector<int32_t>> children;
+  std::vector<double> panel_f, panel_b;
+  std::vector<int32_t> struct_idx;
+  std::vector<int32_t> pull_ptr, pull_idx;
+  std::vector<std::vector<int32_t>> level_nodes;
+  int64_t ubuf_rows = 0;
+  // statistics
+  double t_geometry = 0, t_order = 0, t_symbolic = 0, t_numeric = 0;
+  double factor_flops = 0;
+  int64_t factor_nnz = 0;     // nonzeros of the Cholesky factor (dense node blocks)
+  int64_t panel_entries = 0;  // entries of one panel copy (forward or backward)
+  double selfcheck_residual = -1;  // |L_FF x - b| / |b| of a host solve with the panels
+};
+
+// Returns a Status; on error fills err.
+int build_setup(const SetupInput& in, Setup& out, std::string& err);
+
+// Element geometry only (B_i = Dm_i^{-T}, w_i) in the input element order.
+int element_geometry(int d, int din, int64_t m, const double* V, int64_t n, const int32_t* T,
+                     std::vector<double>& B, std::vector<double>& w, std::string& err);
+
+}  // namespace ffd

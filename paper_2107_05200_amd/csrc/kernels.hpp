@@ -1,0 +1,814 @@
+// gfx950 kernels of the flip-free ADMM iteration.  One wave64 lane per
+// element for the local steps; one lane per vertex row for the W-step
+// right-hand side; per-level dense panel products for the triangular solves.
+// No atomics: every reduction has a fixed order, so runs are bitwise
+// reproducible.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_math.hpp"
+
+namespace ffd {
+
+constexpr int kBlock = 256;      // threads per block for element / vertex kernels
+constexpr int kNumPartials = 9;  // per-block partial sums of the local step
+
+struct NodeDev {
+  int32_t first, c, r, pad;
+  int64_t pf, pb, uoff, soff, poff;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+template <int NF>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NF], double* __restrict out) {
+  __shared__ double red[kBlock / 64][NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    double x = v[f];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    v[f] = x;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) red[wave][f] = v[f];
+  }
+  __syncthreads();
+  if (threadIdx.x < NF) {
+    double s = 0.0;
+#pragma unroll
+    for (int wv = 0; wv < kBlock / 64; ++wv) s += red[wv][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+// element state sizes: U (2D: cos, sin; 3D: 9), P (sym: 3 / 6), Lambda d*d
+template <int D> struct Sz;
+template <> struct Sz<2> { static constexpr int U = 2, P = 3, L = 4, G = 6; };
+template <> struct Sz<3> { static constexpr int U = 9, P = 6, L = 9, G = 12; };
+
+template <int D, typename R>
+__device__ __forceinline__ void load_P(const R* __restrict P, int64_t m, int64_t e, R out[D][D]) {
+  if constexpr (D == 2) {
+    out[0][0] = P[e];
+    out[0][1] = out[1][0] = P[m + e];
+    out[1][1] = P[2 * m + e];
+  } else {
+    out[0][0] = P[e];
+    out[0][1] = out[1][0] = P[m + e];
+    out[0][2] = out[2][0] = P[2 * m + e];
+    out[1][1] = P[3 * m + e];
+    out[1][2] = out[2][1] = P[4 * m + e];
+    out[2][2] = P[5 * m + e];
+  }
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void store_P(R* __restrict P, int64_t m, int64_t e, const R in[D][D]) {
+  if constexpr (D == 2) {
+    P[e] = in[0][0];
+    P[m + e] = in[0][1];
+    P[2 * m + e] = in[1][1];
+  } else {
+    P[e] = in[0][0];
+    P[m + e] = in[0][1];
+    P[2 * m + e] = in[0][2];
+    P[3 * m + e] = in[1][1];
+    P[4 * m + e] = in[1][2];
+    P[5 * m + e] = in[2][2];
+  }
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void load_U(const R* __restrict U, int64_t m, int64_t e, R out[D][D]) {
+  if constexpr (D == 2) {
+    const R c = U[e], s = U[m + e];
+    out[0][0] = c;
+    out[0][1] = -s;
+    out[1][0] = s;
+    out[1][1] = c;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i / 3][i % 3] = U[i * m + e];
+  }
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void store_U(R* __restrict U, int64_t m, int64_t e, const R in[D][D]) {
+  if constexpr (D == 2) {
+    U[e] = in[0][0];
+    U[m + e] = in[1][0];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) U[i * m + e] = in[i / 3][i % 3];
+  }
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void matmul(const R A[D][D], const R B[D][D], R C[D][D]) {
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) s += A[i][k] * B[k][j];
+      C[i][j] = s;
+    }
+}
+
+// P = V diag(p) V^T
+template <int D, typename R>
+__device__ __forceinline__ void spectral(const R V[D][D], const R p[D], R P[D][D]) {
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i; j < D; ++j) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) s += V[i][k] * p[k] * V[j][k];
+      P[i][j] = s;
+      P[j][i] = s;
+    }
+}
+
+template <int D, typename R>
+__device__ __forceinline__ R det(const R J[D][D]) {
+  if constexpr (D == 2) return J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  else
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// |adj(J)|^2 = |J^{-1}|^2 det(J)^2
+template <int D, typename R>
+__device__ __forceinline__ R adj_norm2(const R J[D][D]) {
+  if constexpr (D == 2) return J[0][0] * J[0][0] + J[0][1] * J[0][1] + J[1][0] * J[1][0] + J[1][1] * J[1][1];
+  else {
+    R s = R(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        const R cf = J[i1][j1] * J[i2][j2] - J[i1][j2] * J[i2][j1];
+        s += cf * cf;
+      }
+    return s;
+  }
+}
+
+// closest rotation to Q; for a tie (Q == 0) the previous rotation is kept
+template <int D, typename R>
+__device__ __forceinline__ void rotation(const R Q[D][D], R U[D][D]) {
+  if constexpr (D == 2) {
+    const R zr = Q[0][0] + Q[1][1];
+    const R zi = Q[1][0] - Q[0][1];
+    const R nz2 = zr * zr + zi * zi;
+    if (nz2 > R(0)) {
+      const R inv = dm::rsqrt_(nz2);
+      const R c = zr * inv, s = zi * inv;
+      U[0][0] = c;
+      U[0][1] = -s;
+      U[1][0] = s;
+      U[1][1] = c;
+    }
+  } else {
+    R n2 = R(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) n2 += Q[i][j] * Q[i][j];
+    if (!(n2 > R(0))) return;
+    R W[3][3], sg[3], V[3][3];
+    dm::svd3(Q, W, sg, V);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) U[i][j] = W[i][0] * V[j][0] + W[i][1] * V[j][1] + W[i][2] * V[j][2];
+  }
+}
+
+// symmetric eigen-decomposition of a D x D symmetric matrix
+template <int D, typename R>
+__device__ __forceinline__ void sym_eig(R S[D][D], R q[D], R V[D][D]) {
+  if constexpr (D == 2) dm::eig2(S[0][0], S[0][1], S[1][1], q, V);
+  else dm::eig3(S, q, V);
+}
+
+// corner vectors of G^T r: g[c][k] = sum_a C[a][c] r[a][k], C[:,0] = -sum_j B[:,j]
+template <int D, typename R>
+__device__ __forceinline__ void store_g(R* __restrict g, int64_t e, const R Bm[D][D], const R r[D][D]) {
+  R out[(D + 1) * D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    R s0 = R(0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      R s = R(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) s += Bm[a][j] * r[a][k];
+      out[(j + 1) * D + k] = s;
+      s0 += s;
+    }
+    out[k] = -s0;
+  }
+  R* dst = g + e * (D + 1) * D;
+#pragma unroll
+  for (int i = 0; i < (D + 1) * D; ++i) dst[i] = out[i];
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void load_B(const R* __restrict B, int64_t m, int64_t e, R Bm[D][D]) {
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int j = 0; j < D; ++j) Bm[a][j] = B[(a * D + j) * m + e];
+}
+
+// ---------------------------------------------------------------------------
+// K1: initialisation (Section "Implementation", "Initializing U, P, Lambda")
+// ---------------------------------------------------------------------------
+template <int D, typename R, int ENERGY>
+__global__ __launch_bounds__(kBlock) void k_init(int64_t m, const int32_t* __restrict T, const double* __restrict B64,
+                                                 const R* __restrict Bm_, const R* __restrict w, R rho,
+                                                 const double* __restrict x, R* __restrict U, R* __restrict P,
+                                                 R* __restrict Lam, R* __restrict gnorm2, R* __restrict g) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= m) return;
+  double x0[D], E[D][D];
+  const int32_t v0 = T[e];
+#pragma unroll
+  for (int k = 0; k < D; ++k) x0[k] = x[static_cast<int64_t>(v0) * D + k];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const int32_t vj = T[(j + 1) * m + e];
+#pragma unroll
+    for (int k = 0; k < D; ++k) E[j][k] = x[static_cast<int64_t>(vj) * D + k] - x0[k];
+  }
+  double Jd[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) s += B64[(a * D + j) * m + e] * E[j][k];
+      Jd[a][k] = s;
+    }
+  // flip decision in float64: det J0 <= 0
+  const bool flipped = !(det<D, double>(Jd) > 0.0);
+  R J[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int k = 0; k < D; ++k) J[a][k] = static_cast<R>(Jd[a][k]);
+  const R eps = static_cast<R>(ENERGY == 1 ? dm::kInitEpsSG : dm::kInitEpsSD);
+  R Ur[D][D], Pm[D][D], sv[D];
+  if constexpr (D == 2) {
+    // SVD J = [u0 u1] diag(s0, s1) V2^T: V2 from the eigenvectors of J^T J
+    // (sorted descending, kept a rotation), u0 = J v0 / |J v0|, u1 = u0 turned
+    // by 90 degrees, s1 = u1 . J v1 signed (negative when det J < 0)
+    const R a = J[0][0], b = J[0][1], c = J[1][0], d = J[1][1];
+    R q[2], V2[2][2];
+    dm::eig2(a * a + c * c, a * b + c * d, b * b + d * d, q, V2);
+    if (q[0] < q[1]) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const R t = V2[i][0];
+        V2[i][0] = -V2[i][1];
+        V2[i][1] = t;
+      }
+    }
+    const R c0[2] = {a * V2[0][0] + b * V2[1][0], c * V2[0][0] + d * V2[1][0]};
+    const R c1[2] = {a * V2[0][1] + b * V2[1][1], c * V2[0][1] + d * V2[1][1]};
+    const R n0 = dm::sqrt_(c0[0] * c0[0] + c0[1] * c0[1]);
+    R u0[2];
+    if (n0 > R(0)) {
+      u0[0] = c0[0] / n0;
+      u0[1] = c0[1] / n0;
+    } else {
+      u0[0] = V2[0][0];
+      u0[1] = V2[1][0];
+    }
+    const R u1[2] = {-u0[1], u0[0]};
+    sv[0] = n0;
+    sv[1] = u1[0] * c1[0] + u1[1] * c1[1];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) Ur[i][j] = u0[i] * V2[j][0] + u1[i] * V2[j][1];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) sv[j] = flipped ? eps : (sv[j] > eps ? sv[j] : eps);
+    spectral<2, R>(V2, sv, Pm);
+  } else {
+    R W[3][3], V3[3][3];
+    dm::svd3(J, W, sv, V3);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Ur[i][j] = W[i][0] * V3[j][0] + W[i][1] * V3[j][1] + W[i][2] * V3[j][2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sv[j] = flipped ? eps : (sv[j] > eps ? sv[j] : eps);
+    spectral<3, R>(V3, sv, Pm);
+  }
+  store_U<D, R>(U, m, e, Ur);
+  store_P<D, R>(P, m, e, Pm);
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) Lam[i * m + e] = R(0);
+  R gn = R(0);
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const R p = sv[j];
+    const R gj = ENERGY == 1 ? p - R(1) / p : p - R(1) / (p * p * p);
+    gn += gj * gj;
+  }
+  gnorm2[e] = gn;
+  // r0 = mu (U0 P0 - 0)
+  R Bm[D][D], UP[D][D], r[D][D];
+  load_B<D, R>(Bm_, m, e, Bm);
+  matmul<D, R>(Ur, Pm, UP);
+  const R mu = rho * w[e];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int k = 0; k < D; ++k) r[a][k] = mu * UP[a][k];
+  store_g<D, R>(g, e, Bm, r);
+}
+
+// r = mu (U P - Lambda) -> corner vectors (after the state is set from outside)
+template <int D, typename R, int ENERGY>
+__global__ __launch_bounds__(kBlock) void k_prepare(int64_t m, const R* __restrict Bm_, const R* __restrict w, R rho,
+                                                    const R* __restrict U, const R* __restrict P,
+                                                    const R* __restrict Lam, R* __restrict gnorm2, R* __restrict g) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= m) return;
+  R Ur[D][D], Pm[D][D], UP[D][D], Bm[D][D], r[D][D];
+  load_U<D, R>(U, m, e, Ur);
+  load_P<D, R>(P, m, e, Pm);
+  load_B<D, R>(Bm_, m, e, Bm);
+  matmul<D, R>(Ur, Pm, UP);
+  const R mu = rho * w[e];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int k = 0; k < D; ++k) r[a][k] = mu * (UP[a][k] - Lam[(a * D + k) * m + e]);
+  store_g<D, R>(g, e, Bm, r);
+  R q[D], V[D][D];
+  sym_eig<D, R>(Pm, q, V);
+  R gn = R(0);
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const R p = q[j];
+    const R gj = ENERGY == 1 ? p - R(1) / p : p - R(1) / (p * p * p);
+    gn += gj * gj;
+  }
+  gnorm2[e] = gn;
+}
+
+// ---------------------------------------------------------------------------
+// K2: W-step right-hand side b = (G^T r)_F - L_FC x_C (eq. solvinginw), float64
+// accumulation; rows >= nF copy the pinned positions into the new map.
+// ---------------------------------------------------------------------------
+template <int D, typename R>
+__global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const int32_t* __restrict dt_ptr,
+                                                 const int32_t* __restrict dt_idx, const R* __restrict g,
+                                                 const int32_t* __restrict pin_ptr, const int32_t* __restrict pin_col,
+                                                 const double* __restrict pin_val, const double* __restrict xC,
+                                                 double* __restrict b, double* __restrict xnew) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (j >= n) return;
+  if (j >= nF) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) xnew[j * D + k] = xC[(j - nF) * D + k];
+    return;
+  }
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  const int32_t s = dt_ptr[j], t = dt_ptr[j + 1];
+  for (int32_t q = s; q < t; ++q) {
+    const int64_t o = static_cast<int64_t>(dt_idx[q]) * D;
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] += static_cast<double>(g[o + k]);
+  }
+  for (int32_t q = pin_ptr[j]; q < pin_ptr[j + 1]; ++q) {
+    const double v = pin_val[q];
+    const int64_t c = pin_col[q];
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] -= v * xC[c * D + k];
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) b[j * D + k] = acc[k];
+}
+
+// ---------------------------------------------------------------------------
+// K4 / K5: level-scheduled triangular solves with the node panels.
+// A task is (node, first output row).  RT output rows per task, the 256
+// threads split the inner dimension CS = 256 / RT ways; the input vector is
+// staged through LDS in chunks of CH entries.
+// ---------------------------------------------------------------------------
+constexpr int kSolveCH = 256;
+
+template <int D, int RT>
+__global__ __launch_bounds__(kBlock) void k_solve_fwd(const int2* __restrict tasks, const NodeDev* __restrict nodes,
+                                                      const double* __restrict Pf, const int32_t* __restrict pull_ptr,
+                                                      const int32_t* __restrict pull_idx, const double* __restrict b,
+                                                      double* __restrict y, double* __restrict ub) {
+  constexpr int CS = kBlock / RT;
+  __shared__ double vs[kSolveCH][D];
+  __shared__ double red[CS][RT][D];
+  const int2 tk = tasks[blockIdx.x];
+  const NodeDev nd = nodes[tk.x];
+  const int c = nd.c, nf = nd.c + nd.r;
+  const int row0 = tk.y;
+  const int lr = threadIdx.x % RT, cs = threadIdx.x / RT;
+  const int row = row0 + lr;
+  const bool active = row < nf;
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  const double* __restrict P = Pf + nd.pf;
+  const int jmax = min(c, row0 + RT);
+  for (int j0 = 0; j0 < jmax; j0 += kSolveCH) {
+    const int jn = min(kSolveCH, jmax - j0);
+    for (int t = threadIdx.x; t < jn; t += kBlock) {
+      const int p = j0 + t;
+      double a[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) a[k] = b[static_cast<int64_t>(nd.first + p) * D + k];
+      for (int32_t q = pull_ptr[nd.poff + p]; q < pull_ptr[nd.poff + p + 1]; ++q) {
+        const int64_t o = static_cast<int64_t>(pull_idx[q]) * D;
+#pragma unroll
+        for (int k = 0; k < D; ++k) a[k] += ub[o + k];
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) vs[t][k] = a[k];
+    }
+    __syncthreads();
+    if (active) {
+      const double* __restrict col = P + static_cast<int64_t>(j0) * nf + row;
+#pragma unroll 8
+      for (int jj = cs; jj < jn; jj += CS) {
+        const double pv = col[static_cast<int64_t>(jj) * nf];
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] += pv * vs[jj][k];
+      }
+    }
+    __syncthreads();
+  }
+  if (CS > 1) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) red[cs][lr][k] = acc[k];
+    __syncthreads();
+    if (cs == 0) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double s = red[0][lr][k];
+#pragma unroll
+        for (int q = 1; q < CS; ++q) s += red[q][lr][k];
+        acc[k] = s;
+      }
+    }
+  }
+  if (cs == 0 && active) {
+    if (row < c) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) y[static_cast<int64_t>(nd.first + row) * D + k] = acc[k];
+    } else {
+      for (int32_t q = pull_ptr[nd.poff + row]; q < pull_ptr[nd.poff + row + 1]; ++q) {
+        const int64_t o = static_cast<int64_t>(pull_idx[q]) * D;
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] += ub[o + k];
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) ub[(nd.uoff + row - c) * D + k] = acc[k];
+    }
+  }
+}
+
+template <int D, int RT>
+__global__ __launch_bounds__(kBlock) void k_solve_bwd(const int2* __restrict tasks, const NodeDev* __restrict nodes,
+                                                      const double* __restrict Pb, const int32_t* __restrict sidx,
+                                                      const double* __restrict y, double* __restrict x) {
+  constexpr int CS = kBlock / RT;
+  __shared__ double vs[kSolveCH][D];
+  __shared__ double red[CS][RT][D];
+  const int2 tk = tasks[blockIdx.x];
+  const NodeDev nd = nodes[tk.x];
+  const int c = nd.c, nf = nd.c + nd.r;
+  const int col0 = tk.y;
+  const int lr = threadIdx.x % RT, cs = threadIdx.x / RT;
+  const int j = col0 + lr;
+  const bool active = j < c;
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  const double* __restrict P = Pb + nd.pb;
+  for (int p0 = col0; p0 < nf; p0 += kSolveCH) {
+    const int pn = min(kSolveCH, nf - p0);
+    for (int t = threadIdx.x; t < pn; t += kBlock) {
+      const int p = p0 + t;
+      const int64_t src = p < c ? static_cast<int64_t>(nd.first + p) : static_cast<int64_t>(sidx[nd.soff + p - c]);
+      const double* vsrc = p < c ? y : x;
+#pragma unroll
+      for (int k = 0; k < D; ++k) vs[t][k] = vsrc[src * D + k];
+    }
+    __syncthreads();
+    if (active) {
+      const double* __restrict colp = P + static_cast<int64_t>(p0) * c + j;
+#pragma unroll 8
+      for (int pp = cs; pp < pn; pp += CS) {
+        const double pv = colp[static_cast<int64_t>(pp) * c];
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] += pv * vs[pp][k];
+      }
+    }
+    __syncthreads();
+  }
+  if (CS > 1) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) red[cs][lr][k] = acc[k];
+    __syncthreads();
+    if (cs == 0) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double s = red[0][lr][k];
+#pragma unroll
+        for (int q = 1; q < CS; ++q) s += red[q][lr][k];
+        acc[k] = s;
+      }
+    }
+  }
+  if (cs == 0 && active) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[static_cast<int64_t>(nd.first + j) * D + k] = acc[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K3: the fused local step: J = G W^k; U-step; P-step; Lambda-step; emit the
+// next W-step's corner vectors; per-block partial sums (Algorithm 1 and eq.
+// primaldualerror).  Partials: 0 e_prim^2, 1 e_dual^2, 2 E_P, 3 E_map (over
+// det J > 0), 4 Phi, 5 flips, 6 non-finite Lambda, 7 |GW|^2, 8 |P|^2.
+// ---------------------------------------------------------------------------
+template <int D, typename R, int ENERGY>
+__global__ __launch_bounds__(kBlock) void k_local(int64_t m, const int32_t* __restrict T, const R* __restrict Bm_,
+                                                  const R* __restrict w, R rho, int h_mode,
+                                                  const double* __restrict x, const double* __restrict xprev,
+                                                  R* __restrict U, R* __restrict P, R* __restrict Lam,
+                                                  R* __restrict gnorm2, R* __restrict g,
+                                                  double* __restrict partials) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  double part[kNumPartials];
+#pragma unroll
+  for (int f = 0; f < kNumPartials; ++f) part[f] = 0.0;
+  if (e < m) {
+    // edge differences in float64, then the Jacobians J = B E and J - J_prev
+    double x0[D], d0[D];
+    const int32_t v0 = T[e];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      x0[k] = x[static_cast<int64_t>(v0) * D + k];
+      d0[k] = x0[k] - xprev[static_cast<int64_t>(v0) * D + k];
+    }
+    R E[D][D], dE[D][D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int64_t vj = T[(j + 1) * m + e];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const double xv = x[vj * D + k];
+        E[j][k] = static_cast<R>(xv - x0[k]);
+        dE[j][k] = static_cast<R>((xv - xprev[vj * D + k]) - d0[k]);
+      }
+    }
+    R Bm[D][D], J[D][D], Jd[D][D];
+    load_B<D, R>(Bm_, m, e, Bm);
+    matmul<D, R>(Bm, E, J);
+    matmul<D, R>(Bm, dE, Jd);
+    R Ur[D][D], Pm[D][D], L[D][D], A[D][D], Q[D][D];
+    load_U<D, R>(U, m, e, Ur);
+    load_P<D, R>(P, m, e, Pm);
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) L[i / D][i % D] = Lam[i * m + e];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int k = 0; k < D; ++k) A[a][k] = J[a][k] + L[a][k];
+    // U-step: Q = (J + Lambda) P + (h/mu) U_prev; h/mu = 20 (1 + |grad f(P_prev)|^2) / rho^2
+    matmul<D, R>(A, Pm, Q);
+    if (h_mode == 1) {
+      const R hm = R(20) * (R(1) + gnorm2[e]) / (rho * rho);
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int k = 0; k < D; ++k) Q[a][k] += hm * Ur[a][k];
+    }
+    rotation<D, R>(Q, Ur);
+    // P-step: S = symm(U^T A), per-eigenvalue roots, floor
+    R S[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = i; j < D; ++j) {
+        R s1 = R(0), s2 = R(0);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          s1 += Ur[k][i] * A[k][j];
+          s2 += Ur[k][j] * A[k][i];
+        }
+        S[i][j] = S[j][i] = R(0.5) * (s1 + s2);
+      }
+    R q[D], V[D][D], p[D];
+    sym_eig<D, R>(S, q, V);
+    R detp = R(1), trp = R(0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      p[j] = dm::root<ENERGY, R>(q[j], rho);
+      detp *= p[j];
+      trp += p[j];
+    }
+    const R fl = static_cast<R>(dm::kSqrtEps);
+    if (detp < fl || trp < fl) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) p[j] = p[j] > fl ? p[j] : fl;
+    }
+    spectral<D, R>(V, p, Pm);
+    // Lambda-step and the next right-hand side r = mu (U P - Lambda)
+    R UP[D][D], r[D][D];
+    matmul<D, R>(Ur, Pm, UP);
+    const R we = w[e];
+    const R mu = rho * we;
+    double ep = 0.0, lam2 = 0.0, res2 = 0.0, gw = 0.0;
+    bool finite = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const R dv = J[a][k] - UP[a][k];
+        const R ln = L[a][k] + dv;
+        L[a][k] = ln;
+        r[a][k] = mu * (UP[a][k] - ln);
+        ep += static_cast<double>(dv) * dv;
+        lam2 += static_cast<double>(ln) * ln;
+        res2 += static_cast<double>(dv + ln) * (dv + ln);
+        gw += static_cast<double>(J[a][k]) * J[a][k];
+        finite = finite && (ln - ln == R(0));
+      }
+    store_U<D, R>(U, m, e, Ur);
+    store_P<D, R>(P, m, e, Pm);
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) Lam[i * m + e] = L[i / D][i % D];
+    store_g<D, R>(g, e, Bm, r);
+    double fP = 0.0, p2 = 0.0;
+    R gn = R(0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      fP += dm::f_eig<ENERGY, R>(p[j]);
+      p2 += static_cast<double>(p[j]) * p[j];
+      const R gj = ENERGY == 1 ? p[j] - R(1) / p[j] : p[j] - R(1) / (p[j] * p[j] * p[j]);
+      gn += gj * gj;
+    }
+    gnorm2[e] = gn;
+    double jd2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int k = 0; k < D; ++k) jd2 += static_cast<double>(Jd[a][k]) * Jd[a][k];
+    const double wd = static_cast<double>(we), mud = static_cast<double>(mu);
+    const R dJ = det<D, R>(J);
+    part[0] = ep;
+    part[1] = mud * mud * jd2;
+    part[2] = wd * fP;
+    if (dJ > R(0)) {
+      const double dd = static_cast<double>(dJ);
+      double fJ;
+      if constexpr (ENERGY == 1) fJ = 0.5 * gw - log(dd);
+      else fJ = 0.5 * (gw + static_cast<double>(adj_norm2<D, R>(J)) / (dd * dd));
+      part[3] = wd * fJ;
+    } else {
+      part[5] = 1.0;
+    }
+    part[4] = wd * fP + 0.5 * mud * (res2 - lam2);
+    part[6] = finite ? 0.0 : 1.0;
+    part[7] = gw;
+    part[8] = p2;
+  }
+  block_reduce_store<kNumPartials>(part, partials + static_cast<int64_t>(blockIdx.x) * kNumPartials);
+}
+
+// fixed-order reduction of the block partials into one history record
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict partials, int64_t nb,
+                                                     double* __restrict hist) {
+  double v[kNumPartials];
+#pragma unroll
+  for (int f = 0; f < kNumPartials; ++f) v[f] = 0.0;
+  for (int64_t bi = threadIdx.x; bi < nb; bi += kBlock)
+#pragma unroll
+    for (int f = 0; f < kNumPartials; ++f) v[f] += partials[bi * kNumPartials + f];
+  __shared__ double out[kNumPartials];
+  block_reduce_store<kNumPartials>(v, out);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double flips = out[5];
+    hist[0] = sqrt(out[0]);
+    hist[1] = sqrt(out[1]);
+    hist[2] = out[2];
+    hist[3] = flips > 0.0 ? __longlong_as_double(0x7ff0000000000000LL) : out[3];
+    hist[4] = out[4];
+    hist[5] = flips;
+    hist[6] = out[6];
+    hist[7] = sqrt(out[7]);
+    hist[8] = sqrt(out[8]);
+    hist[9] = __longlong_as_double(0x7ff8000000000000LL);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// layout conversions at the boundary
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_map_in(int64_t n, const int32_t* __restrict new2old, const double* __restrict ext,
+                         double* __restrict xint) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (j >= n) return;
+  const int64_t o = new2old[j];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xint[j * D + k] = ext[o * D + k];
+}
+
+template <int D>
+__global__ void k_map_out(int64_t n, const int32_t* __restrict new2old, const double* __restrict xint,
+                          double* __restrict ext) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (j >= n) return;
+  const int64_t o = new2old[j];
+#pragma unroll
+  for (int k = 0; k < D; ++k) ext[o * D + k] = xint[j * D + k];
+}
+
+template <int D, typename R>
+__global__ void k_state_in(int64_t m, const int32_t* __restrict e_new2old, const R* __restrict Uext,
+                           const R* __restrict Pext, const R* __restrict Lext, R* __restrict U, R* __restrict P,
+                           R* __restrict Lam) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= m) return;
+  const int64_t o = static_cast<int64_t>(e_new2old[e]) * D * D;
+  R Um[D][D], Pm[D][D];
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) {
+    Um[i / D][i % D] = Uext[o + i];
+    Pm[i / D][i % D] = Pext[o + i];
+    Lam[i * m + e] = Lext[o + i];
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i + 1; j < D; ++j) Pm[i][j] = Pm[j][i] = R(0.5) * (Pm[i][j] + Pm[j][i]);
+  store_U<D, R>(U, m, e, Um);
+  store_P<D, R>(P, m, e, Pm);
+}
+
+template <int D, typename R>
+__global__ void k_state_out(int64_t m, const int32_t* __restrict e_new2old, const R* __restrict U,
+                            const R* __restrict P, const R* __restrict Lam, R* __restrict Uext, R* __restrict Pext,
+                            R* __restrict Lext, R* __restrict Wext) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= m) return;
+  const int64_t o = static_cast<int64_t>(e_new2old[e]) * D * D;
+  R Um[D][D], Pm[D][D], W[D][D];
+  load_U<D, R>(U, m, e, Um);
+  load_P<D, R>(P, m, e, Pm);
+  if (Uext)
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) Uext[o + i] = Um[i / D][i % D];
+  if (Pext)
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) Pext[o + i] = Pm[i / D][i % D];
+  if (Lext)
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) Lext[o + i] = Lam[i * m + e];
+  if (Wext) {
+    matmul<D, R>(Um, Pm, W);
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) Wext[o + i] = W[i / D][i % D];
+  }
+}
+
+// pinned positions from the internal map (rows nF..n-1)
+template <int D>
+__global__ void k_pins_from_map(int64_t nF, int64_t nC, const double* __restrict x, double* __restrict xC) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= nC) return;
+#pragma unroll
+  for (int k = 0; k < D; ++k) xC[i * D + k] = x[(nF + i) * D + k];
+}
+
+}  // namespace ffd

@@ -1,0 +1,248 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (relative Frobenius error over the whole array): 1e-5 per
+iteration on the map and on W_el = U P; 1e-4 on the final energy.  Sizes span
+several 256-element tiles with a ragged tail."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2107_05200_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make(w, precision, h_mode=0):
+    from paper_2107_05200_amd.binding import Solver
+    return Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=precision, h_mode=h_mode)
+
+
+def oracle_for(w, h_mode=0):
+    s = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, h_mode=h_mode)
+    s.init(w.x0)
+    return s
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# the whole iteration, free-running, float64 (height-field chart, 200 iterations)
+# ---------------------------------------------------------------------------
+
+def test_height_field_fp64_free_running(gpu_lib):
+    import torch
+    w = mg.height_field_uv()
+    say("case: height_field_uv_32 fp64 free-running 200")
+    g = make(w, 64)
+    g.init(w.x0)
+    r = oracle_for(w)
+    worst_x = worst_w = 0.0
+    for k in range(200):
+        g.iterate(1)
+        r.iterate(1)
+        if k % 10 == 0 or k == 199:
+            st = g.get_state()
+            torch.cuda.synchronize()
+            worst_x = max(worst_x, rel(host(st["map"]), r.x))
+            worst_w = max(worst_w, rel(host(st["Wel"]), r.wel()))
+    say(f"worst rel err map {worst_x:.3e} Wel {worst_w:.3e}")
+    assert worst_x < 1e-5 and worst_w < 1e-5
+    h = g.history()
+    hr = r.history.array()
+    assert abs(h[-1, 2] - hr[-1, 2]) <= 1e-4 * abs(hr[-1, 2])
+    assert np.allclose(h[:, 0], hr[:, 0], rtol=1e-6, atol=1e-12)
+    assert np.allclose(h[:, 1], hr[:, 1], rtol=1e-6, atol=1e-12)
+    assert np.array_equal(h[:, 5], hr[:, 5])
+    fin = np.isfinite(hr[:, 3])
+    assert np.array_equal(np.isfinite(h[:, 3]), fin)
+    assert np.allclose(h[fin, 3], hr[fin, 3], rtol=1e-8)
+    assert np.allclose(h[:, 4], hr[:, 4], rtol=1e-6, atol=1e-10)
+    assert np.allclose(h[:, 7:9], hr[:, 7:9], rtol=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# teacher forcing: one GPU iteration from the oracle's state k-1 vs the oracle
+# ---------------------------------------------------------------------------
+
+CASES = {
+    "height_field_fp32": (lambda: mg.height_field_uv(), 32, 0),
+    "height_field_fp64_h1": (lambda: mg.height_field_uv(), 64, 1),
+    "cube6_sd_fp32": (lambda: mg.twisted_cube(6), 32, 0),
+    "cube6_sd_fp64": (lambda: mg.twisted_cube(6), 64, 0),
+    "cube5_sg_fp32": (lambda: mg.twisted_cube(5, energy=mg.SYMMETRIC_GRADIENT), 32, 0),
+    "sphere_cap_sg_fp32": (lambda: mg.sphere_cap_uv(R=15), 32, 0),
+    "disk_sd_fp64": (lambda: mg.disk_deformation(R=14), 64, 0),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_teacher_forced_steps(gpu_lib, name):
+    import torch
+    mk, prec, h_mode = CASES[name]
+    w = mk()
+    say(f"case: teacher-forced {name} m={w.m}")
+    g = make(w, prec, h_mode)
+    r = oracle_for(w, h_mode)
+    npd = np.float32 if prec == 32 else np.float64
+    for k in range(1, 13):
+        if k in (1, 2, 5, 12):
+            # round the oracle state to the GPU precision, then one step on both
+            x, U, P, L = r.x.copy(), r.U.astype(npd), r.P.astype(npd), r.Lam.astype(npd)
+            P = 0.5 * (P + np.transpose(P, (0, 2, 1)))
+            g.set_state(x, U, P, L, k - 1)
+            g.iterate(1)
+            st = g.get_state()
+            torch.cuda.synchronize()
+            t = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, h_mode=h_mode)
+            t.set_state(x, U.astype(np.float64), P.astype(np.float64), L.astype(np.float64), k - 1)
+            t.iterate(1)
+            ex = rel(host(st["map"]), t.x)
+            ew = rel(host(st["Wel"]), t.wel())
+            el = rel(host(st["Lam"]), t.Lam)
+            say(f"  k={k}: map {ex:.2e} Wel {ew:.2e} Lam {el:.2e}")
+            assert ex < 1e-5 and ew < 1e-5, (k, ex, ew)
+            assert el < (1e-3 if prec == 32 else 1e-8), (k, el)
+            hg = g.history(k - 1, 1)[0]
+            ht = t.history.array()[-1]
+            assert abs(hg[2] - ht[2]) <= 1e-5 * abs(ht[2])
+            assert abs(hg[0] - ht[0]) <= 1e-3 * ht[0] + 1e-6
+            assert np.all(np.linalg.det(host(st["Wel"])) > 0)
+        r.iterate(1)
+
+
+# ---------------------------------------------------------------------------
+# free-running float32 runs: final energy within 1e-4
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,mk,iters", [
+    ("sphere_cap_sg_fp32", lambda: mg.sphere_cap_uv(R=20), 120),
+    ("cube6_sd_fp32", lambda: mg.twisted_cube(6), 100),
+])
+def test_free_running_fp32_energy(gpu_lib, name, mk, iters):
+    import torch
+    w = mk()
+    say(f"case: free-running {name} m={w.m} iters={iters}")
+    g = make(w, 32)
+    g.init(w.x0).iterate(iters)
+    st = g.get_state()
+    torch.cuda.synchronize()
+    r = oracle_for(w)
+    r.iterate(iters)
+    h, hr = g.history(), r.history.array()
+    ee = abs(h[-1, 2] - hr[-1, 2]) / abs(hr[-1, 2])
+    curve = [rel(h[k, 0], hr[k, 0]) for k in (0, iters // 4, iters // 2, iters - 1)]
+    say(f"  final E_P rel err {ee:.2e}; e_prim rel err at 4 points {['%.1e' % c for c in curve]}; "
+        f"map rel err {rel(host(st['map']), r.x):.2e}")
+    assert ee < 1e-4
+    assert np.all(np.linalg.det(host(st["Wel"])) > 0)
+
+
+# ---------------------------------------------------------------------------
+# the global solve alone against a library sparse solve
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mk", [lambda: mg.height_field_uv(), lambda: mg.twisted_cube(9),
+                                lambda: mg.sphere_cap_uv(R=40)], ids=["hf", "cube9", "cap40"])
+def test_solve_matches_sparse_lu(gpu_lib, mk):
+    import torch
+    import scipy.sparse.linalg as spla
+    w = mk()
+    say(f"case: solve {w.name}")
+    g = make(w, 64)
+    order = g.vertex_order()
+    nF = w.n - len(w.pinned_idx)
+    B, wt = O.element_geometry(w.V, w.T)
+    L = O.global_matrix(O.gradient_operator(B, w.T, w.n), w.rho * wt, w.d)
+    free = order[:nF]
+    LFF = L[free][:, free].tocsc()
+    rng = np.random.default_rng(3)
+    b = rng.normal(size=(nF, w.d))
+    x = host(g.solve(torch.tensor(b, device="cuda")))
+    torch.cuda.synchronize()
+    xr = spla.splu(LFF).solve(b)
+    e = rel(x, xr)
+    res = np.linalg.norm(LFF @ x - b) / np.linalg.norm(b)
+    say(f"  rel err {e:.2e} residual {res:.2e}")
+    assert e < 1e-10 and res < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# determinism and checkpoint / resume
+# ---------------------------------------------------------------------------
+
+def test_bitwise_determinism_and_resume(gpu_lib):
+    import torch
+    w = mg.twisted_cube(6)
+    say("case: determinism / resume cube6 fp32")
+    a = make(w, 32)
+    a.init(w.x0).iterate(20)
+    sa = {k: v.clone() for k, v in a.get_state().items()}
+    b = make(w, 32)
+    b.init(w.x0).iterate(20)
+    sb = b.get_state()
+    torch.cuda.synchronize()
+    for k in sa:
+        assert torch.equal(sa[k], sb[k]), k
+    assert np.array_equal(a.history(), b.history())
+    # resume: 10 + set_state + 10 equals 20 straight
+    c = make(w, 32)
+    c.init(w.x0).iterate(10)
+    sc = c.get_state()
+    d = make(w, 32)
+    d.set_state(sc["map"], sc["U"], sc["P"], sc["Lam"], 10)
+    d.iterate(10)
+    sd = d.get_state()
+    torch.cuda.synchronize()
+    for k in ("map", "U", "P", "Lam", "Wel"):
+        assert torch.equal(sd[k], sa[k]), k
+    assert np.array_equal(d.history(10, 10), a.history(10, 10))
+
+
+def test_state_errors(gpu_lib):
+    from paper_2107_05200_amd.binding import FFDError
+    w = mg.height_field_uv(grid=8)
+    g = make(w, 32)
+    with pytest.raises(FFDError) as e:
+        g.iterate(1)
+    assert e.value.status == -7
+    g.init(w.x0).iterate(2)
+    with pytest.raises(FFDError) as e:
+        g.history(0, 3)
+    assert e.value.status == -1
+
+
+def test_pins_change_between_iterations(gpu_lib):
+    """ffd_set_pins (interactive deformation): new handle positions enter the
+    next W-step, exactly as in the oracle."""
+    import torch
+    w = mg.disk_deformation(R=12)
+    say("case: set_pins disk12")
+    g = make(w, 64)
+    g.init(w.x0).iterate(5)
+    r = oracle_for(w)
+    r.iterate(5)
+    newp = w.pinned_pos + 0.05
+    g.set_pins(newp)
+    r.set_pins(newp)
+    g.iterate(5)
+    r.iterate(5)
+    st = g.get_state()
+    torch.cuda.synchronize()
+    assert rel(host(st["map"]), r.x) < 1e-8

@@ -14,3 +14,4 @@ supplement.  It is plain NumPy / SciPy in float64; library primitives
 (SVD, symmetric eigendecomposition, sparse LU solve) serve as steps.
 """
 from .admm import *  # noqa: F401,F403
+from . import adjoint  # noqa: F401

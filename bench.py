@@ -84,6 +84,69 @@ def cpu_baseline(w, state, n_sample: int, passes: int):
             "host_cpu": _cpu_name(), "host_nproc": os.cpu_count()}
 
 
+def adjoint_leg(K: int = 100, every: int = 10):
+    """Disk deformation (99,846 triangles, 16 handles): fwd+bwd seconds per
+    iteration of the checkpointed adjoint divided by plain seconds per iteration."""
+    import torch
+    from paper_2107_05200_amd import binding, meshgen
+    w = meshgen.disk_deformation()
+    s = binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32)
+    s.init(w.V).iterate(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.init(w.V).iterate(K)
+    torch.cuda.synchronize()
+    plain = (time.perf_counter() - t0) / K
+    t0 = time.perf_counter()
+    s.init(w.V).adjoint_forward(K, every)
+    pb, vb = s.adjoint_backward(energy_loss=True)
+    torch.cuda.synchronize()
+    fb = (time.perf_counter() - t0) / K
+    s.close()
+    return {"workload": f"disk deformation, {w.m:,} triangles, 16 handles, K={K}, checkpoint every {every}",
+            "plain_s_per_iter": plain, "fwd_bwd_s_per_iter": fb, "ratio": fb / plain}
+
+
+def batched_leg(iters: int = 200):
+    """256 height-field charts (200..50k triangles, SD/SG mixed): one batched
+    handle vs the same charts run one handle at a time."""
+    import numpy as np
+    import torch
+    from paper_2107_05200_amd import binding, meshgen
+    ws = meshgen.batched_charts()
+    m = sum(w.m for w in ws)
+    t0 = time.perf_counter()
+    bs = binding.BatchSolver(ws, precision=32)
+    setup = time.perf_counter() - t0
+    x0 = np.concatenate([w.x0 for w in ws])
+    bs.init(x0).iterate(5)
+    torch.cuda.synchronize()
+    bs.init(x0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bs.iterate(iters)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    bs.close()
+    solvers = [binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32) for w in ws]
+    for s_, w in zip(solvers, ws):
+        s_.init(w.x0).iterate(2)
+    torch.cuda.synchronize()
+    for s_, w in zip(solvers, ws):
+        s_.init(w.x0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in solvers:
+        s_.iterate(iters)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    for s_ in solvers:
+        s_.close()
+    return {"workload": f"{len(ws)} height-field charts, {m:,} triangles total, SD/SG mixed, {iters} iterations",
+            "batched_elem_iters_per_s": m * iters / tb, "plain_elem_iters_per_s": m * iters / tp,
+            "speedup": tp / tb, "batched_ms_per_iter": tb / iters * 1e3, "setup_s": setup}
+
+
 def _cpu_name():
     try:
         for ln in open("/proc/cpuinfo"):
@@ -103,6 +166,7 @@ def main():
     ap.add_argument("--precision", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=200000)
+    ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and batched legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -186,14 +250,25 @@ def main():
         "roofline_solve": roof_solve,
         "wrhs_gbs": round(wrhs_bytes(d, args.precision, m, nF, n) / (ph["wrhs"] / K * 1e-3) / 1e9, 1),
     }
+    st = None
     if not args.no_cpu_baseline:
-        st = s.get_state()
+        st = {k: v.cpu() for k, v in s.get_state().items()}
         torch.cuda.synchronize()
+    s.close()
+    if not args.no_extra:
+        t0 = time.perf_counter()
+        adj = adjoint_leg()
+        out["fwd_bwd_s_per_iter_vs_plain"] = round(adj["ratio"], 3)
+        out["adjoint"] = adj
+        log(f"adjoint leg: {adj} ({time.perf_counter() - t0:.1f}s)")
+        t0 = time.perf_counter()
+        out["batched"] = batched_leg()
+        log(f"batched leg: {out['batched']} ({time.perf_counter() - t0:.1f}s)")
+    if st is not None:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(w, st, args.cpu_sample, 3)
         log(f"cpu baseline {out['cpu_baseline']['value']:.0f} elems/s ({time.perf_counter() - t0:.1f}s)")
     print(json.dumps(out), flush=True)
-    s.close()
 
 
 if __name__ == "__main__":

@@ -118,6 +118,22 @@ typedef struct {
  * HIP device.  Synchronous.  On success *out is a new handle. */
 ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* out);
 
+/* Batched form: n_meshes independent meshes (same simplex_dim and dim_in;
+ * options with the same precision, h_mode and rho; energy, pins and
+ * auto_pin per mesh; pinned positions given for all meshes or for none) in
+ * one handle.  Their vertices and elements are concatenated in mesh order:
+ * every other call works on the concatenated arrays (map: sum n x d, element
+ * arrays: sum m x d x d) and one ffd_iterate advances all meshes together
+ * (one launch sequence; the meshes' factors form one block-diagonal factor
+ * whose level schedules are merged level by level; elements are grouped by
+ * energy so each launch is single-energy).  History records sum over all
+ * meshes. */
+ffd_status ffd_batch_create(const ffd_mesh* meshes, const ffd_options* opts, int32_t n_meshes, ffd_handle* out);
+
+/* Offsets of each mesh's vertices and elements in the concatenated arrays
+ * (n_meshes + 1 entries each, host; a plain handle reports one mesh). */
+ffd_status ffd_batch_layout(ffd_handle h, int64_t* vertex_offsets, int64_t* element_offsets);
+
 /* Host-only analysis: runs the set-up of ffd_create (geometry, global
  * matrix, ordering, factorisation) without touching a device and returns its
  * statistics; *selfcheck_residual (may be NULL) receives |L_FF x - b| / |b| of
@@ -180,6 +196,30 @@ ffd_status ffd_solve(ffd_handle h, const double* b_dev, double* x_dev, void* str
 /* Internal vertex order: order_host[j] = caller index of internal vertex j
  * (free vertices first, then the pins in options order). */
 ffd_status ffd_get_vertex_order(ffd_handle h, int32_t* order_host);
+
+/* Adjoint, forward part: run n_iter iterations of Algorithm 1 from the
+ * current state (as ffd_iterate, appending history) and keep a device
+ * checkpoint of the state every checkpoint_every iterations, for
+ * ffd_adjoint_backward. */
+ffd_status ffd_adjoint_forward(ffd_handle h, int32_t n_iter, int32_t checkpoint_every, void* stream);
+
+/* Adjoint, reverse part: gradients of a loss of the final element state
+ * with respect to the pinned targets and the rest vertices, through the
+ * n_iter iterations of the last ffd_adjoint_forward (which must be the last
+ * iterations run).  The iterations are recomputed segment by segment from the
+ * checkpoints (Algorithm 1 steps: the W-step by implicit differentiation of
+ * eq. solvinginw with the same factor, the polar U-step, the spectral P-step
+ * of eq. rootfindinginp, the Lambda-step of eq. lambdaupdate).
+ *  Pbar_dev: optional (NULL) device m x d x d in the handle's precision and
+ *    the caller's element order, the gradient of the loss with respect to P^K;
+ *  energy_loss: 1 adds the loss sum_i w_i f(P_i^K) (its P and w terms);
+ *  pins_bar_dev: optional device n_pinned x d float64 output (pinned targets);
+ *  V_bar_dev: optional device n x dim_in float64 output (rest vertices; needs
+ *    dim_in == simplex_dim and assumes W^0 = V, for which the initial state
+ *    does not depend on V).
+ * The handle's state is left as it was after the forward part. */
+ffd_status ffd_adjoint_backward(ffd_handle h, const void* Pbar_dev, int32_t energy_loss, double* pins_bar_dev,
+                                double* V_bar_dev, void* stream);
 
 void ffd_destroy(ffd_handle h);
 

@@ -159,7 +159,7 @@ def _h_sd(p, q, w, mu):
     return (w + mu) * p - w / (p * p * p) - mu * q
 
 
-def root_sd(q, w, mu, iters: int = 200):
+def root_sd(q, w, mu, iters: int = 100):
     """Unique positive root of (w+mu) p^4 - mu q p^3 - w = 0 (eq. peqfsdpluggedin
     per eigenvalue) by bisection, then one Newton step.
 

@@ -68,6 +68,10 @@ _PROTOS = {
     "ffd_get_iteration": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "ffd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ffd_get_vertex_order": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "ffd_adjoint_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "ffd_adjoint_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ffd_batch_create": (C.c_int, [C.POINTER(Mesh), C.POINTER(Options), C.c_int32, C.POINTER(C.c_void_p)]),
+    "ffd_batch_layout": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "ffd_destroy": (None, [C.c_void_p]),
     "ffd_last_error": (C.c_char_p, []),
 }
@@ -248,6 +252,23 @@ class Solver:
         _check(self.lib.ffd_get_vertex_order(self.h, o.ctypes.data_as(C.POINTER(C.c_int32))))
         return o
 
+    def adjoint_forward(self, n_iter: int, checkpoint_every: int = 10, stream=None):
+        """n_iter iterations with checkpoints every checkpoint_every (for adjoint_backward)."""
+        _check(self.lib.ffd_adjoint_forward(self.h, int(n_iter), int(checkpoint_every), _stream(stream)))
+        return self
+
+    def adjoint_backward(self, Pbar=None, energy_loss: bool = True, stream=None):
+        """Gradients (pins_bar (n_pinned, d), V_bar (n, d), float64 device tensors) of
+        sum_i w_i f(P_i^K) (energy_loss) plus <Pbar, P^K> through the last adjoint_forward."""
+        import torch
+        pb = torch.zeros((max(self.n_pinned, 1), self.d), dtype=torch.float64, device=self.device)
+        vb = torch.zeros((self.n, self.d), dtype=torch.float64, device=self.device)
+        Pt = None if Pbar is None else self._dev(Pbar, self.dtype).reshape(self.m, self.d, self.d)
+        _check(self.lib.ffd_adjoint_backward(self.h, C.c_void_p(_dptr(Pt)), int(bool(energy_loss)),
+                                             C.c_void_p(pb.data_ptr()), C.c_void_p(vb.data_ptr()),
+                                             _stream(stream)))
+        return pb[: self.n_pinned], vb
+
     def solve(self, b, stream=None):
         """x = L_FF^{-1} b in the internal free-vertex order (n_free, d) float64."""
         import torch
@@ -255,3 +276,43 @@ class Solver:
         x = torch.zeros((self.n, self.d), dtype=torch.float64, device=self.device)
         _check(self.lib.ffd_solve(self.h, C.c_void_p(bb.data_ptr()), C.c_void_p(x.data_ptr()), _stream(stream)))
         return x[: bb.shape[0]]
+
+
+class BatchSolver(Solver):
+    """Many meshes in one handle (ffd_batch_create): arrays are the meshes'
+    arrays concatenated in order; ``layout()`` gives the offsets."""
+
+    def __init__(self, workloads, precision=32, h_mode=0, leaf_size=0):
+        import torch
+        self.lib = load()
+        ws = list(workloads)
+        self.d = ws[0].T.shape[1] - 1
+        self.n = int(sum(w.V.shape[0] for w in ws))
+        self.m = int(sum(w.T.shape[0] for w in ws))
+        self.precision = precision
+        self.dtype = torch.float32 if precision == 32 else torch.float64
+        meshes = (Mesh * len(ws))()
+        opts = (Options * len(ws))()
+        keep = []
+        npin = 0
+        for i, w in enumerate(ws):
+            ms, k1 = _mesh_struct(w.V, w.T)
+            op, k2 = _options_struct(self.d, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision, h_mode, 1,
+                                     leaf_size)
+            meshes[i] = ms
+            opts[i] = op
+            keep += [k1, k2]
+            npin += len(w.pinned_idx) if len(w.pinned_idx) else 1
+        h = C.c_void_p()
+        _check(self.lib.ffd_batch_create(meshes, opts, len(ws), C.byref(h)))
+        self.h = h
+        self.n_pinned = npin
+        self.n_meshes = len(ws)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def layout(self):
+        vo = np.empty(self.n_meshes + 1, dtype=np.int64)
+        eo = np.empty(self.n_meshes + 1, dtype=np.int64)
+        _check(self.lib.ffd_batch_layout(self.h, vo.ctypes.data_as(C.POINTER(C.c_int64)),
+                                         eo.ctypes.data_as(C.POINTER(C.c_int64))))
+        return vo, eo

@@ -13,6 +13,7 @@
 
 #include "../../include/ffd.h"
 #include "host/setup.hpp"
+#include "adjoint.hpp"
 #include "kernels.hpp"
 
 using namespace ffd;
@@ -34,10 +35,11 @@ ffd_status fail(ffd_status st, const std::string& msg) {
                   std::string(#expr) + ": " + hipGetErrorString(e_));                     \
   } while (0)
 
-constexpr int kRT = 64;  // output rows per solve task
 constexpr int64_t kHistCap0 = 1 << 14;
 
 inline unsigned nblk(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
+
+constexpr int64_t kMinLevelTasks = 1024;  // blocks a solve level should offer before its inner ranges are split
 
 }  // namespace
 
@@ -47,13 +49,21 @@ struct ffd_ctx {
   int64_t n = 0, m = 0, nF = 0, nC = 0;
   bool pins_given = false, auto_pinned = false, initialized = false;
   int64_t k = 0;          // completed iterations
+  struct Seg {
+    int64_t e0, e1;   // element range of one energy (elements are grouped by energy)
+    int energy;
+    int64_t pb0;      // first partial-sum block of the range
+  };
+  std::vector<Seg> segs;
+  std::vector<int64_t> voff, eoff;  // batch layout: vertex / element offsets per mesh (empty: one mesh)
+  int64_t nparts = 0;     // partial-sum blocks of one local step
   int cur = 0;            // index of the buffer holding W^k
   int dev = 0;
   hipStream_t last_stream = nullptr;
   ffd_info info{};
   // host copies
   std::vector<int32_t> vnew2old;
-  std::vector<int32_t> level_fwd_off, level_bwd_off;  // task offsets per level (size nlev + 1)
+  std::vector<int32_t> level_fwd_off, level_bwd_off;  // main task offsets per level (size nlev + 1)
   // device buffers
   int32_t *T = nullptr, *vnew2old_d = nullptr, *enew2old_d = nullptr;
   double* B64 = nullptr;
@@ -65,12 +75,34 @@ struct ffd_ctx {
   int32_t *dt_ptr = nullptr, *dt_idx = nullptr, *pin_ptr = nullptr, *pin_col = nullptr;
   double* pin_val = nullptr;
   NodeDev* nodes = nullptr;
-  double *Pf = nullptr, *Pb = nullptr;
+  double *Prow = nullptr, *Pcol = nullptr;  // factor panels, row- and column-major copies
   int32_t *sidx = nullptr, *pull_ptr = nullptr, *pull_idx = nullptr;
-  int2 *tasks_fwd = nullptr, *tasks_bwd = nullptr;
+  SolveTask *tasks_fwd = nullptr, *tasks_bwd = nullptr, *red_fwd = nullptr, *red_bwd = nullptr;
+  std::vector<int32_t> red_fwd_off, red_bwd_off;  // reduction task offsets per level
+  double* solve_part = nullptr;                   // split-K partials (reused level by level)
   int64_t device_bytes = 0;
   std::vector<void*> allocs;
   std::vector<hipEvent_t> events;
+  double* hist_scratch = nullptr;  // history record target of recomputed iterations
+  // adjoint: incidence of all vertex rows, L_CF, checkpoints and adjoint state
+  int32_t *av_ptr = nullptr, *av_idx = nullptr, *lcf_ptr = nullptr, *lcf_col = nullptr;
+  double* lcf_val = nullptr;
+  int64_t adj_k0 = -1, adj_K = 0, adj_every = 0, adj_nslots = 0;
+  char* adj_ck = nullptr;    // checkpoint slots
+  char* adj_seg = nullptr;   // per-iteration states of one segment (every + 1 slots)
+  char* adj_fin = nullptr;   // the state after the K iterations
+  double *Ubar = nullptr, *Pbar = nullptr, *Lbar = nullptr, *Bbar = nullptr, *wbar = nullptr;
+  double *gadj = nullptr, *lam = nullptr, *xbar = nullptr, *pinsbar = nullptr, *vbar = nullptr;
+  // one saved state: U, P, Lambda, |grad f(P)|^2, the next right-hand side's
+  // corner vectors (so a restored state continues bit for bit), and the map
+  size_t slot_elem_entries() const {
+    const size_t nU = d == 2 ? 2 : 9, nP = d == 2 ? 3 : 6;
+    return nU + nP + static_cast<size_t>(d) * d + 1 + static_cast<size_t>(d + 1) * d;
+  }
+  size_t slot_bytes() const {
+    const size_t el = rsize() * m * slot_elem_entries();
+    return ((el + 255) / 256) * 256 + static_cast<size_t>(n) * d * sizeof(double);
+  }
 
   template <typename T_>
   hipError_t alloc(T_** p, size_t count) {
@@ -113,32 +145,34 @@ std::vector<R> soa(const std::vector<double>& aos, int64_t m, int per) {
 // --------------------------------------------------------------------------
 
 template <int D, typename R, int E>
-void launch_init(ffd_ctx* h, hipStream_t s) {
-  hipLaunchKernelGGL((k_init<D, R, E>), dim3(nblk(h->m)), dim3(kBlock), 0, s, h->m, h->T, h->B64,
+void launch_init(ffd_ctx* h, const ffd_ctx::Seg& g, hipStream_t s) {
+  hipLaunchKernelGGL((k_init<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1, h->T, h->B64,
                      static_cast<const R*>(h->B), static_cast<const R*>(h->w), static_cast<R>(h->rho), h->x[h->cur],
                      static_cast<R*>(h->U), static_cast<R*>(h->P), static_cast<R*>(h->L), static_cast<R*>(h->gn),
                      static_cast<R*>(h->g));
 }
 
 template <int D, typename R, int E>
-void launch_prepare(ffd_ctx* h, hipStream_t s) {
-  hipLaunchKernelGGL((k_prepare<D, R, E>), dim3(nblk(h->m)), dim3(kBlock), 0, s, h->m, static_cast<const R*>(h->B),
-                     static_cast<const R*>(h->w), static_cast<R>(h->rho), static_cast<const R*>(h->U),
-                     static_cast<const R*>(h->P), static_cast<const R*>(h->L), static_cast<R*>(h->gn),
-                     static_cast<R*>(h->g));
+void launch_prepare(ffd_ctx* h, const ffd_ctx::Seg& g, hipStream_t s) {
+  hipLaunchKernelGGL((k_prepare<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1,
+                     static_cast<const R*>(h->B), static_cast<const R*>(h->w), static_cast<R>(h->rho),
+                     static_cast<const R*>(h->U), static_cast<const R*>(h->P), static_cast<const R*>(h->L),
+                     static_cast<R*>(h->gn), static_cast<R*>(h->g));
 }
 
 template <int D, typename R, int E>
-void launch_local(ffd_ctx* h, const double* xnew, const double* xold, hipStream_t s) {
-  hipLaunchKernelGGL((k_local<D, R, E>), dim3(nblk(h->m)), dim3(kBlock), 0, s, h->m, h->T,
-                     static_cast<const R*>(h->B), static_cast<const R*>(h->w), static_cast<R>(h->rho), h->h_mode, xnew,
+void launch_local(ffd_ctx* h, const ffd_ctx::Seg& g, const double* xnew, const double* xold, int store_u,
+                  hipStream_t s) {
+  hipLaunchKernelGGL((k_local<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1, h->T,
+                     static_cast<const R*>(h->B), static_cast<const R*>(h->w), static_cast<R>(h->rho), h->h_mode,
+                     store_u, xnew,
                      xold, static_cast<R*>(h->U), static_cast<R*>(h->P), static_cast<R*>(h->L), static_cast<R*>(h->gn),
-                     static_cast<R*>(h->g), h->partials);
+                     static_cast<R*>(h->g), h->partials + g.pb0 * kNumPartials);
 }
 
 template <int D, typename R>
 void launch_wrhs(ffd_ctx* h, double* xnew, hipStream_t s) {
-  hipLaunchKernelGGL((k_wrhs<D, R>), dim3(nblk(h->n)), dim3(kBlock), 0, s, h->nF, h->n, h->dt_ptr, h->dt_idx,
+  hipLaunchKernelGGL((k_wrhs<D, R>), dim3(nblk(4 * h->n)), dim3(kBlock), 0, s, h->nF, h->n, h->dt_ptr, h->dt_idx,
                      static_cast<const R*>(h->g), h->pin_ptr, h->pin_col, h->pin_val, h->xC, h->b, xnew);
 }
 
@@ -148,8 +182,13 @@ void launch_solve_fwd(ffd_ctx* h, const double* b, hipStream_t s) {
   for (int l = 0; l < nlev; ++l) {
     const int nt = h->level_fwd_off[l + 1] - h->level_fwd_off[l];
     if (nt > 0)
-      hipLaunchKernelGGL((k_solve_fwd<D, kRT>), dim3(nt), dim3(kBlock), 0, s, h->tasks_fwd + h->level_fwd_off[l],
-                         h->nodes, h->Pf, h->pull_ptr, h->pull_idx, b, h->y, h->ub);
+      hipLaunchKernelGGL((k_solve_fwd<D>), dim3(nt), dim3(kBlock), 0, s, h->tasks_fwd + h->level_fwd_off[l], h->nodes,
+                         h->Pcol, h->pull_ptr, h->pull_idx, b, h->y, h->ub, h->solve_part);
+    const int nr = h->red_fwd_off[l + 1] - h->red_fwd_off[l];
+    if (nr > 0)
+      hipLaunchKernelGGL((k_solve_fwd_reduce<D>), dim3((nr + 3) / 4), dim3(kBlock), 0, s,
+                         h->red_fwd + h->red_fwd_off[l], nr, h->nodes, h->pull_ptr, h->pull_idx, h->y, h->ub,
+                         h->solve_part);
   }
 }
 
@@ -159,8 +198,12 @@ void launch_solve_bwd(ffd_ctx* h, double* x, hipStream_t s) {
   for (int l = nlev - 1; l >= 0; --l) {
     const int nt = h->level_bwd_off[l + 1] - h->level_bwd_off[l];
     if (nt > 0)
-      hipLaunchKernelGGL((k_solve_bwd<D, kRT>), dim3(nt), dim3(kBlock), 0, s, h->tasks_bwd + h->level_bwd_off[l],
-                         h->nodes, h->Pb, h->sidx, h->y, x);
+      hipLaunchKernelGGL((k_solve_bwd<D>), dim3(nt), dim3(kBlock), 0, s, h->tasks_bwd + h->level_bwd_off[l], h->nodes,
+                         h->Prow, h->sidx, h->y, x, h->solve_part);
+    const int nr = h->red_bwd_off[l + 1] - h->red_bwd_off[l];
+    if (nr > 0)
+      hipLaunchKernelGGL((k_solve_bwd_reduce<D>), dim3((nr + 3) / 4), dim3(kBlock), 0, s,
+                         h->red_bwd + h->red_bwd_off[l], nr, h->nodes, x, h->solve_part);
   }
 }
 
@@ -170,37 +213,28 @@ void launch_solve(ffd_ctx* h, const double* b, double* x, hipStream_t s) {
   launch_solve_bwd<D>(h, x, s);
 }
 
-void do_init(ffd_ctx* h, hipStream_t s) {
-  const int key = h->d * 100 + h->prec + h->energy;
-#define CASE(D, P, E, R) \
-  case D * 100 + P + E: launch_init<D, R, E>(h, s); break;
-  switch (key) {
-    CASE(2, 32, 0, float) CASE(2, 32, 1, float) CASE(2, 64, 0, double) CASE(2, 64, 1, double)
-    CASE(3, 32, 0, float) CASE(3, 32, 1, float) CASE(3, 64, 0, double) CASE(3, 64, 1, double)
+#define SEG_CASES(FN, ...)                                                  \
+  switch (h->d * 100 + h->prec + g.energy) {                                \
+    case 232: FN<2, float, 0>(__VA_ARGS__); break;                          \
+    case 233: FN<2, float, 1>(__VA_ARGS__); break;                          \
+    case 264: FN<2, double, 0>(__VA_ARGS__); break;                         \
+    case 265: FN<2, double, 1>(__VA_ARGS__); break;                         \
+    case 332: FN<3, float, 0>(__VA_ARGS__); break;                          \
+    case 333: FN<3, float, 1>(__VA_ARGS__); break;                          \
+    case 364: FN<3, double, 0>(__VA_ARGS__); break;                         \
+    case 365: FN<3, double, 1>(__VA_ARGS__); break;                         \
   }
-#undef CASE
+
+void do_init(ffd_ctx* h, hipStream_t s) {
+  for (const auto& g : h->segs) SEG_CASES(launch_init, h, g, s)
 }
 
 void do_prepare(ffd_ctx* h, hipStream_t s) {
-  const int key = h->d * 100 + h->prec + h->energy;
-#define CASE(D, P, E, R) \
-  case D * 100 + P + E: launch_prepare<D, R, E>(h, s); break;
-  switch (key) {
-    CASE(2, 32, 0, float) CASE(2, 32, 1, float) CASE(2, 64, 0, double) CASE(2, 64, 1, double)
-    CASE(3, 32, 0, float) CASE(3, 32, 1, float) CASE(3, 64, 0, double) CASE(3, 64, 1, double)
-  }
-#undef CASE
+  for (const auto& g : h->segs) SEG_CASES(launch_prepare, h, g, s)
 }
 
-void do_local(ffd_ctx* h, const double* xnew, const double* xold, hipStream_t s) {
-  const int key = h->d * 100 + h->prec + h->energy;
-#define CASE(D, P, E, R) \
-  case D * 100 + P + E: launch_local<D, R, E>(h, xnew, xold, s); break;
-  switch (key) {
-    CASE(2, 32, 0, float) CASE(2, 32, 1, float) CASE(2, 64, 0, double) CASE(2, 64, 1, double)
-    CASE(3, 32, 0, float) CASE(3, 32, 1, float) CASE(3, 64, 0, double) CASE(3, 64, 1, double)
-  }
-#undef CASE
+void do_local(ffd_ctx* h, const double* xnew, const double* xold, int store_u, hipStream_t s) {
+  for (const auto& g : h->segs) SEG_CASES(launch_local, h, g, xnew, xold, store_u, s)
 }
 
 void do_wrhs(ffd_ctx* h, double* xnew, hipStream_t s) {
@@ -221,7 +255,10 @@ void do_solve(ffd_ctx* h, const double* b, double* x, hipStream_t s) {
 
 // one iteration of Algorithm 1; with ev != nullptr an event is recorded after
 // each of the five phases
-void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev) {
+// store_u: write the rotation and |grad f|^2 of this iteration (3D, h = 0, reads
+// neither; they are state outputs, so the last iteration of a call and every
+// iteration whose state is saved store them)
+void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true, bool store_u = true) {
   double* xold = h->x[h->cur];
   double* xnew = h->x[1 - h->cur];
   do_wrhs(h, xnew, s);
@@ -236,13 +273,13 @@ void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev) {
     else launch_solve_bwd<3>(h, xnew, s);
   }
   if (ev) (void)hipEventRecord(ev[2], s);
-  do_local(h, xnew, xold, s);
+  do_local(h, xnew, xold, store_u ? 1 : 0, s);
   if (ev) (void)hipEventRecord(ev[3], s);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials, static_cast<int64_t>(nblk(h->m)),
-                     h->hist + h->k * FFD_HIST_FIELDS);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials, h->nparts,
+                     record ? h->hist + h->k * FFD_HIST_FIELDS : h->hist_scratch);
   if (ev) (void)hipEventRecord(ev[4], s);
   h->cur = 1 - h->cur;
-  h->k += 1;
+  if (record) h->k += 1;
 }
 
 ffd_status ensure_hist(ffd_ctx* h, int64_t need, hipStream_t s) {
@@ -267,32 +304,106 @@ ffd_status ensure_hist(ffd_ctx* h, int64_t need, hipStream_t s) {
   return FFD_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// adjoint helpers
+// ---------------------------------------------------------------------------
+struct SlotView {
+  void *U, *P, *L, *gn, *g;
+  double* x;
+};
+
+SlotView slot_view(ffd_ctx* h, char* base) {
+  const size_t nU = h->d == 2 ? 2 : 9, nP = h->d == 2 ? 3 : 6, rs = h->rsize(), m = h->m, d = h->d;
+  SlotView v;
+  v.U = base;
+  v.P = base + rs * m * nU;
+  v.L = base + rs * m * (nU + nP);
+  v.gn = base + rs * m * (nU + nP + d * d);
+  v.g = base + rs * m * (nU + nP + d * d + 1);
+  const size_t el = rs * m * h->slot_elem_entries();
+  v.x = reinterpret_cast<double*>(base + ((el + 255) / 256) * 256);
+  return v;
+}
+
+// element state and map, copied in both directions
+hipError_t copy_state(ffd_ctx* h, char* slot, bool save, hipStream_t s) {
+  const size_t nU = h->d == 2 ? 2 : 9, nP = h->d == 2 ? 3 : 6, rs = h->rsize(), m = h->m, d = h->d;
+  SlotView v = slot_view(h, slot);
+  void* live[6] = {h->U, h->P, h->L, h->gn, h->g, h->x[h->cur]};
+  void* saved[6] = {v.U, v.P, v.L, v.gn, v.g, v.x};
+  const size_t bytes[6] = {rs * m * nU, rs * m * nP, rs * m * d * d, rs * m, rs * m * (d + 1) * d,
+                           sizeof(double) * h->n * d};
+  for (int i = 0; i < 6; ++i) {
+    hipError_t e = save ? hipMemcpyAsync(saved[i], live[i], bytes[i], hipMemcpyDeviceToDevice, s)
+                        : hipMemcpyAsync(live[i], saved[i], bytes[i], hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t save_state(ffd_ctx* h, char* slot, hipStream_t s) { return copy_state(h, slot, true, s); }
+hipError_t load_state(ffd_ctx* h, char* slot, hipStream_t s) { return copy_state(h, slot, false, s); }
+
+template <int D, typename R, int E>
+void launch_adj_seed(ffd_ctx* h, const ffd_ctx::Seg& g, const void* Pbar_ext, int energy_loss, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_seed<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1,
+                     static_cast<const R*>(h->P),
+                     static_cast<const R*>(h->w), energy_loss, static_cast<const R*>(Pbar_ext), h->enew2old_d,
+                     h->Ubar, h->Pbar, h->Lbar, h->Bbar, h->wbar);
+}
+
+template <int D, typename R, int E>
+void launch_adj_local(ffd_ctx* h, const ffd_ctx::Seg& g, const SlotView& prev, const double* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_local<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1, h->T,
+                     static_cast<const R*>(h->B), h->B64, static_cast<R>(h->rho), x, static_cast<const R*>(prev.U),
+                     static_cast<const R*>(prev.P), static_cast<const R*>(prev.L), h->Ubar, h->Pbar, h->Lbar, h->Bbar,
+                     h->gadj);
+}
+
+template <int D, typename R, int E>
+void launch_adj_wstep(ffd_ctx* h, const SlotView& prev, const double* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_wstep<D, R>), dim3(nblk(h->m)), dim3(kBlock), 0, s, h->m, h->T, h->B64,
+                     static_cast<const R*>(h->w), static_cast<R>(h->rho), x, h->lam, static_cast<const R*>(prev.U),
+                     static_cast<const R*>(prev.P), static_cast<const R*>(prev.L), h->Ubar, h->Pbar, h->Lbar, h->Bbar,
+                     h->wbar);
+}
+
+template <int D, typename R, int E>
+void launch_adj_vbar(ffd_ctx* h, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_vbar<D, R>), dim3(nblk(h->m)), dim3(kBlock), 0, s, h->m, h->B64,
+                     static_cast<const R*>(h->w), h->Bbar, h->wbar, h->gadj);
+}
+
+#define ADJ_DISPATCH(FN, ...)                                                        \
+  do {                                                                               \
+    switch (h->d * 100 + h->prec + h->energy) {                                      \
+      case 232: FN<2, float, 0>(__VA_ARGS__); break;                                 \
+      case 233: FN<2, float, 1>(__VA_ARGS__); break;                                 \
+      case 264: FN<2, double, 0>(__VA_ARGS__); break;                                \
+      case 265: FN<2, double, 1>(__VA_ARGS__); break;                                \
+      case 332: FN<3, float, 0>(__VA_ARGS__); break;                                 \
+      case 333: FN<3, float, 1>(__VA_ARGS__); break;                                 \
+      case 364: FN<3, double, 0>(__VA_ARGS__); break;                                \
+      case 365: FN<3, double, 1>(__VA_ARGS__); break;                                \
+    }                                                                                \
+  } while (0)
+
 }  // namespace
 
 extern "C" {
 
 const char* ffd_last_error(void) { return g_last_error.c_str(); }
 
-ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* out) {
-  if (!mesh || !opt || !out) return fail(FFD_ERR_INVALID_ARG, "NULL argument");
-  *out = nullptr;
-  if (!(opt->energy == 0 || opt->energy == 1)) return fail(FFD_ERR_INVALID_ARG, "energy must be 0 or 1");
-  if (!(opt->precision == 32 || opt->precision == 64)) return fail(FFD_ERR_INVALID_ARG, "precision must be 32 or 64");
-  if (!(opt->h_mode == 0 || opt->h_mode == 1)) return fail(FFD_ERR_INVALID_ARG, "h_mode must be 0 or 1");
-  if (opt->n_pinned < 0 || (opt->n_pinned > 0 && !opt->pinned_idx))
-    return fail(FFD_ERR_INVALID_ARG, "bad pinned vertex list");
+namespace {
+
+// shared by ffd_create and ffd_batch_create: mesh is the (concatenated) mesh,
+// opt the common options, pins in mesh indices, pin_pos empty = taken from W^0
+ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const std::vector<int32_t>& pins,
+                       const std::vector<double>& pin_pos, bool auto_pinned, const std::vector<int8_t>& elem_energy,
+                       const std::vector<int64_t>& voff, const std::vector<int64_t>& eoff, ffd_handle* out) {
+  const ffd_mesh* mesh = &mesh_in;
   const int d = mesh->simplex_dim;
-  std::vector<int32_t> pins;
-  bool auto_pinned = false;
-  if (opt->n_pinned > 0) {
-    pins.assign(opt->pinned_idx, opt->pinned_idx + opt->n_pinned);
-    if (opt->pinned_pos)
-      for (int64_t i = 0; i < opt->n_pinned * d; ++i)
-        if (!std::isfinite(opt->pinned_pos[i])) return fail(FFD_ERR_NOT_FINITE, "non-finite pinned position");
-  } else if (opt->auto_pin) {
-    pins.push_back(0);
-    auto_pinned = true;
-  }
   SetupInput in;
   in.d = d;
   in.din = mesh->dim_in;
@@ -300,10 +411,11 @@ ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* 
   in.m = mesh->n_elements;
   in.V = mesh->V;
   in.T = mesh->T;
-  in.rho = opt->rho;
+  in.rho = opt.rho;
   in.n_pinned = static_cast<int64_t>(pins.size());
   in.pinned_idx = pins.data();
-  in.leaf_size = opt->leaf_size;
+  in.leaf_size = opt.leaf_size;
+  in.elem_energy = elem_energy.empty() ? nullptr : elem_energy.data();
   Setup S;
   std::string err;
   int st = build_setup(in, S, err);
@@ -320,15 +432,17 @@ ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* 
   const auto t0 = std::chrono::steady_clock::now();
   h->d = d;
   h->din = S.din;
-  h->prec = opt->precision;
-  h->energy = opt->energy;
-  h->h_mode = opt->h_mode;
-  h->rho = opt->rho;
+  h->prec = opt.precision;
+  h->energy = opt.energy;
+  h->h_mode = opt.h_mode;
+  h->rho = opt.rho;
   h->n = S.n;
   h->m = S.m;
   h->nF = S.nF;
   h->nC = S.nC;
-  h->pins_given = opt->n_pinned > 0 && opt->pinned_pos != nullptr;
+  h->pins_given = !pin_pos.empty();
+  h->voff = voff;
+  h->eoff = eoff;
   h->auto_pinned = auto_pinned;
   h->vnew2old = S.vnew2old;
   const int64_t m = S.m, n = S.n, nc = d + 1;
@@ -383,45 +497,117 @@ ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* 
   UP(h->alloc(&h->b, std::max<int64_t>(h->nF, 1) * d));
   UP(h->alloc(&h->y, std::max<int64_t>(h->nF, 1) * d));
   UP(h->alloc(&h->ub, std::max<int64_t>(S.ubuf_rows, 1) * d));
-  UP(h->alloc(&h->partials, static_cast<size_t>(nblk(m)) * kNumPartials));
+  {
+    if (elem_energy.empty()) {
+      h->segs.push_back(ffd_ctx::Seg{0, m, opt.energy, 0});
+    } else {
+      if (S.m_energy0 > 0) h->segs.push_back(ffd_ctx::Seg{0, S.m_energy0, 0, 0});
+      if (S.m_energy0 < m) h->segs.push_back(ffd_ctx::Seg{S.m_energy0, m, 1, 0});
+    }
+    int64_t pb = 0;
+    for (auto& g : h->segs) {
+      g.pb0 = pb;
+      pb += nblk(g.e1 - g.e0);
+    }
+    h->nparts = pb;
+  }
+  UP(h->alloc(&h->partials, static_cast<size_t>(std::max<int64_t>(h->nparts, 1)) * kNumPartials));
   UP(upload(h, &h->dt_ptr, S.dt_ptr));
   UP(upload(h, &h->dt_idx, S.dt_idx));
   UP(upload(h, &h->pin_ptr, S.pin_ptr));
   UP(upload(h, &h->pin_col, S.pin_col));
   UP(upload(h, &h->pin_val, S.pin_val));
+  UP(upload(h, &h->av_ptr, S.av_ptr));
+  UP(upload(h, &h->av_idx, S.av_idx));
+  UP(upload(h, &h->lcf_ptr, S.lcf_ptr));
+  UP(upload(h, &h->lcf_col, S.lcf_col));
+  UP(upload(h, &h->lcf_val, S.lcf_val));
+  UP(h->alloc(&h->hist_scratch, FFD_HIST_FIELDS));
   {
+    std::vector<double> prow, pcol;
+    std::vector<int64_t> poff;
+    build_device_panels(S, prow, pcol, poff);
+    std::vector<double>().swap(S.panel_f);
+    UP(upload(h, &h->Prow, prow));
+    std::vector<double>().swap(prow);
+    UP(upload(h, &h->Pcol, pcol));
+    std::vector<double>().swap(pcol);
     std::vector<NodeDev> nd(S.nodes.size());
     for (size_t i = 0; i < S.nodes.size(); ++i) {
       const SolveNode& N = S.nodes[i];
-      nd[i] = NodeDev{N.first, N.c, N.r, 0, N.pf, N.pb, N.uoff, N.soff, N.poff};
+      nd[i] = NodeDev{N.first, N.c, N.r, 0, poff[i], N.uoff, N.soff, N.poff};
     }
     UP(upload(h, &h->nodes, nd));
-    std::vector<int2> tf, tb;
+    std::vector<SolveTask> tf, tb, rf, rb;
+    int32_t max_slots = 1;
     h->level_fwd_off.push_back(0);
     h->level_bwd_off.push_back(0);
+    h->red_fwd_off.push_back(0);
+    h->red_bwd_off.push_back(0);
+    // Output blocks of a level: (node, out0, inner lo, inner hi).  A level with
+    // few output blocks splits their inner ranges into chunks (the largest
+    // chunk that still gives kMinLevelTasks blocks), reduced by a second
+    // launch; other levels run one task per output block.
+    struct OB {
+      int32_t node, out0, lo, hi;
+    };
+    auto schedule = [&](const std::vector<OB>& obs, std::vector<SolveTask>& tasks, std::vector<SolveTask>& red,
+                        int32_t& slots) {
+      int64_t chunk = 0;  // 0: no split
+      if (static_cast<int64_t>(obs.size()) < kMinLevelTasks) {
+        chunk = kSolveKC;
+        for (int64_t kc = 8 * kSolveKC; kc >= kSolveKC; kc /= 2) {
+          int64_t nt = 0;
+          for (const OB& o : obs) nt += (o.hi - o.lo + kc - 1) / kc;
+          if (nt >= kMinLevelTasks) {
+            chunk = kc;
+            break;
+          }
+        }
+      }
+      for (const OB& o : obs) {
+        const int64_t len = o.hi - o.lo;
+        const int32_t nk = chunk > 0 ? static_cast<int32_t>((len + chunk - 1) / chunk) : 1;
+        if (nk == 1) {
+          tasks.push_back(SolveTask{o.node, o.out0, o.lo, o.hi, -1, 1});
+          continue;
+        }
+        const int32_t base = slots;
+        slots += nk;
+        for (int32_t q = 0; q < nk; ++q)
+          tasks.push_back(SolveTask{o.node, o.out0, static_cast<int32_t>(o.lo + q * chunk),
+                                    static_cast<int32_t>(std::min<int64_t>(o.hi, o.lo + (q + 1) * chunk)), base + q,
+                                    nk});
+        red.push_back(SolveTask{o.node, o.out0, 0, 0, base, nk});
+      }
+    };
     for (const auto& lvl : S.level_nodes) {
+      std::vector<OB> of, ob;
       for (int32_t i : lvl) {
         const SolveNode& N = S.nodes[i];
-        for (int r0 = 0; r0 < N.c + N.r; r0 += kRT) tf.push_back(make_int2(i, r0));
-        for (int r0 = 0; r0 < N.c; r0 += kRT) tb.push_back(make_int2(i, r0));
+        const int nf = N.c + N.r;
+        for (int o0 = 0; o0 < nf; o0 += kSolveRT) of.push_back(OB{i, o0, 0, std::min(N.c, o0 + kSolveRT)});
+        for (int o0 = 0; o0 < N.c; o0 += kSolveRT) ob.push_back(OB{i, o0, o0, nf});
       }
+      int32_t sf = 0, sb = 0;  // partial slots of this level (reused by the next)
+      schedule(of, tf, rf, sf);
+      schedule(ob, tb, rb, sb);
+      max_slots = std::max(max_slots, std::max(sf, sb));
       h->level_fwd_off.push_back(static_cast<int32_t>(tf.size()));
       h->level_bwd_off.push_back(static_cast<int32_t>(tb.size()));
+      h->red_fwd_off.push_back(static_cast<int32_t>(rf.size()));
+      h->red_bwd_off.push_back(static_cast<int32_t>(rb.size()));
     }
+    UP(upload(h, &h->red_fwd, rf));
+    UP(upload(h, &h->red_bwd, rb));
+    UP(h->alloc(&h->solve_part, static_cast<size_t>(max_slots) * kSolveRT * d));
     UP(upload(h, &h->tasks_fwd, tf));
     UP(upload(h, &h->tasks_bwd, tb));
   }
-  UP(upload(h, &h->Pf, S.panel_f));
-  std::vector<double>().swap(S.panel_f);
-  UP(upload(h, &h->Pb, S.panel_b));
-  std::vector<double>().swap(S.panel_b);
   UP(upload(h, &h->sidx, S.struct_idx));
   UP(upload(h, &h->pull_ptr, S.pull_ptr));
   UP(upload(h, &h->pull_idx, S.pull_idx));
-  if (h->pins_given) {
-    std::vector<double> pp(opt->pinned_pos, opt->pinned_pos + opt->n_pinned * d);
-    UP(hipMemcpy(h->xC, pp.data(), pp.size() * sizeof(double), hipMemcpyHostToDevice));
-  }
+  if (h->pins_given) UP(hipMemcpy(h->xC, pin_pos.data(), pin_pos.size() * sizeof(double), hipMemcpyHostToDevice));
   UP(hipDeviceSynchronize());
 #undef UP
   const auto t1 = std::chrono::steady_clock::now();
@@ -439,6 +625,107 @@ ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* 
   I.t_upload = std::chrono::duration<double>(t1 - t0).count();
   I.factor_flops = S.factor_flops;
   *out = h;
+  return FFD_OK;
+}
+
+}  // namespace
+
+ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* out) {
+  if (!mesh || !opt || !out) return fail(FFD_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (!(opt->energy == 0 || opt->energy == 1)) return fail(FFD_ERR_INVALID_ARG, "energy must be 0 or 1");
+  if (!(opt->precision == 32 || opt->precision == 64)) return fail(FFD_ERR_INVALID_ARG, "precision must be 32 or 64");
+  if (!(opt->h_mode == 0 || opt->h_mode == 1)) return fail(FFD_ERR_INVALID_ARG, "h_mode must be 0 or 1");
+
+  if (opt->n_pinned < 0 || (opt->n_pinned > 0 && !opt->pinned_idx))
+    return fail(FFD_ERR_INVALID_ARG, "bad pinned vertex list");
+  const int d = mesh->simplex_dim;
+  std::vector<int32_t> pins;
+  bool auto_pinned = false;
+  if (opt->n_pinned > 0) {
+    pins.assign(opt->pinned_idx, opt->pinned_idx + opt->n_pinned);
+    if (opt->pinned_pos)
+      for (int64_t i = 0; i < opt->n_pinned * d; ++i)
+        if (!std::isfinite(opt->pinned_pos[i])) return fail(FFD_ERR_NOT_FINITE, "non-finite pinned position");
+  } else if (opt->auto_pin) {
+    pins.push_back(0);
+    auto_pinned = true;
+  }
+  std::vector<double> ppos;
+  if (opt->n_pinned > 0 && opt->pinned_pos) ppos.assign(opt->pinned_pos, opt->pinned_pos + opt->n_pinned * d);
+  return create_impl(*mesh, *opt, pins, ppos, auto_pinned, {}, {}, {}, out);
+}
+
+ffd_status ffd_batch_create(const ffd_mesh* meshes, const ffd_options* opts, int32_t n_meshes, ffd_handle* out) {
+  if (!meshes || !opts || !out || n_meshes <= 0) return fail(FFD_ERR_INVALID_ARG, "NULL argument or no meshes");
+  *out = nullptr;
+  const ffd_options& o0 = opts[0];
+  const int d = meshes[0].simplex_dim, din = meshes[0].dim_in;
+  if (!(o0.precision == 32 || o0.precision == 64)) return fail(FFD_ERR_INVALID_ARG, "precision must be 32 or 64");
+  if (!(o0.h_mode == 0 || o0.h_mode == 1)) return fail(FFD_ERR_INVALID_ARG, "h_mode must be 0 or 1");
+  const bool with_pos = o0.n_pinned > 0 && o0.pinned_pos != nullptr;
+  std::vector<double> V;
+  std::vector<int32_t> T, pins;
+  std::vector<double> ppos;
+  std::vector<int8_t> energy;
+  std::vector<int64_t> voff{0}, eoff{0};
+  for (int32_t b = 0; b < n_meshes; ++b) {
+    const ffd_mesh& M = meshes[b];
+    const ffd_options& O = opts[b];
+    if (M.simplex_dim != d || M.dim_in != din) return fail(FFD_ERR_INVALID_ARG, "meshes of a batch share d and dim_in");
+    if (O.precision != o0.precision || O.h_mode != o0.h_mode || O.rho != o0.rho)
+      return fail(FFD_ERR_INVALID_ARG, "meshes of a batch share precision, h_mode and rho");
+    if (!(O.energy == 0 || O.energy == 1)) return fail(FFD_ERR_INVALID_ARG, "energy must be 0 or 1");
+    if (!M.V || !M.T || M.n_vertices <= 0 || M.n_elements <= 0) return fail(FFD_ERR_INVALID_ARG, "empty mesh");
+    if (O.n_pinned < 0 || (O.n_pinned > 0 && !O.pinned_idx)) return fail(FFD_ERR_INVALID_ARG, "bad pinned vertex list");
+    const int64_t vb = voff.back();
+    if (vb + M.n_vertices > INT32_MAX / 2) return fail(FFD_ERR_INVALID_ARG, "batch too large");
+    V.insert(V.end(), M.V, M.V + M.n_vertices * din);
+    for (int64_t i = 0; i < M.n_elements * (d + 1); ++i) {
+      if (M.T[i] < 0 || M.T[i] >= M.n_vertices) return fail(FFD_ERR_INVALID_ARG, "element index out of range");
+      T.push_back(static_cast<int32_t>(M.T[i] + vb));
+    }
+    energy.insert(energy.end(), M.n_elements, static_cast<int8_t>(O.energy));
+    if (O.n_pinned > 0) {
+      if ((O.pinned_pos != nullptr) != with_pos)
+        return fail(FFD_ERR_INVALID_ARG, "give pinned positions for all meshes of a batch or for none");
+      for (int64_t i = 0; i < O.n_pinned; ++i) {
+        if (O.pinned_idx[i] < 0 || O.pinned_idx[i] >= M.n_vertices)
+          return fail(FFD_ERR_INVALID_ARG, "pinned index out of range");
+        pins.push_back(static_cast<int32_t>(O.pinned_idx[i] + vb));
+      }
+      if (with_pos) {
+        for (int64_t i = 0; i < O.n_pinned * d; ++i)
+          if (!std::isfinite(O.pinned_pos[i])) return fail(FFD_ERR_NOT_FINITE, "non-finite pinned position");
+        ppos.insert(ppos.end(), O.pinned_pos, O.pinned_pos + O.n_pinned * d);
+      }
+    } else if (O.auto_pin) {
+      if (with_pos) return fail(FFD_ERR_INVALID_ARG, "an auto-pinned mesh in a batch with given pin positions");
+      pins.push_back(static_cast<int32_t>(vb));
+    }
+    voff.push_back(vb + M.n_vertices);
+    eoff.push_back(eoff.back() + M.n_elements);
+  }
+  ffd_mesh all{d, din, voff.back(), eoff.back(), V.data(), T.data()};
+  ffd_options common = o0;
+  return create_impl(all, common, pins, ppos, false, energy, voff, eoff, out);
+}
+
+ffd_status ffd_batch_layout(ffd_handle h, int64_t* vertex_offsets, int64_t* element_offsets) {
+  if (!h) return fail(FFD_ERR_INVALID_ARG, "NULL handle");
+  if (h->voff.empty()) {
+    if (vertex_offsets) {
+      vertex_offsets[0] = 0;
+      vertex_offsets[1] = h->n;
+    }
+    if (element_offsets) {
+      element_offsets[0] = 0;
+      element_offsets[1] = h->m;
+    }
+    return FFD_OK;
+  }
+  if (vertex_offsets) std::memcpy(vertex_offsets, h->voff.data(), h->voff.size() * sizeof(int64_t));
+  if (element_offsets) std::memcpy(element_offsets, h->eoff.data(), h->eoff.size() * sizeof(int64_t));
   return FFD_OK;
 }
 
@@ -524,7 +811,7 @@ ffd_status ffd_iterate(ffd_handle h, int32_t n_iter, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   ffd_status st = ensure_hist(h, h->k + n_iter, s);
   if (st != FFD_OK) return st;
-  for (int32_t it = 0; it < n_iter; ++it) one_iteration(h, s, nullptr);
+  for (int32_t it = 0; it < n_iter; ++it) one_iteration(h, s, nullptr, true, it == n_iter - 1);
   HIP_TRY(hipGetLastError());
   h->last_stream = s;
   return FFD_OK;
@@ -544,7 +831,8 @@ ffd_status ffd_iterate_profiled(ffd_handle h, int32_t n_iter, void* stream, doub
     h->events.push_back(ev);
   }
   HIP_TRY(hipEventRecord(h->events[0], s));
-  for (int32_t it = 0; it < n_iter; ++it) one_iteration(h, s, h->events.data() + 1 + static_cast<size_t>(it) * 5);
+  for (int32_t it = 0; it < n_iter; ++it)
+    one_iteration(h, s, h->events.data() + 1 + static_cast<size_t>(it) * 5, true, it == n_iter - 1);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventSynchronize(h->events[need - 1]));
   for (int f = 0; f < FFD_PROFILE_FIELDS; ++f) phase_ms_host[f] = 0.0;
@@ -652,6 +940,107 @@ ffd_status ffd_solve(ffd_handle h, const double* b_dev, double* x_dev, void* str
 ffd_status ffd_get_vertex_order(ffd_handle h, int32_t* order_host) {
   if (!h || !order_host) return fail(FFD_ERR_INVALID_ARG, "NULL argument");
   std::memcpy(order_host, h->vnew2old.data(), h->vnew2old.size() * sizeof(int32_t));
+  return FFD_OK;
+}
+
+ffd_status ffd_adjoint_forward(ffd_handle h, int32_t n_iter, int32_t checkpoint_every, void* stream) {
+  if (!h) return fail(FFD_ERR_INVALID_ARG, "NULL handle");
+  if (!h->initialized) return fail(FFD_ERR_STATE, "ffd_adjoint_forward before ffd_init / ffd_set_state");
+  if (n_iter <= 0 || checkpoint_every <= 0) return fail(FFD_ERR_INVALID_ARG, "n_iter and checkpoint_every must be > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ffd_status st = ensure_hist(h, h->k + n_iter, s);
+  if (st != FFD_OK) return st;
+  const int64_t nslots = (n_iter + checkpoint_every - 1) / checkpoint_every;
+  const size_t sb = h->slot_bytes();
+  if (nslots > h->adj_nslots || checkpoint_every != h->adj_every) {
+    HIP_TRY(hipStreamSynchronize(s));
+    for (char** pp : {&h->adj_ck, &h->adj_seg, &h->adj_fin})
+      if (*pp) {
+        for (auto& a : h->allocs)
+          if (a == *pp) a = nullptr;
+        (void)hipFree(*pp);
+        *pp = nullptr;
+      }
+    HIP_TRY(h->alloc(&h->adj_ck, sb * nslots));
+    HIP_TRY(h->alloc(&h->adj_seg, sb * (checkpoint_every + 1)));
+    HIP_TRY(h->alloc(&h->adj_fin, sb));
+    h->adj_nslots = nslots;
+  }
+  h->adj_k0 = h->k;
+  h->adj_K = n_iter;
+  h->adj_every = checkpoint_every;
+  for (int32_t it = 0; it < n_iter; ++it) {
+    if (it % checkpoint_every == 0) HIP_TRY(save_state(h, h->adj_ck + sb * (it / checkpoint_every), s));
+    one_iteration(h, s, nullptr);
+  }
+  HIP_TRY(hipGetLastError());
+  h->last_stream = s;
+  return FFD_OK;
+}
+
+ffd_status ffd_adjoint_backward(ffd_handle h, const void* Pbar_dev, int32_t energy_loss, double* pins_bar_dev,
+                                double* V_bar_dev, void* stream) {
+  if (!h) return fail(FFD_ERR_INVALID_ARG, "NULL handle");
+  if (h->adj_k0 < 0 || h->k != h->adj_k0 + h->adj_K)
+    return fail(FFD_ERR_STATE, "ffd_adjoint_backward needs ffd_adjoint_forward as the last iterations");
+  if (V_bar_dev && h->din != h->d)
+    return fail(FFD_ERR_INVALID_ARG, "rest-vertex gradients need dim_in == simplex_dim");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int d = h->d;
+  const int64_t m = h->m, n = h->n;
+  if (!h->Ubar) {
+    HIP_TRY(h->alloc(&h->Ubar, m * d * d));
+    HIP_TRY(h->alloc(&h->Pbar, m * d * d));
+    HIP_TRY(h->alloc(&h->Lbar, m * d * d));
+    HIP_TRY(h->alloc(&h->Bbar, m * d * d));
+    HIP_TRY(h->alloc(&h->wbar, m));
+    HIP_TRY(h->alloc(&h->gadj, m * (d + 1) * d));
+    HIP_TRY(h->alloc(&h->lam, n * d));
+    HIP_TRY(h->alloc(&h->xbar, std::max<int64_t>(h->nF, 1) * d));
+    HIP_TRY(h->alloc(&h->pinsbar, std::max<int64_t>(h->nC, 1) * d));
+    HIP_TRY(h->alloc(&h->vbar, n * d));
+  }
+  HIP_TRY(hipMemsetAsync(h->lam, 0, sizeof(double) * n * d, s));
+  HIP_TRY(hipMemsetAsync(h->pinsbar, 0, sizeof(double) * std::max<int64_t>(h->nC, 1) * d, s));
+  const size_t sb = h->slot_bytes();
+  HIP_TRY(save_state(h, h->adj_fin, s));
+  for (const auto& g : h->segs) SEG_CASES(launch_adj_seed, h, g, Pbar_dev, energy_loss, s)
+  const int64_t K = h->adj_K, every = h->adj_every;
+  const int64_t nseg = (K + every - 1) / every;
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t start = seg * every, len = std::min(every, K - start);
+    HIP_TRY(load_state(h, h->adj_ck + sb * seg, s));
+    HIP_TRY(save_state(h, h->adj_seg, s));
+    for (int64_t t = 1; t <= len; ++t) {
+      one_iteration(h, s, nullptr, false);
+      HIP_TRY(save_state(h, h->adj_seg + sb * t, s));
+    }
+    for (int64_t t = len; t >= 1; --t) {
+      const SlotView prev = slot_view(h, h->adj_seg + sb * (t - 1));
+      const double* xk = slot_view(h, h->adj_seg + sb * t).x;
+      for (const auto& g : h->segs) SEG_CASES(launch_adj_local, h, g, prev, xk, s)
+      hipLaunchKernelGGL((d == 2 ? k_adj_gather<2> : k_adj_gather<3>), dim3(nblk(n)), dim3(kBlock), 0, s, h->nF, n,
+                         h->av_ptr, h->av_idx, h->gadj, h->xbar, h->pinsbar, 1.0);
+      do_solve(h, h->xbar, h->lam, s);
+      ADJ_DISPATCH(launch_adj_wstep, h, prev, xk, s);
+      if (h->nC > 0)
+        hipLaunchKernelGGL((d == 2 ? k_adj_pins<2> : k_adj_pins<3>), dim3(nblk(h->nC)), dim3(kBlock), 0, s, h->nC,
+                           h->lcf_ptr, h->lcf_col, h->lcf_val, h->lam, h->pinsbar);
+    }
+  }
+  if (V_bar_dev) {
+    ADJ_DISPATCH(launch_adj_vbar, h, s);
+    // all rows: pass nF = 0 so every row is written to vbar
+    hipLaunchKernelGGL((d == 2 ? k_adj_gather<2> : k_adj_gather<3>), dim3(nblk(n)), dim3(kBlock), 0, s, n, n,
+                       h->av_ptr, h->av_idx, h->gadj, h->vbar, static_cast<double*>(nullptr), 0.0);
+    hipLaunchKernelGGL((d == 2 ? k_map_out<2> : k_map_out<3>), dim3(nblk(n)), dim3(kBlock), 0, s, n, h->vnew2old_d,
+                       h->vbar, V_bar_dev);
+  }
+  if (pins_bar_dev && h->nC > 0)
+    HIP_TRY(hipMemcpyAsync(pins_bar_dev, h->pinsbar, sizeof(double) * h->nC * d, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(load_state(h, h->adj_fin, s));
+  HIP_TRY(hipGetLastError());
+  h->last_stream = s;
   return FFD_OK;
 }
 

@@ -34,7 +34,10 @@ constexpr double kSqrtEps = 1.4901161193847656e-08;   // eps_m^(1/2)
 constexpr double kInitEpsSG = 1.220703125e-04;        // eps_m^(1/4)
 constexpr double kInitEpsSD = 1.1048543456039805e-02; // eps_m^(1/8)
 
-__device__ __forceinline__ float rsqrt_(float x) { return 1.0f / sqrtf(x); }
+// reciprocal: one v_rcp_f32 (1 ulp) in float32, exact division in float64
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
@@ -54,7 +57,7 @@ template <typename R>
 __device__ __forceinline__ R root_sg(R q, R rho) {
   const R a = R(1) + rho;
   const R disc = sqrt_(rho * rho * q * q + R(4) * a);
-  return q >= R(0) ? (rho * q + disc) / (R(2) * a) : R(2) / (disc - rho * q);
+  return q >= R(0) ? (rho * q + disc) * rcp_(R(2) * a) : R(2) * rcp_(disc - rho * q);
 }
 
 // symmetric Dirichlet: unique positive root of h(p) = (1+rho) p - p^-3 - rho q.
@@ -67,20 +70,20 @@ __device__ __forceinline__ R root_sd(R q, R rho) {
   R p;
   if (q >= R(0)) {
     const R lo1 = sqrt_(rsqrt_(a));  // a^(-1/4)
-    const R lo2 = rho * q / a;
+    const R lo2 = rho * q * rcp_(a);
     p = lo1 > lo2 ? lo1 : lo2;
   } else {
     const R lo1 = sqrt_(rsqrt_(R(2) * a));
-    const R lo2 = cbrt_(R(1) / (R(2) * rho * (-q)));
+    const R lo2 = cbrt_(rcp_(R(2) * rho * (-q)));
     p = lo1 < lo2 ? lo1 : lo2;
   }
 #pragma unroll 1
   for (int it = 0; it < 40; ++it) {
-    const R ip = R(1) / p;
+    const R ip = rcp_(p);
     const R ip3 = ip * ip * ip;
     const R h = a * p - ip3 - rho * q;
     const R dh = a + R(3) * ip3 * ip;
-    const R pn = p - h / dh;
+    const R pn = p - h * rcp_(dh);
     if (!(pn > p)) break;
     p = pn;
   }
@@ -114,10 +117,10 @@ __device__ __forceinline__ void schur2(R app, R apq, R aqq, R& c, R& s, R& t) {
     t = R(0);
     return;
   }
-  const R tau = (aqq - app) / (R(2) * apq);
+  const R tau = (aqq - app) * rcp_(R(2) * apq);
   const R at = abs_(tau);
   // for |tau| huge the rotation is negligible: t ~ 1/(2 tau)
-  t = at > R(1e18) ? R(0.5) / tau : (tau >= R(0) ? R(1) : R(-1)) / (at + sqrt_(R(1) + tau * tau));
+  t = at > R(1e18) ? R(0.5) * rcp_(tau) : (tau >= R(0) ? R(1) : R(-1)) * rcp_(at + sqrt_(R(1) + tau * tau));
   c = rsqrt_(R(1) + t * t);
   s = t * c;
 }
@@ -201,9 +204,9 @@ __device__ __forceinline__ void svd3(const R A[3][3], R U[3][3], R sig[3], R V[3
       const R ga = Bm[0][p] * Bm[0][q] + Bm[1][p] * Bm[1][q] + Bm[2][p] * Bm[2][q];
       if (!(abs_(ga) > Tol<R>::rel * sqrt_(al * be))) continue;
       rotated = true;
-      const R zeta = (be - al) / (R(2) * ga);
+      const R zeta = (be - al) * rcp_(R(2) * ga);
       const R az = abs_(zeta);
-      const R t = az > R(1e18) ? R(0.5) / zeta : (zeta >= R(0) ? R(1) : R(-1)) / (az + sqrt_(R(1) + zeta * zeta));
+      const R t = az > R(1e18) ? R(0.5) * rcp_(zeta) : (zeta >= R(0) ? R(1) : R(-1)) * rcp_(az + sqrt_(R(1) + zeta * zeta));
       const R c = rsqrt_(R(1) + t * t);
       const R s = c * t;
 #pragma unroll

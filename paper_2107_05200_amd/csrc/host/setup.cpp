@@ -252,6 +252,12 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
     }
     pinned[v] = 1;
   }
+  if (in.elem_energy)
+    for (int64_t e = 0; e < m; ++e)
+      if (in.elem_energy[e] != 0 && in.elem_energy[e] != 1) {
+        err = "element energies must be 0 or 1";
+        return ERR_INVALID_ARG;
+      }
   S.d = d;
   S.din = din;
   S.n = n;
@@ -366,7 +372,37 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
   freev.reserve(S.nF);
   for (int64_t v = 0; v < n; ++v)
     if (!pinned[v]) freev.push_back(static_cast<int32_t>(v));
-  std::vector<int32_t> roots = nd.run(freev);
+  // nested dissection per connected component of the free-vertex graph, so
+  // that separate meshes (a batch of charts) never share a separator
+  std::vector<int32_t> roots;
+  {
+    std::vector<int32_t> comp(n, -1), stack;
+    int32_t ncomp = 0;
+    std::vector<std::vector<int32_t>> members;
+    for (int32_t s0 : freev) {
+      if (comp[s0] >= 0) continue;
+      members.emplace_back();
+      comp[s0] = ncomp;
+      stack.push_back(s0);
+      while (!stack.empty()) {
+        const int32_t v = stack.back();
+        stack.pop_back();
+        members.back().push_back(v);
+        for (int64_t k = aptr[v]; k < aptr[v + 1]; ++k)
+          if (comp[adjv[k]] < 0) {
+            comp[adjv[k]] = ncomp;
+            stack.push_back(adjv[k]);
+          }
+      }
+      ++ncomp;
+    }
+    std::vector<int32_t>().swap(freev);
+    for (auto& mem : members) {
+      std::sort(mem.begin(), mem.end());
+      std::vector<int32_t> r = nd.run(mem);
+      roots.insert(roots.end(), r.begin(), r.end());
+    }
+  }
   const int nn = static_cast<int>(nd.cols.size());
   // postorder numbering
   S.vnew2old.assign(n, -1);
@@ -445,7 +481,6 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
   for (int i = 0; i < nn; ++i) {
     SolveNode& N = S.nodes[i];
     N.pf = pf;
-    N.pb = pf;
     N.uoff = uo;
     N.soff = so;
     N.poff = po;
@@ -519,7 +554,6 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
   // ---- numeric multifrontal factorisation --------------------------------------
   t0 = now();
   S.panel_f.assign(pf, 0.0);
-  S.panel_b.assign(pf, 0.0);
   std::vector<std::vector<double>> upd(nn);
   std::vector<int> fail(nn, 0);
   auto factor_node = [&](int i) {
@@ -571,15 +605,10 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
       dense::gemm_nn(r, c, c, 1.0, F.data() + c, nf, Linv.data(), c, 0.0, M.data(), r);
     }
     double* Pf = S.panel_f.data() + N.pf;
-    double* Pb = S.panel_b.data() + N.pb;
     for (int j = 0; j < c; ++j) {
       for (int p = 0; p < c; ++p) Pf[p + static_cast<int64_t>(j) * nf] = p >= j ? Linv[p + static_cast<size_t>(j) * c] : 0.0;
       for (int q = 0; q < r; ++q) Pf[c + q + static_cast<int64_t>(j) * nf] = -M[q + static_cast<size_t>(j) * r];
     }
-    for (int p = 0; p < nf; ++p)
-      for (int j = 0; j < c; ++j)
-        Pb[j + static_cast<int64_t>(p) * c] =
-            p < c ? (p >= j ? Linv[p + static_cast<size_t>(j) * c] : 0.0) : -M[(p - c) + static_cast<size_t>(j) * r];
   };
   // subtree sizes (work) to split into parallel subtrees and a sequential top
   std::vector<double> work(nn, 0);
@@ -631,7 +660,16 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
   }
   S.enew2old.resize(m);
   std::iota(S.enew2old.begin(), S.enew2old.end(), 0);
-  std::stable_sort(S.enew2old.begin(), S.enew2old.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  if (in.elem_energy) {
+    std::stable_sort(S.enew2old.begin(), S.enew2old.end(), [&](int32_t a, int32_t b) {
+      return in.elem_energy[a] != in.elem_energy[b] ? in.elem_energy[a] < in.elem_energy[b] : key[a] < key[b];
+    });
+    S.m_energy0 = 0;
+    for (int64_t e = 0; e < m; ++e) S.m_energy0 += in.elem_energy[e] == 0;
+  } else {
+    std::stable_sort(S.enew2old.begin(), S.enew2old.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    S.m_energy0 = m;
+  }
   S.B.resize(static_cast<size_t>(m) * d * d);
   S.w.resize(m);
   S.T.resize(static_cast<size_t>(m) * nc);
@@ -682,11 +720,11 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
     for (int i = nn - 1; i >= 0; --i) {
       const SolveNode& N = S.nodes[i];
       const int c = N.c, r = N.r, nf = c + r;
-      const double* Pb = S.panel_b.data() + N.pb;
+      const double* Pf = S.panel_f.data() + N.pf;
       for (int j = 0; j < c; ++j) {
         double a = 0.0;
         for (int p = 0; p < nf; ++p)
-          a += Pb[j + static_cast<int64_t>(p) * c] * (p < c ? y[N.first + p] : x[S.struct_idx[N.soff + p - c]]);
+          a += Pf[p + static_cast<int64_t>(j) * nf] * (p < c ? y[N.first + p] : x[S.struct_idx[N.soff + p - c]]);
         x[N.first + j] = a;
       }
     }
@@ -703,6 +741,28 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
     }
     S.selfcheck_residual = std::sqrt(rn / bn);
   }
+  S.av_ptr.assign(n + 1, 0);
+  for (int64_t e = 0; e < m; ++e)
+    for (int c = 0; c < nc; ++c) S.av_ptr[S.T[e * nc + c] + 1]++;
+  for (int64_t v = 0; v < n; ++v) S.av_ptr[v + 1] += S.av_ptr[v];
+  S.av_idx.assign(S.av_ptr[n], 0);
+  {
+    std::vector<int32_t> fill(S.av_ptr.begin(), S.av_ptr.end() - 1);
+    for (int64_t e = 0; e < m; ++e)
+      for (int c = 0; c < nc; ++c) S.av_idx[fill[S.T[e * nc + c]]++] = static_cast<int32_t>(e * nc + c);
+  }
+  S.lcf_ptr.assign(S.nC + 1, 0);
+  for (int64_t i = 0; i < S.nC; ++i) {
+    const int32_t v = S.vnew2old[S.nF + i];
+    for (int64_t k = Lptr[v]; k < Lptr[v + 1]; ++k) {
+      const int32_t u = S.vold2new[Lcol[k]];
+      if (u < S.nF) {
+        S.lcf_col.push_back(u);
+        S.lcf_val.push_back(Lval[k]);
+      }
+    }
+    S.lcf_ptr[i + 1] = static_cast<int32_t>(S.lcf_col.size());
+  }
   S.pin_ptr.assign(S.nF + 1, 0);
   for (int64_t j = 0; j < S.nF; ++j) {
     const int32_t v = S.vnew2old[j];
@@ -716,6 +776,37 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
     S.pin_ptr[j + 1] = static_cast<int32_t>(S.pin_col.size());
   }
   return OK;
+}
+
+int64_t build_device_panels(const Setup& S, std::vector<double>& prow, std::vector<double>& pcol,
+                            std::vector<int64_t>& off) {
+  const size_t nn = S.nodes.size();
+  off.assign(nn, 0);
+  int64_t tot = 0;
+  for (size_t i = 0; i < nn; ++i) {
+    const int64_t c = S.nodes[i].c, nf = S.nodes[i].c + S.nodes[i].r;
+    const int64_t ldr = (c + 1) & ~int64_t(1), ldc = (nf + 1) & ~int64_t(1);
+    off[i] = tot;
+    tot += std::max(nf * ldr, c * ldc);
+    tot = (tot + 1) & ~int64_t(1);
+  }
+  prow.assign(tot, 0.0);
+  pcol.assign(tot, 0.0);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < static_cast<int64_t>(nn); ++i) {
+    const int64_t c = S.nodes[i].c, nf = S.nodes[i].c + S.nodes[i].r;
+    const int64_t ldr = (c + 1) & ~int64_t(1), ldc = (nf + 1) & ~int64_t(1);
+    const double* src = S.panel_f.data() + S.nodes[i].pf;  // column-major, ld = nf
+    double* R = prow.data() + off[i];
+    double* Cc = pcol.data() + off[i];
+    for (int64_t j = 0; j < c; ++j)
+      for (int64_t p = 0; p < nf; ++p) {
+        const double v = src[p + j * nf];
+        R[p * ldr + j] = v;
+        Cc[j * ldc + p] = v;
+      }
+  }
+  return tot;
 }
 
 }  // namespace ffd

@@ -31,6 +31,7 @@ struct SetupInput {
   int64_t n_pinned = 0;
   const int32_t* pinned_idx = nullptr;
   int leaf_size = 0;             // 0: automatic
+  const int8_t* elem_energy = nullptr;  // optional per-element energy (0 or 1), m entries
   bool selfcheck = false;        // solve with the panels on the host and record the residual
 };
 
@@ -40,7 +41,6 @@ struct SetupInput {
 struct SolveNode {
   int32_t first = 0, c = 0, r = 0, level = 0;
   int64_t pf = 0;    // forward panel [Linv; -M], (c + r) x c column-major, ld = c + r
-  int64_t pb = 0;    // backward panel [Linv^T | -M^T], c x (c + r) column-major, ld = c
   int64_t uoff = 0;  // first row of this node's update vector in the update buffer
   int64_t soff = 0;  // offset into struct_idx
   int64_t poff = 0;  // offset into pull_ptr (c + r + 1 entries)
@@ -55,15 +55,21 @@ struct Setup {
   std::vector<double> w;        // m
   std::vector<int32_t> T;       // m x (d+1)
   std::vector<int32_t> vnew2old, vold2new, enew2old;
+  int64_t m_energy0 = 0;        // elements of energy 0 (they come first when elem_energy is given)
   // D^T over free rows: entries e*(d+1)+corner, rows ordered by element index
   std::vector<int32_t> dt_ptr, dt_idx;
   // L_FC over free rows: pinned slot and value
   std::vector<int32_t> pin_ptr, pin_col;
   std::vector<double> pin_val;
+  // incidences of every vertex (free and pinned rows), entries e*(d+1)+corner
+  std::vector<int32_t> av_ptr, av_idx;
+  // L_CF over pinned rows: free column and value
+  std::vector<int32_t> lcf_ptr, lcf_col;
+  std::vector<double> lcf_val;
   // factor of L_FF
   std::vector<SolveNode> nodes;
   std::vector<std::vector<int32_t>> children;
-  std::vector<double> panel_f, panel_b;
+  std::vector<double> panel_f;  // [Linv; -M] per node; the backward pass reads it transposed
   std::vector<int32_t> struct_idx;
   std::vector<int32_t> pull_ptr, pull_idx;
   std::vector<std::vector<int32_t>> level_nodes;
@@ -72,12 +78,19 @@ struct Setup {
   double t_geometry = 0, t_order = 0, t_symbolic = 0, t_numeric = 0;
   double factor_flops = 0;
   int64_t factor_nnz = 0;     // nonzeros of the Cholesky factor (dense node blocks)
-  int64_t panel_entries = 0;  // entries of one panel copy (forward or backward)
+  int64_t panel_entries = 0;  // float64 entries of the panels
   double selfcheck_residual = -1;  // |L_FF x - b| / |b| of a host solve with the panels
 };
 
 // Returns a Status; on error fills err.
 int build_setup(const SetupInput& in, Setup& out, std::string& err);
+
+// Device panel copies: for node s with c columns and nf = c + r rows, a
+// row-major copy (row length c rounded up to even) and a column-major copy
+// (column length nf rounded up to even), both at offset off[s] (even), padding
+// zero.  Returns the total length of each copy.
+int64_t build_device_panels(const Setup& S, std::vector<double>& prow, std::vector<double>& pcol,
+                            std::vector<int64_t>& off);
 
 // Element geometry only (B_i = Dm_i^{-T}, w_i) in the input element order.
 int element_geometry(int d, int din, int64_t m, const double* V, int64_t n, const int32_t* T,

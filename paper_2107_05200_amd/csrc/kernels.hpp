@@ -17,7 +17,8 @@ constexpr int kNumPartials = 9;  // per-block partial sums of the local step
 
 struct NodeDev {
   int32_t first, c, r, pad;
-  int64_t pf, pb, uoff, soff, poff;
+  int64_t pf;    // offset of this node's panel in both panel copies (16-byte aligned)
+  int64_t uoff, soff, poff;
 };
 
 // ---------------------------------------------------------------------------
@@ -236,12 +237,13 @@ __device__ __forceinline__ void load_B(const R* __restrict B, int64_t m, int64_t
 // K1: initialisation (Section "Implementation", "Initializing U, P, Lambda")
 // ---------------------------------------------------------------------------
 template <int D, typename R, int ENERGY>
-__global__ __launch_bounds__(kBlock) void k_init(int64_t m, const int32_t* __restrict T, const double* __restrict B64,
+__global__ __launch_bounds__(kBlock) void k_init(int64_t m, int64_t e0, int64_t e1, const int32_t* __restrict T,
+                                                 const double* __restrict B64,
                                                  const R* __restrict Bm_, const R* __restrict w, R rho,
                                                  const double* __restrict x, R* __restrict U, R* __restrict P,
                                                  R* __restrict Lam, R* __restrict gnorm2, R* __restrict g) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (e >= m) return;
+  const int64_t e = e0 + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= e1) return;
   double x0[D], E[D][D];
   const int32_t v0 = T[e];
 #pragma unroll
@@ -344,11 +346,12 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t m, const int32_t* __res
 
 // r = mu (U P - Lambda) -> corner vectors (after the state is set from outside)
 template <int D, typename R, int ENERGY>
-__global__ __launch_bounds__(kBlock) void k_prepare(int64_t m, const R* __restrict Bm_, const R* __restrict w, R rho,
-                                                    const R* __restrict U, const R* __restrict P,
-                                                    const R* __restrict Lam, R* __restrict gnorm2, R* __restrict g) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (e >= m) return;
+__global__ __launch_bounds__(kBlock) void k_prepare(int64_t m, int64_t e0, int64_t e1, const R* __restrict Bm_,
+                                                    const R* __restrict w, R rho, const R* __restrict U,
+                                                    const R* __restrict P, const R* __restrict Lam,
+                                                    R* __restrict gnorm2, R* __restrict g) {
+  const int64_t e = e0 + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= e1) return;
   R Ur[D][D], Pm[D][D], UP[D][D], Bm[D][D], r[D][D];
   load_U<D, R>(U, m, e, Ur);
   load_P<D, R>(P, m, e, Pm);
@@ -374,7 +377,9 @@ __global__ __launch_bounds__(kBlock) void k_prepare(int64_t m, const R* __restri
 
 // ---------------------------------------------------------------------------
 // K2: W-step right-hand side b = (G^T r)_F - L_FC x_C (eq. solvinginw), float64
-// accumulation; rows >= nF copy the pinned positions into the new map.
+// accumulation; four lanes per vertex row share its incidence list and are
+// combined by a fixed shuffle tree.  Rows >= nF copy the pinned positions into
+// the new map.
 // ---------------------------------------------------------------------------
 template <int D, typename R>
 __global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const int32_t* __restrict dt_ptr,
@@ -382,22 +387,31 @@ __global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const in
                                                  const int32_t* __restrict pin_ptr, const int32_t* __restrict pin_col,
                                                  const double* __restrict pin_val, const double* __restrict xC,
                                                  double* __restrict b, double* __restrict xnew) {
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t j = t >> 2;
+  const int sub = static_cast<int>(t & 3);
   if (j >= n) return;
   if (j >= nF) {
+    if (sub == 0)
 #pragma unroll
-    for (int k = 0; k < D; ++k) xnew[j * D + k] = xC[(j - nF) * D + k];
+      for (int k = 0; k < D; ++k) xnew[j * D + k] = xC[(j - nF) * D + k];
     return;
   }
   double acc[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) acc[k] = 0.0;
-  const int32_t s = dt_ptr[j], t = dt_ptr[j + 1];
-  for (int32_t q = s; q < t; ++q) {
+  const int32_t s = dt_ptr[j], e = dt_ptr[j + 1];
+  for (int32_t q = s + sub; q < e; q += 4) {
     const int64_t o = static_cast<int64_t>(dt_idx[q]) * D;
 #pragma unroll
     for (int k = 0; k < D; ++k) acc[k] += static_cast<double>(g[o + k]);
   }
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    acc[k] += __shfl_xor(acc[k], 1, 64);
+    acc[k] += __shfl_xor(acc[k], 2, 64);
+  }
+  if (sub != 0) return;
   for (int32_t q = pin_ptr[j]; q < pin_ptr[j + 1]; ++q) {
     const double v = pin_val[q];
     const int64_t c = pin_col[q];
@@ -409,35 +423,79 @@ __global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const in
 }
 
 // ---------------------------------------------------------------------------
-// K4 / K5: level-scheduled triangular solves with the node panels.
-// A task is (node, first output row).  RT output rows per task, the 256
-// threads split the inner dimension CS = 256 / RT ways; the input vector is
-// staged through LDS in chunks of CH entries.
+// K4 / K5: level-scheduled triangular solves with the node panels
+// [Linv; -M] ((c + r) x c): forward y = Linv v, u = carried - M v (v = the
+// node's right-hand side plus its children's update vectors, gathered by the
+// extend-add pull lists); backward x_C = [Linv^T | -M^T] [y; x_R].
+//
+// Both passes put the 64 lanes of a wave on 64 consecutive OUTPUTS and loop
+// over the inner index, so every wave load is 512 contiguous bytes: the
+// forward reads a column-major copy of the panel (column length ldc = nf
+// rounded up to even), the backward a row-major copy (row length ldr = c
+// rounded up to even).  A task owns 64 outputs and one chunk of at most
+// kSolveKC inner entries; the four waves of a block split that chunk and add
+// their sums in a fixed order.  Output blocks whose inner range spans several
+// chunks write per-chunk partials that a reduction kernel adds in chunk order
+// (no atomics; bitwise reproducible).
 // ---------------------------------------------------------------------------
-constexpr int kSolveCH = 256;
+constexpr int kSolveRT = 64;    // outputs per task (one per lane)
+constexpr int kSolveKC = 256;   // inner entries staged in LDS at a time
 
-template <int D, int RT>
-__global__ __launch_bounds__(kBlock) void k_solve_fwd(const int2* __restrict tasks, const NodeDev* __restrict nodes,
-                                                      const double* __restrict Pf, const int32_t* __restrict pull_ptr,
+// a task owns outputs [out0, out0 + 64) of `node` and the inner range [lo, hi);
+// slot < 0: the task covers the whole inner range and writes final outputs;
+// otherwise it writes partials to slot and a reduction adds nk slots from base
+struct SolveTask {
+  int32_t node, out0, lo, hi, slot, nk;
+};
+
+template <int D>
+__device__ __forceinline__ void solve_block_sum(double (&acc)[D], int lane, int wave) {
+  __shared__ double red[4][kSolveRT][D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) red[wave][lane][k] = acc[k];
+  __syncthreads();
+  if (wave == 0)
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] = ((red[0][lane][k] + red[1][lane][k]) + red[2][lane][k]) + red[3][lane][k];
+}
+
+// forward output i of node nd: y row (i < c) or update row (carried part added)
+template <int D>
+__device__ __forceinline__ void fwd_finalize(const NodeDev& nd, int i, double (&acc)[D],
+                                             const int32_t* __restrict pull_ptr, const int32_t* __restrict pull_idx,
+                                             double* __restrict y, double* __restrict ub) {
+  if (i < nd.c) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) y[static_cast<int64_t>(nd.first + i) * D + k] = acc[k];
+  } else {
+    for (int32_t q = pull_ptr[nd.poff + i]; q < pull_ptr[nd.poff + i + 1]; ++q) {
+      const int64_t o = static_cast<int64_t>(pull_idx[q]) * D;
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc[k] += ub[o + k];
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) ub[(nd.uoff + i - nd.c) * D + k] = acc[k];
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_solve_fwd(const SolveTask* __restrict tasks,
+                                                      const NodeDev* __restrict nodes, const double* __restrict Pcol,
+                                                      const int32_t* __restrict pull_ptr,
                                                       const int32_t* __restrict pull_idx, const double* __restrict b,
-                                                      double* __restrict y, double* __restrict ub) {
-  constexpr int CS = kBlock / RT;
-  __shared__ double vs[kSolveCH][D];
-  __shared__ double red[CS][RT][D];
-  const int2 tk = tasks[blockIdx.x];
-  const NodeDev nd = nodes[tk.x];
-  const int c = nd.c, nf = nd.c + nd.r;
-  const int row0 = tk.y;
-  const int lr = threadIdx.x % RT, cs = threadIdx.x / RT;
-  const int row = row0 + lr;
-  const bool active = row < nf;
+                                                      double* __restrict y, double* __restrict ub,
+                                                      double* __restrict part) {
+  __shared__ double vs[kSolveKC][D];
+  const SolveTask tk = tasks[blockIdx.x];
+  const NodeDev nd = nodes[tk.node];
+  const int nf = nd.c + nd.r, ldc = (nf + 1) & ~1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = tk.out0 + lane;
   double acc[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) acc[k] = 0.0;
-  const double* __restrict P = Pf + nd.pf;
-  const int jmax = min(c, row0 + RT);
-  for (int j0 = 0; j0 < jmax; j0 += kSolveCH) {
-    const int jn = min(kSolveCH, jmax - j0);
+  for (int j0 = tk.lo; j0 < tk.hi; j0 += kSolveKC) {
+    const int jn = min(kSolveKC, tk.hi - j0);
     for (int t = threadIdx.x; t < jn; t += kBlock) {
       const int p = j0 + t;
       double a[D];
@@ -452,67 +510,66 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd(const int2* __restrict tas
       for (int k = 0; k < D; ++k) vs[t][k] = a[k];
     }
     __syncthreads();
-    if (active) {
-      const double* __restrict col = P + static_cast<int64_t>(j0) * nf + row;
+    if (i < nf) {
+      const double* __restrict col = Pcol + nd.pf + static_cast<int64_t>(j0) * ldc + i;
 #pragma unroll 8
-      for (int jj = cs; jj < jn; jj += CS) {
-        const double pv = col[static_cast<int64_t>(jj) * nf];
+      for (int jj = wave; jj < jn; jj += 4) {
+        const double pv = col[static_cast<int64_t>(jj) * ldc];
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] += pv * vs[jj][k];
       }
     }
     __syncthreads();
   }
-  if (CS > 1) {
+  solve_block_sum<D>(acc, lane, wave);
+  if (wave != 0 || i >= nf) return;
+  if (tk.slot >= 0) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) red[cs][lr][k] = acc[k];
-    __syncthreads();
-    if (cs == 0) {
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        double s = red[0][lr][k];
-#pragma unroll
-        for (int q = 1; q < CS; ++q) s += red[q][lr][k];
-        acc[k] = s;
-      }
-    }
-  }
-  if (cs == 0 && active) {
-    if (row < c) {
-#pragma unroll
-      for (int k = 0; k < D; ++k) y[static_cast<int64_t>(nd.first + row) * D + k] = acc[k];
-    } else {
-      for (int32_t q = pull_ptr[nd.poff + row]; q < pull_ptr[nd.poff + row + 1]; ++q) {
-        const int64_t o = static_cast<int64_t>(pull_idx[q]) * D;
-#pragma unroll
-        for (int k = 0; k < D; ++k) acc[k] += ub[o + k];
-      }
-#pragma unroll
-      for (int k = 0; k < D; ++k) ub[(nd.uoff + row - c) * D + k] = acc[k];
-    }
+    for (int k = 0; k < D; ++k) part[(static_cast<int64_t>(tk.slot) * kSolveRT + lane) * D + k] = acc[k];
+  } else {
+    fwd_finalize<D>(nd, i, acc, pull_ptr, pull_idx, y, ub);
   }
 }
 
-template <int D, int RT>
-__global__ __launch_bounds__(kBlock) void k_solve_bwd(const int2* __restrict tasks, const NodeDev* __restrict nodes,
-                                                      const double* __restrict Pb, const int32_t* __restrict sidx,
-                                                      const double* __restrict y, double* __restrict x) {
-  constexpr int CS = kBlock / RT;
-  __shared__ double vs[kSolveCH][D];
-  __shared__ double red[CS][RT][D];
-  const int2 tk = tasks[blockIdx.x];
-  const NodeDev nd = nodes[tk.x];
-  const int c = nd.c, nf = nd.c + nd.r;
-  const int col0 = tk.y;
-  const int lr = threadIdx.x % RT, cs = threadIdx.x / RT;
-  const int j = col0 + lr;
-  const bool active = j < c;
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_solve_fwd_reduce(const SolveTask* __restrict tasks, int ntasks,
+                                                             const NodeDev* __restrict nodes,
+                                                             const int32_t* __restrict pull_ptr,
+                                                             const int32_t* __restrict pull_idx,
+                                                             double* __restrict y, double* __restrict ub,
+                                                             const double* __restrict part) {
+  const int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (t >= ntasks) return;
+  const SolveTask tk = tasks[t];
+  const NodeDev nd = nodes[tk.node];
+  const int lane = threadIdx.x & 63;
+  const int i = tk.out0 + lane;
+  if (i >= nd.c + nd.r) return;
   double acc[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) acc[k] = 0.0;
-  const double* __restrict P = Pb + nd.pb;
-  for (int p0 = col0; p0 < nf; p0 += kSolveCH) {
-    const int pn = min(kSolveCH, nf - p0);
+  for (int q = 0; q < tk.nk; ++q)
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] += part[(static_cast<int64_t>(tk.slot + q) * kSolveRT + lane) * D + k];
+  fwd_finalize<D>(nd, i, acc, pull_ptr, pull_idx, y, ub);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_solve_bwd(const SolveTask* __restrict tasks,
+                                                      const NodeDev* __restrict nodes, const double* __restrict Prow,
+                                                      const int32_t* __restrict sidx, const double* __restrict y,
+                                                      double* __restrict x, double* __restrict part) {
+  __shared__ double vs[kSolveKC][D];
+  const SolveTask tk = tasks[blockIdx.x];
+  const NodeDev nd = nodes[tk.node];
+  const int c = nd.c, ldr = (nd.c + 1) & ~1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = tk.out0 + lane;
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  for (int p0 = tk.lo; p0 < tk.hi; p0 += kSolveKC) {
+    const int pn = min(kSolveKC, tk.hi - p0);
     for (int t = threadIdx.x; t < pn; t += kBlock) {
       const int p = p0 + t;
       const int64_t src = p < c ? static_cast<int64_t>(nd.first + p) : static_cast<int64_t>(sidx[nd.soff + p - c]);
@@ -521,35 +578,47 @@ __global__ __launch_bounds__(kBlock) void k_solve_bwd(const int2* __restrict tas
       for (int k = 0; k < D; ++k) vs[t][k] = vsrc[src * D + k];
     }
     __syncthreads();
-    if (active) {
-      const double* __restrict colp = P + static_cast<int64_t>(p0) * c + j;
+    if (j < c) {
+      const double* __restrict rowp = Prow + nd.pf + static_cast<int64_t>(p0) * ldr + j;
 #pragma unroll 8
-      for (int pp = cs; pp < pn; pp += CS) {
-        const double pv = colp[static_cast<int64_t>(pp) * c];
+      for (int pp = wave; pp < pn; pp += 4) {
+        const double pv = rowp[static_cast<int64_t>(pp) * ldr];
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] += pv * vs[pp][k];
       }
     }
     __syncthreads();
   }
-  if (CS > 1) {
+  solve_block_sum<D>(acc, lane, wave);
+  if (wave != 0 || j >= c) return;
+  if (tk.slot >= 0) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) red[cs][lr][k] = acc[k];
-    __syncthreads();
-    if (cs == 0) {
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        double s = red[0][lr][k];
-#pragma unroll
-        for (int q = 1; q < CS; ++q) s += red[q][lr][k];
-        acc[k] = s;
-      }
-    }
-  }
-  if (cs == 0 && active) {
+    for (int k = 0; k < D; ++k) part[(static_cast<int64_t>(tk.slot) * kSolveRT + lane) * D + k] = acc[k];
+  } else {
 #pragma unroll
     for (int k = 0; k < D; ++k) x[static_cast<int64_t>(nd.first + j) * D + k] = acc[k];
   }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_solve_bwd_reduce(const SolveTask* __restrict tasks, int ntasks,
+                                                             const NodeDev* __restrict nodes, double* __restrict x,
+                                                             const double* __restrict part) {
+  const int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (t >= ntasks) return;
+  const SolveTask tk = tasks[t];
+  const NodeDev nd = nodes[tk.node];
+  const int lane = threadIdx.x & 63;
+  const int j = tk.out0 + lane;
+  if (j >= nd.c) return;
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  for (int q = 0; q < tk.nk; ++q)
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] += part[(static_cast<int64_t>(tk.slot + q) * kSolveRT + lane) * D + k];
+#pragma unroll
+  for (int k = 0; k < D; ++k) x[static_cast<int64_t>(nd.first + j) * D + k] = acc[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -559,42 +628,78 @@ __global__ __launch_bounds__(kBlock) void k_solve_bwd(const int2* __restrict tas
 // det J > 0), 4 Phi, 5 flips, 6 non-finite Lambda, 7 |GW|^2, 8 |P|^2.
 // ---------------------------------------------------------------------------
 template <int D, typename R, int ENERGY>
-__global__ __launch_bounds__(kBlock) void k_local(int64_t m, const int32_t* __restrict T, const R* __restrict Bm_,
-                                                  const R* __restrict w, R rho, int h_mode,
+__global__ __launch_bounds__(kBlock) void k_local(int64_t m, int64_t e0, int64_t e1, const int32_t* __restrict T,
+                                                  const R* __restrict Bm_,
+                                                  const R* __restrict w, R rho, int h_mode, int store_u,
                                                   const double* __restrict x, const double* __restrict xprev,
                                                   R* __restrict U, R* __restrict P, R* __restrict Lam,
                                                   R* __restrict gnorm2, R* __restrict g,
                                                   double* __restrict partials) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t e = e0 + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   double part[kNumPartials];
 #pragma unroll
   for (int f = 0; f < kNumPartials; ++f) part[f] = 0.0;
-  if (e < m) {
-    // edge differences in float64, then the Jacobians J = B E and J - J_prev
-    double x0[D], d0[D];
-    const int32_t v0 = T[e];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      x0[k] = x[static_cast<int64_t>(v0) * D + k];
-      d0[k] = x0[k] - xprev[static_cast<int64_t>(v0) * D + k];
-    }
-    R E[D][D], dE[D][D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      const int64_t vj = T[(j + 1) * m + e];
+  if (e < e1) {
+    const R we = w[e];
+    const R mu = rho * we;
+    const double wd = static_cast<double>(we), mud = static_cast<double>(mu);
+    R J[D][D];
+    {
+      // edge differences in float64, then J = B E and the dual residual term
+      double x0[D], d0[D];
+      const int32_t v0 = T[e];
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        const double xv = x[vj * D + k];
-        E[j][k] = static_cast<R>(xv - x0[k]);
-        dE[j][k] = static_cast<R>((xv - xprev[vj * D + k]) - d0[k]);
+        x0[k] = x[static_cast<int64_t>(v0) * D + k];
+        d0[k] = x0[k] - xprev[static_cast<int64_t>(v0) * D + k];
+      }
+      R E[D][D], dE[D][D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const int64_t vj = T[(j + 1) * m + e];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const double xv = x[vj * D + k];
+          E[j][k] = static_cast<R>(xv - x0[k]);
+          dE[j][k] = static_cast<R>((xv - xprev[vj * D + k]) - d0[k]);
+        }
+      }
+      R Bm[D][D], Jd[D][D];
+      load_B<D, R>(Bm_, m, e, Bm);
+      matmul<D, R>(Bm, E, J);
+      matmul<D, R>(Bm, dE, Jd);
+      double jd2 = 0.0, gw = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          jd2 += static_cast<double>(Jd[a][k]) * Jd[a][k];
+          gw += static_cast<double>(J[a][k]) * J[a][k];
+        }
+      part[1] = mud * mud * jd2;
+      part[7] = gw;
+      const R dJ = det<D, R>(J);
+      if (dJ > R(0)) {
+        const double dd = static_cast<double>(dJ);
+        double fJ;
+        if constexpr (ENERGY == 1) fJ = 0.5 * gw - log(dd);
+        else fJ = 0.5 * (gw + static_cast<double>(adj_norm2<D, R>(J)) / (dd * dd));
+        part[3] = wd * fJ;
+      } else {
+        part[5] = 1.0;
       }
     }
-    R Bm[D][D], J[D][D], Jd[D][D];
-    load_B<D, R>(Bm_, m, e, Bm);
-    matmul<D, R>(Bm, E, J);
-    matmul<D, R>(Bm, dE, Jd);
-    R Ur[D][D], Pm[D][D], L[D][D], A[D][D], Q[D][D];
-    load_U<D, R>(U, m, e, Ur);
+    R Ur[D][D], Pm[D][D], L[D][D], A[D][D];
+    // the previous rotation is an input only through the proximal term (h > 0)
+    // and the 2D tie rule; otherwise the rotation is recomputed from Q alone
+    if (D == 2 || h_mode == 1) {
+      load_U<D, R>(U, m, e, Ur);
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) Ur[i][j] = i == j ? R(1) : R(0);
+    }
     load_P<D, R>(P, m, e, Pm);
 #pragma unroll
     for (int i = 0; i < D * D; ++i) L[i / D][i % D] = Lam[i * m + e];
@@ -602,51 +707,55 @@ __global__ __launch_bounds__(kBlock) void k_local(int64_t m, const int32_t* __re
     for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int k = 0; k < D; ++k) A[a][k] = J[a][k] + L[a][k];
-    // U-step: Q = (J + Lambda) P + (h/mu) U_prev; h/mu = 20 (1 + |grad f(P_prev)|^2) / rho^2
-    matmul<D, R>(A, Pm, Q);
-    if (h_mode == 1) {
-      const R hm = R(20) * (R(1) + gnorm2[e]) / (rho * rho);
+    {
+      // U-step: Q = (J + Lambda) P + (h/mu) U_prev; h/mu = 20 (1 + |grad f(P_prev)|^2) / rho^2
+      R Q[D][D];
+      matmul<D, R>(A, Pm, Q);
+      if (h_mode == 1) {
+        const R hm = R(20) * (R(1) + gnorm2[e]) / (rho * rho);
 #pragma unroll
-      for (int a = 0; a < D; ++a)
+        for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int k = 0; k < D; ++k) Q[a][k] += hm * Ur[a][k];
-    }
-    rotation<D, R>(Q, Ur);
-    // P-step: S = symm(U^T A), per-eigenvalue roots, floor
-    R S[D][D];
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-      for (int j = i; j < D; ++j) {
-        R s1 = R(0), s2 = R(0);
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          s1 += Ur[k][i] * A[k][j];
-          s2 += Ur[k][j] * A[k][i];
-        }
-        S[i][j] = S[j][i] = R(0.5) * (s1 + s2);
+          for (int k = 0; k < D; ++k) Q[a][k] += hm * Ur[a][k];
       }
-    R q[D], V[D][D], p[D];
-    sym_eig<D, R>(S, q, V);
-    R detp = R(1), trp = R(0);
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      p[j] = dm::root<ENERGY, R>(q[j], rho);
-      detp *= p[j];
-      trp += p[j];
+      rotation<D, R>(Q, Ur);
     }
-    const R fl = static_cast<R>(dm::kSqrtEps);
-    if (detp < fl || trp < fl) {
+    // P-step: S = symm(U^T A), per-eigenvalue roots, floor
+    R p[D];
+    {
+      R S[D][D];
 #pragma unroll
-      for (int j = 0; j < D; ++j) p[j] = p[j] > fl ? p[j] : fl;
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+          R s1 = R(0), s2 = R(0);
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            s1 += Ur[k][i] * A[k][j];
+            s2 += Ur[k][j] * A[k][i];
+          }
+          S[i][j] = S[j][i] = R(0.5) * (s1 + s2);
+        }
+      R q[D], V[D][D];
+      sym_eig<D, R>(S, q, V);
+      R detp = R(1), trp = R(0);
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        p[j] = dm::root<ENERGY, R>(q[j], rho);
+        detp *= p[j];
+        trp += p[j];
+      }
+      const R fl = static_cast<R>(dm::kSqrtEps);
+      if (detp < fl || trp < fl) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) p[j] = p[j] > fl ? p[j] : fl;
+      }
+      spectral<D, R>(V, p, Pm);
     }
-    spectral<D, R>(V, p, Pm);
     // Lambda-step and the next right-hand side r = mu (U P - Lambda)
     R UP[D][D], r[D][D];
     matmul<D, R>(Ur, Pm, UP);
-    const R we = w[e];
-    const R mu = rho * we;
-    double ep = 0.0, lam2 = 0.0, res2 = 0.0, gw = 0.0;
+    double ep = 0.0, lam2 = 0.0, res2 = 0.0;
     bool finite = true;
 #pragma unroll
     for (int a = 0; a < D; ++a)
@@ -659,14 +768,17 @@ __global__ __launch_bounds__(kBlock) void k_local(int64_t m, const int32_t* __re
         ep += static_cast<double>(dv) * dv;
         lam2 += static_cast<double>(ln) * ln;
         res2 += static_cast<double>(dv + ln) * (dv + ln);
-        gw += static_cast<double>(J[a][k]) * J[a][k];
         finite = finite && (ln - ln == R(0));
       }
-    store_U<D, R>(U, m, e, Ur);
+    if (D == 2 || store_u) store_U<D, R>(U, m, e, Ur);
     store_P<D, R>(P, m, e, Pm);
 #pragma unroll
     for (int i = 0; i < D * D; ++i) Lam[i * m + e] = L[i / D][i % D];
-    store_g<D, R>(g, e, Bm, r);
+    {
+      R Bm[D][D];
+      load_B<D, R>(Bm_, m, e, Bm);
+      store_g<D, R>(g, e, Bm, r);
+    }
     double fP = 0.0, p2 = 0.0;
     R gn = R(0);
 #pragma unroll
@@ -676,29 +788,11 @@ __global__ __launch_bounds__(kBlock) void k_local(int64_t m, const int32_t* __re
       const R gj = ENERGY == 1 ? p[j] - R(1) / p[j] : p[j] - R(1) / (p[j] * p[j] * p[j]);
       gn += gj * gj;
     }
-    gnorm2[e] = gn;
-    double jd2 = 0.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int k = 0; k < D; ++k) jd2 += static_cast<double>(Jd[a][k]) * Jd[a][k];
-    const double wd = static_cast<double>(we), mud = static_cast<double>(mu);
-    const R dJ = det<D, R>(J);
+    if (h_mode == 1 || store_u) gnorm2[e] = gn;
     part[0] = ep;
-    part[1] = mud * mud * jd2;
     part[2] = wd * fP;
-    if (dJ > R(0)) {
-      const double dd = static_cast<double>(dJ);
-      double fJ;
-      if constexpr (ENERGY == 1) fJ = 0.5 * gw - log(dd);
-      else fJ = 0.5 * (gw + static_cast<double>(adj_norm2<D, R>(J)) / (dd * dd));
-      part[3] = wd * fJ;
-    } else {
-      part[5] = 1.0;
-    }
     part[4] = wd * fP + 0.5 * mud * (res2 - lam2);
     part[6] = finite ? 0.0 : 1.0;
-    part[7] = gw;
     part[8] = p2;
   }
   block_reduce_store<kNumPartials>(part, partials + static_cast<int64_t>(blockIdx.x) * kNumPartials);

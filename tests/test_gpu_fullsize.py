@@ -1,0 +1,90 @@
+"""Full-size checks on the benchmark workload (twisted tet cube, 1,572,864 tets,
+float32 element steps), in the launch configuration the benchmark times.  The
+oracle cannot run this size end to end, so it checks sampled elements one by
+one and properties that hold at any size."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2107_05200_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def cube64(gpu_lib):
+    import torch
+    from paper_2107_05200_amd.binding import Solver
+    w = mg.twisted_cube(64)
+    say(f"case: full-size {w.name} m={w.m}")
+    s = Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32)
+    s.init(w.x0).iterate(3)
+    st3 = {k: v.cpu().numpy() for k, v in s.get_state().items()}
+    s.iterate(1)
+    st4 = {k: v.cpu().numpy() for k, v in s.get_state().items()}
+    torch.cuda.synchronize()
+    yield w, s, st3, st4
+    s.close()
+
+
+def test_fullsize_sampled_local_step(cube64):
+    w, s, st3, st4 = cube64
+    rng = np.random.default_rng(7)
+    sel = np.sort(rng.choice(w.m, size=3000, replace=False))
+    T = w.T[sel]
+    verts, Tl = np.unique(T, return_inverse=True)
+    Tl = Tl.reshape(T.shape)
+    B, wt = O.element_geometry(w.V[verts], Tl)
+    G = O.gradient_operator(B, Tl, len(verts))
+    J = O.jacobians(G, st4["map"][verts], 3)
+    U3 = st3["U"][sel].astype(np.float64)
+    P3 = st3["P"][sel].astype(np.float64)
+    L3 = st3["Lam"][sel].astype(np.float64)
+    A = J + L3
+    U4 = O.rot3(A @ P3)
+    At = np.transpose(U4, (0, 2, 1)) @ A
+    P4, _ = O.p_step(0.5 * (At + np.transpose(At, (0, 2, 1))), wt, w.rho * wt, w.energy)
+    L4 = L3 + J - U4 @ P4
+    eW = rel(st4["Wel"][sel], U4 @ P4)
+    eL = rel(st4["Lam"][sel], L4)
+    eU = rel(st4["U"][sel], U4)
+    say(f"  sampled local step: Wel {eW:.2e} U {eU:.2e} Lam {eL:.2e}")
+    assert eW < 1e-5 and eU < 1e-5 and eL < 1e-3
+
+
+def test_fullsize_solve_residual(cube64):
+    import torch
+    w, s, _, _ = cube64
+    order = s.vertex_order()
+    nF = w.n - len(w.pinned_idx)
+    B, wt = O.element_geometry(w.V, w.T)
+    L = O.global_matrix(O.gradient_operator(B, w.T, w.n), w.rho * wt, 3)
+    free = order[:nF]
+    LFF = L[free][:, free].tocsr()
+    b = np.random.default_rng(1).normal(size=(nF, 3))
+    x = s.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+    res = np.linalg.norm(LFF @ x - b) / np.linalg.norm(b)
+    say(f"  full-size solve residual {res:.2e}")
+    assert res < 1e-10
+
+
+def test_fullsize_invariants(cube64):
+    w, s, st3, st4 = cube64
+    h = s.history()
+    assert h.shape[0] == 4
+    assert np.all(np.isfinite(h[:, :3])) and np.all(h[:, 6] == 0)
+    d = np.linalg.det(st4["Wel"].astype(np.float64))
+    assert np.all(d > 0)
+    # pinned vertices sit at their targets
+    assert np.abs(st4["map"][w.pinned_idx] - w.pinned_pos).max() == 0.0

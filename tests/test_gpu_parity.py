@@ -27,9 +27,10 @@ def say(*a):
     sys.stdout.flush()
 
 
-def make(w, precision, h_mode=0):
+def make(w, precision, h_mode=0, leaf_size=0):
     from paper_2107_05200_amd.binding import Solver
-    return Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=precision, h_mode=h_mode)
+    return Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=precision, h_mode=h_mode,
+                  leaf_size=leaf_size)
 
 
 def oracle_for(w, h_mode=0):
@@ -89,16 +90,18 @@ CASES = {
     "cube5_sg_fp32": (lambda: mg.twisted_cube(5, energy=mg.SYMMETRIC_GRADIENT), 32, 0),
     "sphere_cap_sg_fp32": (lambda: mg.sphere_cap_uv(R=15), 32, 0),
     "disk_sd_fp64": (lambda: mg.disk_deformation(R=14), 64, 0),
+    "cube7_sd_fp32_leaf5": (lambda: mg.twisted_cube(7), 32, 0, 5),
 }
 
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_teacher_forced_steps(gpu_lib, name):
     import torch
-    mk, prec, h_mode = CASES[name]
+    mk, prec, h_mode = CASES[name][:3]
+    leaf = CASES[name][3] if len(CASES[name]) > 3 else 0
     w = mk()
     say(f"case: teacher-forced {name} m={w.m}")
-    g = make(w, prec, h_mode)
+    g = make(w, prec, h_mode, leaf)
     r = oracle_for(w, h_mode)
     npd = np.float32 if prec == 32 else np.float64
     for k in range(1, 13):
@@ -158,14 +161,15 @@ def test_free_running_fp32_energy(gpu_lib, name, mk, iters):
 # the global solve alone against a library sparse solve
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("leaf", [0, 3], ids=["leaf_auto", "leaf3"])
 @pytest.mark.parametrize("mk", [lambda: mg.height_field_uv(), lambda: mg.twisted_cube(9),
                                 lambda: mg.sphere_cap_uv(R=40)], ids=["hf", "cube9", "cap40"])
-def test_solve_matches_sparse_lu(gpu_lib, mk):
+def test_solve_matches_sparse_lu(gpu_lib, mk, leaf):
     import torch
     import scipy.sparse.linalg as spla
     w = mk()
-    say(f"case: solve {w.name}")
-    g = make(w, 64)
+    say(f"case: solve {w.name} leaf {leaf}")
+    g = make(w, 64, leaf_size=leaf)
     order = g.vertex_order()
     nF = w.n - len(w.pinned_idx)
     B, wt = O.element_geometry(w.V, w.T)
@@ -200,7 +204,7 @@ def test_bitwise_determinism_and_resume(gpu_lib):
     torch.cuda.synchronize()
     for k in sa:
         assert torch.equal(sa[k], sb[k]), k
-    assert np.array_equal(a.history(), b.history())
+    assert np.array_equal(a.history(), b.history(), equal_nan=True)
     # resume: 10 + set_state + 10 equals 20 straight
     c = make(w, 32)
     c.init(w.x0).iterate(10)
@@ -212,7 +216,7 @@ def test_bitwise_determinism_and_resume(gpu_lib):
     torch.cuda.synchronize()
     for k in ("map", "U", "P", "Lam", "Wel"):
         assert torch.equal(sd[k], sa[k]), k
-    assert np.array_equal(d.history(10, 10), a.history(10, 10))
+    assert np.array_equal(d.history(10, 10), a.history(10, 10), equal_nan=True)
 
 
 def test_state_errors(gpu_lib):

@@ -221,6 +221,23 @@ ffd_status ffd_adjoint_forward(ffd_handle h, int32_t n_iter, int32_t checkpoint_
 ffd_status ffd_adjoint_backward(ffd_handle h, const void* Pbar_dev, int32_t energy_loss, double* pins_bar_dev,
                                 double* V_bar_dev, void* stream);
 
+/* Autotuner: picks the launch shapes of the handle's kernels by timing them
+ * with HIP events on `stream` from the current state (which is saved before
+ * and restored after; the timed iterations are not recorded): the local-step
+ * block size (64 / 128 / 256 elements), the lanes per vertex row of the
+ * right-hand side (2 / 4 / 8) and, level by level for both triangular-solve
+ * passes, the task shape: blocks of four waves or one wave per task, 64 / 32 /
+ * 16 outputs per task, and inner-range splitting (none, 2048 .. 256).  With
+ * cache_path (may be NULL) the choice is read from / appended to a text file,
+ * one line per key "arch|d|energy|precision|element bucket|factor
+ * bucket|levels|h" followed by the block size, lanes per row, the level count
+ * and three numbers (mode, outputs, chunk) per level and pass.  choice_out
+ * (may be NULL): 4 int32 (block size, lanes per row, solve levels run one wave
+ * per task, solve levels with split inner ranges; both passes counted).
+ * Element results do not depend on the choice; history sums and the solve's
+ * rounding order may change in the last bits. */
+ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int32_t* choice_out);
+
 void ffd_destroy(ffd_handle h);
 
 const char* ffd_last_error(void);

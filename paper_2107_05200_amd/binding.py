@@ -72,6 +72,7 @@ _PROTOS = {
     "ffd_adjoint_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ffd_batch_create": (C.c_int, [C.POINTER(Mesh), C.POINTER(Options), C.c_int32, C.POINTER(C.c_void_p)]),
     "ffd_batch_layout": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "ffd_autotune": (C.c_int, [C.c_void_p, C.c_char_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "ffd_destroy": (None, [C.c_void_p]),
     "ffd_last_error": (C.c_char_p, []),
 }
@@ -251,6 +252,13 @@ class Solver:
         o = np.empty(self.n, dtype=np.int32)
         _check(self.lib.ffd_get_vertex_order(self.h, o.ctypes.data_as(C.POINTER(C.c_int32))))
         return o
+
+    def autotune(self, cache_path: str | None = None, stream=None) -> dict:
+        """Pick launch shapes by timing them (state saved and restored)."""
+        out = (C.c_int32 * 4)()
+        _check(self.lib.ffd_autotune(self.h, cache_path.encode() if cache_path else None, _stream(stream), out))
+        return {"local_block": out[0], "wrhs_lanes": out[1], "solve_wave_levels": out[2],
+                "solve_split_levels": out[3]}
 
     def adjoint_forward(self, n_iter: int, checkpoint_every: int = 10, stream=None):
         """n_iter iterations with checkpoints every checkpoint_every (for adjoint_backward)."""

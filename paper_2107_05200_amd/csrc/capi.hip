@@ -4,9 +4,11 @@
 //   levels -> K3 fused U/P/Lambda step -> finalize (history record).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <sstream>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -39,9 +41,19 @@ constexpr int64_t kHistCap0 = 1 << 14;
 
 inline unsigned nblk(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
-constexpr int64_t kMinLevelTasks = 1024;  // blocks a solve level should offer before its inner ranges are split
 
 }  // namespace
+
+// Launch configuration of one solve level of one pass: mode 0 = blocks of
+// four waves per task, 1 = one wave per task; opt = outputs per task (64, 32,
+// 16); chunk > 0 splits inner ranges longer than chunk (block mode only).
+struct LevelCfg {
+  int32_t mode = 0, opt = 64, chunk = 0;
+  bool operator==(const LevelCfg& o) const { return mode == o.mode && opt == o.opt && chunk == o.chunk; }
+};
+struct LevelRun {
+  int32_t mode = 0, opt = 64, t0 = 0, nt = 0, r0 = 0, nr = 0;  // tasks [t0, t0+nt), reductions [r0, r0+nr)
+};
 
 struct ffd_ctx {
   int d = 0, din = 0, prec = 32, energy = 0, h_mode = 0;
@@ -56,6 +68,11 @@ struct ffd_ctx {
   };
   std::vector<Seg> segs;
   std::vector<int64_t> voff, eoff;  // batch layout: vertex / element offsets per mesh (empty: one mesh)
+  // launch shapes (chosen by ffd_autotune)
+  int local_bs = 256;              // threads per block of the local step
+  int wrhs_lpr = 4;                // lanes per vertex row of the right-hand side
+  std::vector<SolveNode> hnodes;   // host copies for rebuilding the solve schedule
+  std::vector<std::vector<int32_t>> hlevels;
   int64_t nparts = 0;     // partial-sum blocks of one local step
   int cur = 0;            // index of the buffer holding W^k
   int dev = 0;
@@ -63,7 +80,6 @@ struct ffd_ctx {
   ffd_info info{};
   // host copies
   std::vector<int32_t> vnew2old;
-  std::vector<int32_t> level_fwd_off, level_bwd_off;  // main task offsets per level (size nlev + 1)
   // device buffers
   int32_t *T = nullptr, *vnew2old_d = nullptr, *enew2old_d = nullptr;
   double* B64 = nullptr;
@@ -71,14 +87,17 @@ struct ffd_ctx {
   double *x[2] = {nullptr, nullptr}, *xC = nullptr;
   void *U = nullptr, *P = nullptr, *L = nullptr, *gn = nullptr, *g = nullptr;
   double *b = nullptr, *y = nullptr, *ub = nullptr, *partials = nullptr, *hist = nullptr;
+  double* partials2 = nullptr;  // first-stage sums of the partials (many local-step blocks)
   int64_t hist_cap = 0;
   int32_t *dt_ptr = nullptr, *dt_idx = nullptr, *pin_ptr = nullptr, *pin_col = nullptr;
   double* pin_val = nullptr;
-  NodeDev* nodes = nullptr;
+  std::vector<int64_t> hpoff;  // device panel offset of every node
+  std::vector<LevelCfg> cfg_fwd, cfg_bwd;  // per-level launch configuration of both solve passes
+  std::vector<LevelRun> run_fwd, run_bwd;  // per-level task ranges built from them
   double *Prow = nullptr, *Pcol = nullptr;  // factor panels, row- and column-major copies
   int32_t *sidx = nullptr, *pull_ptr = nullptr, *pull_idx = nullptr;
   SolveTask *tasks_fwd = nullptr, *tasks_bwd = nullptr, *red_fwd = nullptr, *red_bwd = nullptr;
-  std::vector<int32_t> red_fwd_off, red_bwd_off;  // reduction task offsets per level
+  size_t cap_tf = 0, cap_tb = 0, cap_rf = 0, cap_rb = 0, cap_slots = 0;  // capacities (entries)
   double* solve_part = nullptr;                   // split-K partials (reused level by level)
   int64_t device_bytes = 0;
   std::vector<void*> allocs;
@@ -160,51 +179,102 @@ void launch_prepare(ffd_ctx* h, const ffd_ctx::Seg& g, hipStream_t s) {
                      static_cast<R*>(h->gn), static_cast<R*>(h->g));
 }
 
+template <int D, typename R, int E, int BS>
+void launch_local_bs(ffd_ctx* h, const ffd_ctx::Seg& g, const double* xnew, const double* xold, int store_u,
+                     hipStream_t s) {
+  hipLaunchKernelGGL((k_local<D, R, E, BS>), dim3(static_cast<unsigned>((g.e1 - g.e0 + BS - 1) / BS)), dim3(BS), 0, s,
+                     h->m, g.e0, g.e1, h->T, static_cast<const R*>(h->B), static_cast<const R*>(h->w),
+                     static_cast<R>(h->rho), h->h_mode, store_u, xnew, xold, static_cast<R*>(h->U),
+                     static_cast<R*>(h->P), static_cast<R*>(h->L), static_cast<R*>(h->gn), static_cast<R*>(h->g),
+                     h->partials + g.pb0 * kNumPartials);
+}
+
 template <int D, typename R, int E>
 void launch_local(ffd_ctx* h, const ffd_ctx::Seg& g, const double* xnew, const double* xold, int store_u,
                   hipStream_t s) {
-  hipLaunchKernelGGL((k_local<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1, h->T,
-                     static_cast<const R*>(h->B), static_cast<const R*>(h->w), static_cast<R>(h->rho), h->h_mode,
-                     store_u, xnew,
-                     xold, static_cast<R*>(h->U), static_cast<R*>(h->P), static_cast<R*>(h->L), static_cast<R*>(h->gn),
-                     static_cast<R*>(h->g), h->partials + g.pb0 * kNumPartials);
+  if (h->local_bs == 64) launch_local_bs<D, R, E, 64>(h, g, xnew, xold, store_u, s);
+  else if (h->local_bs == 128) launch_local_bs<D, R, E, 128>(h, g, xnew, xold, store_u, s);
+  else launch_local_bs<D, R, E, 256>(h, g, xnew, xold, store_u, s);
+}
+
+// partial-sum block offsets of the energy ranges for the local-step block size
+void set_local_block(ffd_ctx* h, int bs) {
+  h->local_bs = bs;
+  int64_t pb = 0;
+  for (auto& g : h->segs) {
+    g.pb0 = pb;
+    pb += (g.e1 - g.e0 + bs - 1) / bs;
+  }
+  h->nparts = pb;
+}
+
+template <int D, typename R, int LPR>
+void launch_wrhs_l(ffd_ctx* h, double* xnew, hipStream_t s) {
+  hipLaunchKernelGGL((k_wrhs<D, R, LPR>), dim3(nblk(LPR * h->n)), dim3(kBlock), 0, s, h->nF, h->n, h->dt_ptr,
+                     h->dt_idx, static_cast<const R*>(h->g), h->pin_ptr, h->pin_col, h->pin_val, h->xC, h->b, xnew);
 }
 
 template <int D, typename R>
 void launch_wrhs(ffd_ctx* h, double* xnew, hipStream_t s) {
-  hipLaunchKernelGGL((k_wrhs<D, R>), dim3(nblk(4 * h->n)), dim3(kBlock), 0, s, h->nF, h->n, h->dt_ptr, h->dt_idx,
-                     static_cast<const R*>(h->g), h->pin_ptr, h->pin_col, h->pin_val, h->xC, h->b, xnew);
+  if (h->wrhs_lpr == 2) launch_wrhs_l<D, R, 2>(h, xnew, s);
+  else if (h->wrhs_lpr == 8) launch_wrhs_l<D, R, 8>(h, xnew, s);
+  else launch_wrhs_l<D, R, 4>(h, xnew, s);
+}
+
+template <int D, int OPT>
+void launch_fwd_opt(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, const double* b, hipStream_t s) {
+  if (r.mode == 1)
+    hipLaunchKernelGGL((k_solve_fwd_wave<D, OPT>), dim3((r.nt + 3) / 4), dim3(kBlock), 0, s, tasks, r.nt, h->Pcol,
+                       h->pull_ptr, h->pull_idx, b, h->y, h->ub);
+  else
+    hipLaunchKernelGGL((k_solve_fwd<D, OPT>), dim3(r.nt), dim3(kBlock), 0, s, tasks, h->Pcol, h->pull_ptr,
+                       h->pull_idx, b, h->y, h->ub, h->solve_part);
+}
+
+template <int D, int OPT>
+void launch_bwd_opt(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, double* x, hipStream_t s) {
+  if (r.mode == 1)
+    hipLaunchKernelGGL((k_solve_bwd_wave<D, OPT>), dim3((r.nt + 3) / 4), dim3(kBlock), 0, s, tasks, r.nt, h->Prow,
+                       h->sidx, h->y, x);
+  else
+    hipLaunchKernelGGL((k_solve_bwd<D, OPT>), dim3(r.nt), dim3(kBlock), 0, s, tasks, h->Prow, h->sidx, h->y, x,
+                       h->solve_part);
+}
+
+template <int D>
+void launch_fwd_level(ffd_ctx* h, const LevelRun& r, const double* b, hipStream_t s) {
+  const SolveTask* tasks = h->tasks_fwd + r.t0;
+  if (r.nt > 0) {
+    if (r.opt == 16) launch_fwd_opt<D, 16>(h, r, tasks, b, s);
+    else if (r.opt == 32) launch_fwd_opt<D, 32>(h, r, tasks, b, s);
+    else launch_fwd_opt<D, 64>(h, r, tasks, b, s);
+  }
+  if (r.nr > 0)
+    hipLaunchKernelGGL((k_solve_fwd_reduce<D>), dim3((r.nr + 3) / 4), dim3(kBlock), 0, s, h->red_fwd + r.r0, r.nr,
+                       h->pull_ptr, h->pull_idx, h->y, h->ub, h->solve_part);
+}
+
+template <int D>
+void launch_bwd_level(ffd_ctx* h, const LevelRun& r, double* x, hipStream_t s) {
+  const SolveTask* tasks = h->tasks_bwd + r.t0;
+  if (r.nt > 0) {
+    if (r.opt == 16) launch_bwd_opt<D, 16>(h, r, tasks, x, s);
+    else if (r.opt == 32) launch_bwd_opt<D, 32>(h, r, tasks, x, s);
+    else launch_bwd_opt<D, 64>(h, r, tasks, x, s);
+  }
+  if (r.nr > 0)
+    hipLaunchKernelGGL((k_solve_bwd_reduce<D>), dim3((r.nr + 3) / 4), dim3(kBlock), 0, s, h->red_bwd + r.r0, r.nr, x,
+                       h->solve_part);
 }
 
 template <int D>
 void launch_solve_fwd(ffd_ctx* h, const double* b, hipStream_t s) {
-  const int nlev = static_cast<int>(h->level_fwd_off.size()) - 1;
-  for (int l = 0; l < nlev; ++l) {
-    const int nt = h->level_fwd_off[l + 1] - h->level_fwd_off[l];
-    if (nt > 0)
-      hipLaunchKernelGGL((k_solve_fwd<D>), dim3(nt), dim3(kBlock), 0, s, h->tasks_fwd + h->level_fwd_off[l], h->nodes,
-                         h->Pcol, h->pull_ptr, h->pull_idx, b, h->y, h->ub, h->solve_part);
-    const int nr = h->red_fwd_off[l + 1] - h->red_fwd_off[l];
-    if (nr > 0)
-      hipLaunchKernelGGL((k_solve_fwd_reduce<D>), dim3((nr + 3) / 4), dim3(kBlock), 0, s,
-                         h->red_fwd + h->red_fwd_off[l], nr, h->nodes, h->pull_ptr, h->pull_idx, h->y, h->ub,
-                         h->solve_part);
-  }
+  for (const LevelRun& r : h->run_fwd) launch_fwd_level<D>(h, r, b, s);
 }
 
 template <int D>
 void launch_solve_bwd(ffd_ctx* h, double* x, hipStream_t s) {
-  const int nlev = static_cast<int>(h->level_fwd_off.size()) - 1;
-  for (int l = nlev - 1; l >= 0; --l) {
-    const int nt = h->level_bwd_off[l + 1] - h->level_bwd_off[l];
-    if (nt > 0)
-      hipLaunchKernelGGL((k_solve_bwd<D>), dim3(nt), dim3(kBlock), 0, s, h->tasks_bwd + h->level_bwd_off[l], h->nodes,
-                         h->Prow, h->sidx, h->y, x, h->solve_part);
-    const int nr = h->red_bwd_off[l + 1] - h->red_bwd_off[l];
-    if (nr > 0)
-      hipLaunchKernelGGL((k_solve_bwd_reduce<D>), dim3((nr + 3) / 4), dim3(kBlock), 0, s,
-                         h->red_bwd + h->red_bwd_off[l], nr, h->nodes, x, h->solve_part);
-  }
+  for (auto it = h->run_bwd.rbegin(); it != h->run_bwd.rend(); ++it) launch_bwd_level<D>(h, *it, x, s);
 }
 
 template <int D>
@@ -275,11 +345,167 @@ void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true
   if (ev) (void)hipEventRecord(ev[2], s);
   do_local(h, xnew, xold, store_u ? 1 : 0, s);
   if (ev) (void)hipEventRecord(ev[3], s);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials, h->nparts,
-                     record ? h->hist + h->k * FFD_HIST_FIELDS : h->hist_scratch);
+  double* rec = record ? h->hist + h->k * FFD_HIST_FIELDS : h->hist_scratch;
+  if (h->nparts > 2 * kFinalizeRows) {
+    const int64_t nb2 = (h->nparts + kFinalizeRows - 1) / kFinalizeRows;
+    hipLaunchKernelGGL(k_partials_reduce, dim3(static_cast<unsigned>(nb2)), dim3(kBlock), 0, s, h->partials,
+                       h->nparts, h->partials2);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials2, nb2, rec);
+  } else {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials, h->nparts, rec);
+  }
   if (ev) (void)hipEventRecord(ev[4], s);
   h->cur = 1 - h->cur;
   if (record) h->k += 1;
+}
+
+// Output blocks of one level of one pass: (node, first output, inner range).
+struct OutBlock {
+  int32_t node, out0, lo, hi;
+};
+
+std::vector<OutBlock> level_blocks(const ffd_ctx* h, const std::vector<int32_t>& lvl, bool fwd, int opt) {
+  std::vector<OutBlock> obs;
+  for (int32_t i : lvl) {
+    const SolveNode& N = h->hnodes[i];
+    const int nf = N.c + N.r;
+    if (fwd) {
+      for (int o0 = 0; o0 < nf; o0 += opt) obs.push_back(OutBlock{i, o0, 0, std::min(N.c, o0 + opt)});
+    } else {
+      for (int o0 = 0; o0 < N.c; o0 += opt) obs.push_back(OutBlock{i, o0, o0, nf});
+    }
+  }
+  // longest inner ranges first: the blocks that take longest start first
+  std::stable_sort(obs.begin(), obs.end(),
+                   [](const OutBlock& a, const OutBlock& b) { return a.hi - a.lo > b.hi - b.lo; });
+  return obs;
+}
+
+// Default configuration of a level: four-wave blocks of 64 outputs; a level
+// with fewer than 512 blocks splits inner ranges into the largest chunks
+// (4096 .. 256) that give it 512 tasks.
+LevelCfg default_level_cfg(const ffd_ctx* h, const std::vector<int32_t>& lvl, bool fwd) {
+  constexpr int64_t kMinTasks = 512;
+  LevelCfg c;
+  const std::vector<OutBlock> obs = level_blocks(h, lvl, fwd, 64);
+  if (static_cast<int64_t>(obs.size()) >= kMinTasks) return c;
+  c.chunk = 256;
+  for (int64_t kc = 4096; kc >= 256; kc /= 2) {
+    int64_t nt = 0;
+    for (const OutBlock& o : obs) nt += (o.hi - o.lo + kc - 1) / kc;
+    if (nt >= kMinTasks) {
+      c.chunk = static_cast<int32_t>(kc);
+      break;
+    }
+  }
+  return c;
+}
+
+template <typename T_>
+hipError_t upload_cap(ffd_ctx* h, T_** dst, size_t* cap, const std::vector<T_>& src) {
+  if (src.size() > *cap) {
+    if (*dst) {
+      for (auto& a : h->allocs)
+        if (a == *dst) a = nullptr;
+      (void)hipFree(*dst);
+      *dst = nullptr;
+    }
+    const size_t n = src.size() + src.size() / 4 + 16;
+    hipError_t e = h->alloc(dst, n);
+    if (e != hipSuccess) {
+      *cap = 0;
+      return e;
+    }
+    *cap = n;
+  }
+  if (src.empty()) return hipSuccess;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T_), hipMemcpyHostToDevice);
+}
+
+// Builds the task lists of both passes from cfg_fwd / cfg_bwd (defaults for
+// levels without one) and uploads them.  Waits for the device first: the
+// task buffers may be in use by earlier launches.
+ffd_status build_solve_schedule(ffd_ctx* h) {
+  const size_t nlev = h->hlevels.size();
+  if (h->cfg_fwd.size() != nlev || h->cfg_bwd.size() != nlev) {
+    h->cfg_fwd.resize(nlev);
+    h->cfg_bwd.resize(nlev);
+    for (size_t l = 0; l < nlev; ++l) {
+      h->cfg_fwd[l] = default_level_cfg(h, h->hlevels[l], true);
+      h->cfg_bwd[l] = default_level_cfg(h, h->hlevels[l], false);
+    }
+  }
+  std::vector<SolveTask> tf, tb, rf, rb;
+  int64_t max_slots = 1;
+  h->run_fwd.assign(nlev, LevelRun{});
+  h->run_bwd.assign(nlev, LevelRun{});
+  auto task_of = [&](const OutBlock& o, bool fwd, int32_t lo, int32_t hi, int32_t slot, int32_t nk) {
+    const SolveNode& N = h->hnodes[o.node];
+    const int32_t nf = N.c + N.r;
+    SolveTask t{};
+    t.pf = h->hpoff[o.node];
+    t.poff = N.poff;
+    t.uoff = N.uoff;
+    t.soff = N.soff;
+    t.ld = fwd ? ((nf + 1) & ~1) : ((N.c + 1) & ~1);
+    t.first = N.first;
+    t.c = N.c;
+    t.nf = nf;
+    t.out0 = o.out0;
+    t.lo = lo;
+    t.hi = hi;
+    t.slot = slot;
+    t.nk = nk;
+    return t;
+  };
+  auto build = [&](size_t l, bool fwd, const LevelCfg& cfg, std::vector<SolveTask>& tasks,
+                   std::vector<SolveTask>& red, LevelRun& run) {
+    const std::vector<OutBlock> obs = level_blocks(h, h->hlevels[l], fwd, cfg.opt);
+    run.mode = cfg.mode;
+    run.opt = cfg.opt;
+    run.t0 = static_cast<int32_t>(tasks.size());
+    run.r0 = static_cast<int32_t>(red.size());
+    int32_t slots = 0;
+    for (const OutBlock& o : obs) {
+      const int64_t len = o.hi - o.lo;
+      const int32_t nk = (cfg.mode == 0 && cfg.chunk > 0) ? static_cast<int32_t>((len + cfg.chunk - 1) / cfg.chunk) : 1;
+      if (nk <= 1) {
+        tasks.push_back(task_of(o, fwd, o.lo, o.hi, -1, 1));
+        continue;
+      }
+      const int32_t base = slots;
+      slots += nk;
+      for (int32_t q = 0; q < nk; ++q)
+        tasks.push_back(task_of(o, fwd, static_cast<int32_t>(o.lo + q * cfg.chunk),
+                                static_cast<int32_t>(std::min<int64_t>(o.hi, o.lo + static_cast<int64_t>(q + 1) * cfg.chunk)),
+                                base + q, nk));
+      red.push_back(task_of(o, fwd, 0, cfg.opt, base, nk));  // hi: outputs of the block
+    }
+    run.nt = static_cast<int32_t>(tasks.size()) - run.t0;
+    run.nr = static_cast<int32_t>(red.size()) - run.r0;
+    max_slots = std::max<int64_t>(max_slots, slots);
+  };
+  for (size_t l = 0; l < nlev; ++l) {
+    build(l, true, h->cfg_fwd[l], tf, rf, h->run_fwd[l]);
+    build(l, false, h->cfg_bwd[l], tb, rb, h->run_bwd[l]);
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return fail(FFD_ERR_DEVICE, "device error before a schedule upload");
+  bool ok = upload_cap(h, &h->tasks_fwd, &h->cap_tf, tf) == hipSuccess &&
+            upload_cap(h, &h->tasks_bwd, &h->cap_tb, tb) == hipSuccess &&
+            upload_cap(h, &h->red_fwd, &h->cap_rf, rf) == hipSuccess &&
+            upload_cap(h, &h->red_bwd, &h->cap_rb, rb) == hipSuccess;
+  if (ok && static_cast<size_t>(max_slots) > h->cap_slots) {
+    if (h->solve_part) {
+      for (auto& a : h->allocs)
+        if (a == h->solve_part) a = nullptr;
+      (void)hipFree(h->solve_part);
+      h->solve_part = nullptr;
+    }
+    ok = h->alloc(&h->solve_part, static_cast<size_t>(max_slots) * kSolveOutMax * h->d) == hipSuccess;
+    h->cap_slots = ok ? static_cast<size_t>(max_slots) : 0;
+  }
+  if (!ok) return fail(FFD_ERR_OUT_OF_MEMORY, "solve schedule upload failed");
+  return FFD_OK;
 }
 
 ffd_status ensure_hist(ffd_ctx* h, int64_t need, hipStream_t s) {
@@ -395,6 +621,8 @@ extern "C" {
 
 const char* ffd_last_error(void) { return g_last_error.c_str(); }
 
+}  // extern "C"
+
 namespace {
 
 // shared by ffd_create and ffd_batch_create: mesh is the (concatenated) mesh,
@@ -504,14 +732,12 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
       if (S.m_energy0 > 0) h->segs.push_back(ffd_ctx::Seg{0, S.m_energy0, 0, 0});
       if (S.m_energy0 < m) h->segs.push_back(ffd_ctx::Seg{S.m_energy0, m, 1, 0});
     }
-    int64_t pb = 0;
-    for (auto& g : h->segs) {
-      g.pb0 = pb;
-      pb += nblk(g.e1 - g.e0);
-    }
-    h->nparts = pb;
+    int64_t pmax = 0;
+    for (auto& g : h->segs) pmax += (g.e1 - g.e0 + 63) / 64;
+    set_local_block(h, 256);
+    UP(h->alloc(&h->partials, static_cast<size_t>(std::max<int64_t>(pmax, 1)) * kNumPartials));
+    UP(h->alloc(&h->partials2, static_cast<size_t>((pmax + kFinalizeRows - 1) / kFinalizeRows + 1) * kNumPartials));
   }
-  UP(h->alloc(&h->partials, static_cast<size_t>(std::max<int64_t>(h->nparts, 1)) * kNumPartials));
   UP(upload(h, &h->dt_ptr, S.dt_ptr));
   UP(upload(h, &h->dt_idx, S.dt_idx));
   UP(upload(h, &h->pin_ptr, S.pin_ptr));
@@ -532,77 +758,10 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
     std::vector<double>().swap(prow);
     UP(upload(h, &h->Pcol, pcol));
     std::vector<double>().swap(pcol);
-    std::vector<NodeDev> nd(S.nodes.size());
-    for (size_t i = 0; i < S.nodes.size(); ++i) {
-      const SolveNode& N = S.nodes[i];
-      nd[i] = NodeDev{N.first, N.c, N.r, 0, poff[i], N.uoff, N.soff, N.poff};
-    }
-    UP(upload(h, &h->nodes, nd));
-    std::vector<SolveTask> tf, tb, rf, rb;
-    int32_t max_slots = 1;
-    h->level_fwd_off.push_back(0);
-    h->level_bwd_off.push_back(0);
-    h->red_fwd_off.push_back(0);
-    h->red_bwd_off.push_back(0);
-    // Output blocks of a level: (node, out0, inner lo, inner hi).  A level with
-    // few output blocks splits their inner ranges into chunks (the largest
-    // chunk that still gives kMinLevelTasks blocks), reduced by a second
-    // launch; other levels run one task per output block.
-    struct OB {
-      int32_t node, out0, lo, hi;
-    };
-    auto schedule = [&](const std::vector<OB>& obs, std::vector<SolveTask>& tasks, std::vector<SolveTask>& red,
-                        int32_t& slots) {
-      int64_t chunk = 0;  // 0: no split
-      if (static_cast<int64_t>(obs.size()) < kMinLevelTasks) {
-        chunk = kSolveKC;
-        for (int64_t kc = 8 * kSolveKC; kc >= kSolveKC; kc /= 2) {
-          int64_t nt = 0;
-          for (const OB& o : obs) nt += (o.hi - o.lo + kc - 1) / kc;
-          if (nt >= kMinLevelTasks) {
-            chunk = kc;
-            break;
-          }
-        }
-      }
-      for (const OB& o : obs) {
-        const int64_t len = o.hi - o.lo;
-        const int32_t nk = chunk > 0 ? static_cast<int32_t>((len + chunk - 1) / chunk) : 1;
-        if (nk == 1) {
-          tasks.push_back(SolveTask{o.node, o.out0, o.lo, o.hi, -1, 1});
-          continue;
-        }
-        const int32_t base = slots;
-        slots += nk;
-        for (int32_t q = 0; q < nk; ++q)
-          tasks.push_back(SolveTask{o.node, o.out0, static_cast<int32_t>(o.lo + q * chunk),
-                                    static_cast<int32_t>(std::min<int64_t>(o.hi, o.lo + (q + 1) * chunk)), base + q,
-                                    nk});
-        red.push_back(SolveTask{o.node, o.out0, 0, 0, base, nk});
-      }
-    };
-    for (const auto& lvl : S.level_nodes) {
-      std::vector<OB> of, ob;
-      for (int32_t i : lvl) {
-        const SolveNode& N = S.nodes[i];
-        const int nf = N.c + N.r;
-        for (int o0 = 0; o0 < nf; o0 += kSolveRT) of.push_back(OB{i, o0, 0, std::min(N.c, o0 + kSolveRT)});
-        for (int o0 = 0; o0 < N.c; o0 += kSolveRT) ob.push_back(OB{i, o0, o0, nf});
-      }
-      int32_t sf = 0, sb = 0;  // partial slots of this level (reused by the next)
-      schedule(of, tf, rf, sf);
-      schedule(ob, tb, rb, sb);
-      max_slots = std::max(max_slots, std::max(sf, sb));
-      h->level_fwd_off.push_back(static_cast<int32_t>(tf.size()));
-      h->level_bwd_off.push_back(static_cast<int32_t>(tb.size()));
-      h->red_fwd_off.push_back(static_cast<int32_t>(rf.size()));
-      h->red_bwd_off.push_back(static_cast<int32_t>(rb.size()));
-    }
-    UP(upload(h, &h->red_fwd, rf));
-    UP(upload(h, &h->red_bwd, rb));
-    UP(h->alloc(&h->solve_part, static_cast<size_t>(max_slots) * kSolveRT * d));
-    UP(upload(h, &h->tasks_fwd, tf));
-    UP(upload(h, &h->tasks_bwd, tb));
+    h->hpoff = poff;
+    h->hnodes = S.nodes;
+    h->hlevels = S.level_nodes;
+    if (build_solve_schedule(h) != FFD_OK) return cleanup(FFD_ERR_OUT_OF_MEMORY);
   }
   UP(upload(h, &h->sidx, S.struct_idx));
   UP(upload(h, &h->pull_ptr, S.pull_ptr));
@@ -629,6 +788,7 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
 }
 
 }  // namespace
+extern "C" {
 
 ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* out) {
   if (!mesh || !opt || !out) return fail(FFD_ERR_INVALID_ARG, "NULL argument");
@@ -1040,6 +1200,223 @@ ffd_status ffd_adjoint_backward(ffd_handle h, const void* Pbar_dev, int32_t ener
     HIP_TRY(hipMemcpyAsync(pins_bar_dev, h->pinsbar, sizeof(double) * h->nC * d, hipMemcpyDeviceToDevice, s));
   HIP_TRY(load_state(h, h->adj_fin, s));
   HIP_TRY(hipGetLastError());
+  h->last_stream = s;
+  return FFD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// time `iters` iterations (not recorded) and return the summed milliseconds of
+// phase `phase` (0 right-hand side, 1+2 solve, 3 local step)
+double time_phase(ffd_ctx* h, hipStream_t s, int phase, int iters) {
+  const size_t need = static_cast<size_t>(iters) * 5 + 1;
+  while (h->events.size() < need) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return 1e30;
+    h->events.push_back(ev);
+  }
+  for (int it = 0; it < 2; ++it) one_iteration(h, s, nullptr, false, true);
+  (void)hipEventRecord(h->events[0], s);
+  for (int it = 0; it < iters; ++it) one_iteration(h, s, h->events.data() + 1 + static_cast<size_t>(it) * 5, false, true);
+  if (hipEventSynchronize(h->events[need - 1]) != hipSuccess) return 1e30;
+  double tot = 0.0;
+  for (int it = 0; it < iters; ++it)
+    for (int p = 0; p < 5; ++p) {
+      const bool want = phase == 1 ? (p == 1 || p == 2) : p == phase;
+      if (!want) continue;
+      float ms = 0.f;
+      const size_t i = 1 + static_cast<size_t>(it) * 5 + p;
+      (void)hipEventElapsedTime(&ms, h->events[i - 1], h->events[i]);
+      tot += ms;
+    }
+  return tot;
+}
+
+// milliseconds of one forward (or backward) solve pass on the current
+// right-hand side, the smallest of `reps` timed passes after one untimed one
+double time_solve_pass(ffd_ctx* h, hipStream_t s, bool fwd, int reps) {
+  while (h->events.size() < 2) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return 1e30;
+    h->events.push_back(ev);
+  }
+  double* xs = h->x[1 - h->cur];
+  double best = 1e30;
+  for (int r = 0; r <= reps; ++r) {
+    (void)hipEventRecord(h->events[0], s);
+    if (fwd) {
+      if (h->d == 2) launch_solve_fwd<2>(h, h->b, s);
+      else launch_solve_fwd<3>(h, h->b, s);
+    } else {
+      if (h->d == 2) launch_solve_bwd<2>(h, xs, s);
+      else launch_solve_bwd<3>(h, xs, s);
+    }
+    (void)hipEventRecord(h->events[1], s);
+    if (hipEventSynchronize(h->events[1]) != hipSuccess) return 1e30;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, h->events[0], h->events[1]);
+    if (r > 0) best = std::min(best, static_cast<double>(ms));
+  }
+  return best;
+}
+
+std::string tune_key(ffd_ctx* h) {
+  hipDeviceProp_t prop;
+  std::string arch = hipGetDeviceProperties(&prop, h->dev) == hipSuccess ? prop.gcnArchName : "unknown";
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  int64_t mb = 1, nb = 1;
+  while (mb < h->m) mb *= 2;
+  while (nb < h->info.factor_nnz) nb *= 2;
+  std::string energy = h->segs.size() > 1 ? "mixed" : std::to_string(h->segs.empty() ? 0 : h->segs[0].energy);
+  return arch + "|d" + std::to_string(h->d) + "|e" + energy + "|p" + std::to_string(h->prec) + "|m" +
+         std::to_string(mb) + "|nnz" + std::to_string(nb) + "|lv" + std::to_string(h->hlevels.size()) + "|h" +
+         std::to_string(h->h_mode);
+}
+
+}  // namespace
+extern "C" {
+
+ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int32_t* choice_out) {
+  if (!h) return fail(FFD_ERR_INVALID_ARG, "NULL handle");
+  if (!h->initialized) return fail(FFD_ERR_STATE, "ffd_autotune before ffd_init / ffd_set_state");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const std::string key = tune_key(h);
+  const size_t nlev = h->hlevels.size();
+  int bs = 0, lpr = 0;
+  std::vector<LevelCfg> cf, cb;
+  bool cached = false;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      std::string line;
+      char buf[4096];
+      while (std::fgets(buf, sizeof buf, f)) {
+        line += buf;
+        if (line.empty() || line.back() != '\n') continue;  // a line longer than the buffer
+        std::istringstream in(line);
+        line.clear();
+        std::string k;
+        int b2 = 0, l2 = 0;
+        size_t n2 = 0;
+        if (!(in >> k >> b2 >> l2 >> n2) || k != key || n2 != nlev) continue;
+        std::vector<LevelCfg> f2(nlev), g2(nlev);
+        bool good = true;
+        for (size_t l = 0; l < nlev && good; ++l) good = static_cast<bool>(in >> f2[l].mode >> f2[l].opt >> f2[l].chunk);
+        for (size_t l = 0; l < nlev && good; ++l) good = static_cast<bool>(in >> g2[l].mode >> g2[l].opt >> g2[l].chunk);
+        if (!good) continue;
+        bs = b2;
+        lpr = l2;
+        cf = f2;
+        cb = g2;
+        cached = true;
+      }
+      std::fclose(f);
+    }
+  }
+  // a configuration read from a file is checked before use
+  auto valid = [](const LevelCfg& c) {
+    return (c.mode == 0 || c.mode == 1) && (c.opt == 16 || c.opt == 32 || c.opt == 64) && c.chunk >= 0 &&
+           (c.mode == 0 || c.chunk == 0);
+  };
+  for (size_t l = 0; l < cf.size() && cached; ++l) cached = valid(cf[l]) && valid(cb[l]);
+  if (!cached) {
+    // coordinate search with the state saved and restored around it; the
+    // timed iterations are not recorded in the history
+    if (!h->adj_fin) HIP_TRY(h->alloc(&h->adj_fin, h->slot_bytes()));
+    HIP_TRY(save_state(h, h->adj_fin, s));
+    const int iters = 6;
+    double best = 1e300;
+    for (int cand : {256, 128, 64}) {
+      set_local_block(h, cand);
+      const double t = time_phase(h, s, 3, iters);
+      if (t < best) {
+        best = t;
+        bs = cand;
+      }
+    }
+    set_local_block(h, bs);
+    best = 1e300;
+    for (int cand : {4, 2, 8}) {
+      h->wrhs_lpr = cand;
+      const double t = time_phase(h, s, 0, iters);
+      if (t < best) {
+        best = t;
+        lpr = cand;
+      }
+    }
+    h->wrhs_lpr = lpr;
+    // solve levels one at a time, both passes, from the default schedule
+    h->cfg_fwd.clear();
+    h->cfg_bwd.clear();
+    ffd_status st = build_solve_schedule(h);
+    if (st != FFD_OK) return st;
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<LevelCfg>& cfg = pass == 0 ? h->cfg_fwd : h->cfg_bwd;
+      double tcur = time_solve_pass(h, s, pass == 0, 3);
+      for (size_t l = 0; l < nlev; ++l) {
+        int64_t max_inner = 0;
+        for (const OutBlock& o : level_blocks(h, h->hlevels[l], pass == 0, 64))
+          max_inner = std::max<int64_t>(max_inner, o.hi - o.lo);
+        std::vector<LevelCfg> cands;
+        for (int opt : {64, 32, 16}) {
+          if (max_inner <= 1024) cands.push_back(LevelCfg{1, opt, 0});
+          for (int chunk : {0, 2048, 1024, 512, 256})
+            if (chunk == 0 || chunk < max_inner) cands.push_back(LevelCfg{0, opt, chunk});
+        }
+        const LevelCfg keep = cfg[l];
+        LevelCfg bestc = keep;
+        for (const LevelCfg& c : cands) {
+          if (c == keep) continue;
+          cfg[l] = c;
+          st = build_solve_schedule(h);
+          if (st != FFD_OK) return st;
+          const double t = time_solve_pass(h, s, pass == 0, 3);
+          if (t < tcur) {
+            tcur = t;
+            bestc = c;
+          }
+        }
+        cfg[l] = bestc;
+      }
+    }
+    cf = h->cfg_fwd;
+    cb = h->cfg_bwd;
+    st = build_solve_schedule(h);
+    if (st != FFD_OK) return st;
+    HIP_TRY(load_state(h, h->adj_fin, s));
+    if (cache_path) {
+      if (FILE* f = std::fopen(cache_path, "a")) {
+        std::fprintf(f, "%s %d %d %zu", key.c_str(), bs, lpr, nlev);
+        for (const LevelCfg& c : cf) std::fprintf(f, " %d %d %d", c.mode, c.opt, c.chunk);
+        for (const LevelCfg& c : cb) std::fprintf(f, " %d %d %d", c.mode, c.opt, c.chunk);
+        std::fprintf(f, "\n");
+        std::fclose(f);
+      }
+    }
+  }
+  if (bs != 64 && bs != 128 && bs != 256) bs = 256;
+  if (lpr != 2 && lpr != 4 && lpr != 8) lpr = 4;
+  set_local_block(h, bs);
+  h->wrhs_lpr = lpr;
+  h->cfg_fwd = cf;
+  h->cfg_bwd = cb;
+  ffd_status st = build_solve_schedule(h);
+  if (st != FFD_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  if (choice_out) {
+    int32_t wave = 0, split = 0;
+    for (const auto* v : {&cf, &cb})
+      for (const LevelCfg& c : *v) {
+        wave += c.mode == 1;
+        split += c.chunk > 0;
+      }
+    choice_out[0] = bs;
+    choice_out[1] = lpr;
+    choice_out[2] = wave;
+    choice_out[3] = split;
+  }
   h->last_stream = s;
   return FFD_OK;
 }

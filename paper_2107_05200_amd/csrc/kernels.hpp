@@ -15,19 +15,13 @@ namespace ffd {
 constexpr int kBlock = 256;      // threads per block for element / vertex kernels
 constexpr int kNumPartials = 9;  // per-block partial sums of the local step
 
-struct NodeDev {
-  int32_t first, c, r, pad;
-  int64_t pf;    // offset of this node's panel in both panel copies (16-byte aligned)
-  int64_t uoff, soff, poff;
-};
-
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
 
-template <int NF>
+template <int NF, int BS = kBlock>
 __device__ __forceinline__ void block_reduce_store(double (&v)[NF], double* __restrict out) {
-  __shared__ double red[kBlock / 64][NF];
+  __shared__ double red[BS / 64][NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
     double x = v[f];
@@ -44,7 +38,7 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NF], double* __re
   if (threadIdx.x < NF) {
     double s = 0.0;
 #pragma unroll
-    for (int wv = 0; wv < kBlock / 64; ++wv) s += red[wv][threadIdx.x];
+    for (int wv = 0; wv < BS / 64; ++wv) s += red[wv][threadIdx.x];
     out[threadIdx.x] = s;
   }
 }
@@ -377,19 +371,19 @@ __global__ __launch_bounds__(kBlock) void k_prepare(int64_t m, int64_t e0, int64
 
 // ---------------------------------------------------------------------------
 // K2: W-step right-hand side b = (G^T r)_F - L_FC x_C (eq. solvinginw), float64
-// accumulation; four lanes per vertex row share its incidence list and are
+// accumulation; LPR lanes (2, 4 or 8, picked by the autotuner) per vertex row share its incidence list and are
 // combined by a fixed shuffle tree.  Rows >= nF copy the pinned positions into
 // the new map.
 // ---------------------------------------------------------------------------
-template <int D, typename R>
+template <int D, typename R, int LPR = 4>
 __global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const int32_t* __restrict dt_ptr,
                                                  const int32_t* __restrict dt_idx, const R* __restrict g,
                                                  const int32_t* __restrict pin_ptr, const int32_t* __restrict pin_col,
                                                  const double* __restrict pin_val, const double* __restrict xC,
                                                  double* __restrict b, double* __restrict xnew) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const int64_t j = t >> 2;
-  const int sub = static_cast<int>(t & 3);
+  const int64_t j = t / LPR;
+  const int sub = static_cast<int>(t % LPR);
   if (j >= n) return;
   if (j >= nF) {
     if (sub == 0)
@@ -401,16 +395,15 @@ __global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const in
 #pragma unroll
   for (int k = 0; k < D; ++k) acc[k] = 0.0;
   const int32_t s = dt_ptr[j], e = dt_ptr[j + 1];
-  for (int32_t q = s + sub; q < e; q += 4) {
+  for (int32_t q = s + sub; q < e; q += LPR) {
     const int64_t o = static_cast<int64_t>(dt_idx[q]) * D;
 #pragma unroll
     for (int k = 0; k < D; ++k) acc[k] += static_cast<double>(g[o + k]);
   }
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    acc[k] += __shfl_xor(acc[k], 1, 64);
-    acc[k] += __shfl_xor(acc[k], 2, 64);
-  }
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (int off = 1; off < LPR; off <<= 1) acc[k] += __shfl_xor(acc[k], off, 64);
   if (sub != 0) return;
   for (int32_t q = pin_ptr[j]; q < pin_ptr[j + 1]; ++q) {
     const double v = pin_val[q];
@@ -426,114 +419,166 @@ __global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const in
 // K4 / K5: level-scheduled triangular solves with the node panels
 // [Linv; -M] ((c + r) x c): forward y = Linv v, u = carried - M v (v = the
 // node's right-hand side plus its children's update vectors, gathered by the
-// extend-add pull lists); backward x_C = [Linv^T | -M^T] [y; x_R].
+// extend-add pull lists; carried = the children's update rows that pass
+// through this node); backward x_C = [Linv^T | -M^T] [y; x_R].
 //
-// Both passes put the 64 lanes of a wave on 64 consecutive OUTPUTS and loop
-// over the inner index, so every wave load is 512 contiguous bytes: the
+// The lanes of a wave sit on OPT consecutive OUTPUTS (OPT = 64, 32 or 16,
+// chosen per level so that the level offers enough blocks) times 64 / OPT
+// inner streams; the four waves of a block add streams, so a block runs
+// NS = 256 / OPT interleaved streams over its inner range and every wave load
+// reads 64 / OPT runs of OPT contiguous doubles (whole 128-byte lines).  The
 // forward reads a column-major copy of the panel (column length ldc = nf
 // rounded up to even), the backward a row-major copy (row length ldr = c
-// rounded up to even).  A task owns 64 outputs and one chunk of at most
-// kSolveKC inner entries; the four waves of a block split that chunk and add
-// their sums in a fixed order.  Output blocks whose inner range spans several
-// chunks write per-chunk partials that a reduction kernel adds in chunk order
-// (no atomics; bitwise reproducible).
+// rounded up to even).  The first batch of panel loads is issued before the
+// LDS staging of the inner vector so the gather latency overlaps the stream.
+// Streams are added in a fixed order.  Levels that still offer too few blocks
+// split the inner ranges into chunks whose partials a reduction kernel adds in
+// chunk order (no atomics; bitwise reproducible).
 // ---------------------------------------------------------------------------
-constexpr int kSolveRT = 64;    // outputs per task (one per lane)
-constexpr int kSolveKC = 256;   // inner entries staged in LDS at a time
+constexpr int kSolveOutMax = 64;  // outputs per task at most (partial slot stride)
+constexpr int kSolveKC = 512;     // inner entries staged in LDS at a time
+constexpr int kSolveBatch = 8;    // panel loads in flight per lane
 
-// a task owns outputs [out0, out0 + 64) of `node` and the inner range [lo, hi);
-// slot < 0: the task covers the whole inner range and writes final outputs;
-// otherwise it writes partials to slot and a reduction adds nk slots from base
+// One block of a solve level (or one wave of a reduction), self-contained so
+// a block starts streaming after a single scalar load.
 struct SolveTask {
-  int32_t node, out0, lo, hi, slot, nk;
+  int64_t pf;                // node panel offset (both copies)
+  int64_t poff, uoff, soff;  // node: pull-list base, update-vector base, struct-index base
+  int32_t ld;                // leading dimension of the copy the pass reads
+  int32_t first, c, nf;      // node: first internal row, pivots, c + r
+  int32_t out0, lo, hi;      // outputs [out0, out0 + OPT) of the pass, inner range [lo, hi)
+  int32_t slot, nk;          // slot < 0: final outputs; else partial slot (reduction: nk slots from slot)
+  int32_t pad[3];
 };
+static_assert(sizeof(SolveTask) == 80, "SolveTask layout");
 
+// carried part of forward output i (an update row): children's update rows
 template <int D>
-__device__ __forceinline__ void solve_block_sum(double (&acc)[D], int lane, int wave) {
-  __shared__ double red[4][kSolveRT][D];
+__device__ __forceinline__ void fwd_carried(const SolveTask& tk, int i, const int32_t* __restrict pull_ptr,
+                                            const int32_t* __restrict pull_idx, const double* __restrict ub,
+                                            double (&cv)[D]) {
+  for (int32_t q = pull_ptr[tk.poff + i]; q < pull_ptr[tk.poff + i + 1]; ++q) {
+    const int64_t o = static_cast<int64_t>(pull_idx[q]) * D;
 #pragma unroll
-  for (int k = 0; k < D; ++k) red[wave][lane][k] = acc[k];
-  __syncthreads();
-  if (wave == 0)
-#pragma unroll
-    for (int k = 0; k < D; ++k) acc[k] = ((red[0][lane][k] + red[1][lane][k]) + red[2][lane][k]) + red[3][lane][k];
-}
-
-// forward output i of node nd: y row (i < c) or update row (carried part added)
-template <int D>
-__device__ __forceinline__ void fwd_finalize(const NodeDev& nd, int i, double (&acc)[D],
-                                             const int32_t* __restrict pull_ptr, const int32_t* __restrict pull_idx,
-                                             double* __restrict y, double* __restrict ub) {
-  if (i < nd.c) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) y[static_cast<int64_t>(nd.first + i) * D + k] = acc[k];
-  } else {
-    for (int32_t q = pull_ptr[nd.poff + i]; q < pull_ptr[nd.poff + i + 1]; ++q) {
-      const int64_t o = static_cast<int64_t>(pull_idx[q]) * D;
-#pragma unroll
-      for (int k = 0; k < D; ++k) acc[k] += ub[o + k];
-    }
-#pragma unroll
-    for (int k = 0; k < D; ++k) ub[(nd.uoff + i - nd.c) * D + k] = acc[k];
+    for (int k = 0; k < D; ++k) cv[k] += ub[o + k];
   }
 }
 
 template <int D>
+__device__ __forceinline__ void fwd_store(const SolveTask& tk, int i, const double (&acc)[D],
+                                          double* __restrict y, double* __restrict ub) {
+  if (i < tk.c) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) y[static_cast<int64_t>(tk.first + i) * D + k] = acc[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < D; ++k) ub[(tk.uoff + i - tk.c) * D + k] = acc[k];
+  }
+}
+
+// Stream the panel entries of inner range [lo, hi) of one block: acc +=
+// sum_j P(out, j) v_j with v staged chunk by chunk into LDS by `stage`.
+// Lane stream st covers j = lo + st, lo + st + NS, ... in order.
+template <int D, int NS, typename Stage>
+__device__ __forceinline__ void solve_stream(const double* __restrict base, int64_t ld, bool live, int lo, int hi,
+                                             int st, double (&vs)[kSolveKC][D], double (&acc)[D], Stage stage) {
+  for (int j0 = lo; j0 < hi; j0 += kSolveKC) {
+    const int jn = min(kSolveKC, hi - j0);
+    const double* __restrict p0 = base + static_cast<int64_t>(j0) * ld;
+    double pv[kSolveBatch];
+#pragma unroll
+    for (int u = 0; u < kSolveBatch; ++u) {
+      const int jj = st + u * NS;
+      pv[u] = (live && jj < jn) ? p0[static_cast<int64_t>(jj) * ld] : 0.0;
+    }
+    stage(j0, jn);
+    __syncthreads();
+    for (int jb = 0; jb < jn; jb += kSolveBatch * NS) {
+      double pn[kSolveBatch];
+#pragma unroll
+      for (int u = 0; u < kSolveBatch; ++u) {
+        const int jj = jb + kSolveBatch * NS + st + u * NS;
+        pn[u] = (live && jj < jn) ? p0[static_cast<int64_t>(jj) * ld] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kSolveBatch; ++u) {
+        const int jj = jb + st + u * NS;
+        if (jj < jn) {
+#pragma unroll
+          for (int k = 0; k < D; ++k) acc[k] += pv[u] * vs[jj][k];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kSolveBatch; ++u) pv[u] = pn[u];
+    }
+    __syncthreads();
+  }
+}
+
+// sum of the NS streams of each output in stream order; valid for threads < OPT
+template <int D, int OPT>
+__device__ __forceinline__ void solve_streams_sum(double (&acc)[D], int o, int st) {
+  constexpr int NS = 4 * (64 / OPT);
+  __shared__ double red[NS][OPT][D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) red[st][o][k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < OPT) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) v += red[q][threadIdx.x][k];
+      acc[k] = v;
+    }
+  }
+}
+
+template <int D, int OPT>
 __global__ __launch_bounds__(kBlock) void k_solve_fwd(const SolveTask* __restrict tasks,
-                                                      const NodeDev* __restrict nodes, const double* __restrict Pcol,
+                                                      const double* __restrict Pcol,
                                                       const int32_t* __restrict pull_ptr,
                                                       const int32_t* __restrict pull_idx, const double* __restrict b,
                                                       double* __restrict y, double* __restrict ub,
                                                       double* __restrict part) {
+  constexpr int NS = 4 * (64 / OPT);
   __shared__ double vs[kSolveKC][D];
   const SolveTask tk = tasks[blockIdx.x];
-  const NodeDev nd = nodes[tk.node];
-  const int nf = nd.c + nd.r, ldc = (nf + 1) & ~1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = tk.out0 + lane;
-  double acc[D];
+  const int o = lane % OPT, st = wave * (64 / OPT) + lane / OPT;
+  const int i = tk.out0 + o;
+  const bool live = i < tk.nf;
+  double cv[D], acc[D];
 #pragma unroll
-  for (int k = 0; k < D; ++k) acc[k] = 0.0;
-  for (int j0 = tk.lo; j0 < tk.hi; j0 += kSolveKC) {
-    const int jn = min(kSolveKC, tk.hi - j0);
+  for (int k = 0; k < D; ++k) cv[k] = acc[k] = 0.0;
+  if (tk.slot < 0 && threadIdx.x < OPT && live && i >= tk.c) fwd_carried<D>(tk, i, pull_ptr, pull_idx, ub, cv);
+  auto stage = [&](int j0, int jn) {
     for (int t = threadIdx.x; t < jn; t += kBlock) {
       const int p = j0 + t;
       double a[D];
 #pragma unroll
-      for (int k = 0; k < D; ++k) a[k] = b[static_cast<int64_t>(nd.first + p) * D + k];
-      for (int32_t q = pull_ptr[nd.poff + p]; q < pull_ptr[nd.poff + p + 1]; ++q) {
-        const int64_t o = static_cast<int64_t>(pull_idx[q]) * D;
-#pragma unroll
-        for (int k = 0; k < D; ++k) a[k] += ub[o + k];
-      }
+      for (int k = 0; k < D; ++k) a[k] = b[static_cast<int64_t>(tk.first + p) * D + k];
+      fwd_carried<D>(tk, p, pull_ptr, pull_idx, ub, a);
 #pragma unroll
       for (int k = 0; k < D; ++k) vs[t][k] = a[k];
     }
-    __syncthreads();
-    if (i < nf) {
-      const double* __restrict col = Pcol + nd.pf + static_cast<int64_t>(j0) * ldc + i;
-#pragma unroll 8
-      for (int jj = wave; jj < jn; jj += 4) {
-        const double pv = col[static_cast<int64_t>(jj) * ldc];
-#pragma unroll
-        for (int k = 0; k < D; ++k) acc[k] += pv * vs[jj][k];
-      }
-    }
-    __syncthreads();
-  }
-  solve_block_sum<D>(acc, lane, wave);
-  if (wave != 0 || i >= nf) return;
+  };
+  solve_stream<D, NS>(Pcol + tk.pf + i, tk.ld, live, tk.lo, tk.hi, st, vs, acc, stage);
+  solve_streams_sum<D, OPT>(acc, o, st);
+  if (threadIdx.x >= OPT || !live) return;
   if (tk.slot >= 0) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) part[(static_cast<int64_t>(tk.slot) * kSolveRT + lane) * D + k] = acc[k];
+    for (int k = 0; k < D; ++k) part[(static_cast<int64_t>(tk.slot) * kSolveOutMax + o) * D + k] = acc[k];
   } else {
-    fwd_finalize<D>(nd, i, acc, pull_ptr, pull_idx, y, ub);
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] += cv[k];
+    fwd_store<D>(tk, i, acc, y, ub);
   }
 }
 
+// one wave per split output block: add its nk chunk partials in order
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_solve_fwd_reduce(const SolveTask* __restrict tasks, int ntasks,
-                                                             const NodeDev* __restrict nodes,
                                                              const int32_t* __restrict pull_ptr,
                                                              const int32_t* __restrict pull_idx,
                                                              double* __restrict y, double* __restrict ub,
@@ -541,84 +586,188 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd_reduce(const SolveTask* __
   const int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (t >= ntasks) return;
   const SolveTask tk = tasks[t];
-  const NodeDev nd = nodes[tk.node];
   const int lane = threadIdx.x & 63;
   const int i = tk.out0 + lane;
-  if (i >= nd.c + nd.r) return;
+  if (lane >= tk.hi || i >= tk.nf) return;  // hi: outputs of the block
   double acc[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) acc[k] = 0.0;
   for (int q = 0; q < tk.nk; ++q)
 #pragma unroll
-    for (int k = 0; k < D; ++k) acc[k] += part[(static_cast<int64_t>(tk.slot + q) * kSolveRT + lane) * D + k];
-  fwd_finalize<D>(nd, i, acc, pull_ptr, pull_idx, y, ub);
+    for (int k = 0; k < D; ++k) acc[k] += part[(static_cast<int64_t>(tk.slot + q) * kSolveOutMax + lane) * D + k];
+  if (i >= tk.c) fwd_carried<D>(tk, i, pull_ptr, pull_idx, ub, acc);
+  fwd_store<D>(tk, i, acc, y, ub);
 }
 
-template <int D>
+template <int D, int OPT>
 __global__ __launch_bounds__(kBlock) void k_solve_bwd(const SolveTask* __restrict tasks,
-                                                      const NodeDev* __restrict nodes, const double* __restrict Prow,
-                                                      const int32_t* __restrict sidx, const double* __restrict y,
-                                                      double* __restrict x, double* __restrict part) {
+                                                      const double* __restrict Prow, const int32_t* __restrict sidx,
+                                                      const double* __restrict y, double* __restrict x,
+                                                      double* __restrict part) {
+  constexpr int NS = 4 * (64 / OPT);
   __shared__ double vs[kSolveKC][D];
   const SolveTask tk = tasks[blockIdx.x];
-  const NodeDev nd = nodes[tk.node];
-  const int c = nd.c, ldr = (nd.c + 1) & ~1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int j = tk.out0 + lane;
+  const int o = lane % OPT, st = wave * (64 / OPT) + lane / OPT;
+  const int j = tk.out0 + o;
+  const bool live = j < tk.c;
   double acc[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) acc[k] = 0.0;
-  for (int p0 = tk.lo; p0 < tk.hi; p0 += kSolveKC) {
-    const int pn = min(kSolveKC, tk.hi - p0);
+  auto stage = [&](int p0, int pn) {
     for (int t = threadIdx.x; t < pn; t += kBlock) {
       const int p = p0 + t;
-      const int64_t src = p < c ? static_cast<int64_t>(nd.first + p) : static_cast<int64_t>(sidx[nd.soff + p - c]);
-      const double* vsrc = p < c ? y : x;
+      const int64_t src = p < tk.c ? static_cast<int64_t>(tk.first + p) : static_cast<int64_t>(sidx[tk.soff + p - tk.c]);
+      const double* vsrc = p < tk.c ? y : x;
 #pragma unroll
       for (int k = 0; k < D; ++k) vs[t][k] = vsrc[src * D + k];
     }
-    __syncthreads();
-    if (j < c) {
-      const double* __restrict rowp = Prow + nd.pf + static_cast<int64_t>(p0) * ldr + j;
-#pragma unroll 8
-      for (int pp = wave; pp < pn; pp += 4) {
-        const double pv = rowp[static_cast<int64_t>(pp) * ldr];
-#pragma unroll
-        for (int k = 0; k < D; ++k) acc[k] += pv * vs[pp][k];
-      }
-    }
-    __syncthreads();
-  }
-  solve_block_sum<D>(acc, lane, wave);
-  if (wave != 0 || j >= c) return;
+  };
+  solve_stream<D, NS>(Prow + tk.pf + j, tk.ld, live, tk.lo, tk.hi, st, vs, acc, stage);
+  solve_streams_sum<D, OPT>(acc, o, st);
+  if (threadIdx.x >= OPT || !live) return;
   if (tk.slot >= 0) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) part[(static_cast<int64_t>(tk.slot) * kSolveRT + lane) * D + k] = acc[k];
+    for (int k = 0; k < D; ++k) part[(static_cast<int64_t>(tk.slot) * kSolveOutMax + o) * D + k] = acc[k];
   } else {
 #pragma unroll
-    for (int k = 0; k < D; ++k) x[static_cast<int64_t>(nd.first + j) * D + k] = acc[k];
+    for (int k = 0; k < D; ++k) x[static_cast<int64_t>(tk.first + j) * D + k] = acc[k];
   }
 }
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_solve_bwd_reduce(const SolveTask* __restrict tasks, int ntasks,
-                                                             const NodeDev* __restrict nodes, double* __restrict x,
-                                                             const double* __restrict part) {
+                                                             double* __restrict x, const double* __restrict part) {
   const int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (t >= ntasks) return;
   const SolveTask tk = tasks[t];
-  const NodeDev nd = nodes[tk.node];
   const int lane = threadIdx.x & 63;
   const int j = tk.out0 + lane;
-  if (j >= nd.c) return;
+  if (lane >= tk.hi || j >= tk.c) return;
   double acc[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) acc[k] = 0.0;
   for (int q = 0; q < tk.nk; ++q)
 #pragma unroll
-    for (int k = 0; k < D; ++k) acc[k] += part[(static_cast<int64_t>(tk.slot + q) * kSolveRT + lane) * D + k];
+    for (int k = 0; k < D; ++k) acc[k] += part[(static_cast<int64_t>(tk.slot + q) * kSolveOutMax + lane) * D + k];
 #pragma unroll
-  for (int k = 0; k < D; ++k) x[static_cast<int64_t>(nd.first + j) * D + k] = acc[k];
+  for (int k = 0; k < D; ++k) x[static_cast<int64_t>(tk.first + j) * D + k] = acc[k];
+}
+
+// Wave-per-task form for levels of small nodes: each wave owns one task (OPT
+// outputs x 64 / OPT streams), stages its inner vector 64 entries at a time in
+// a wave-private LDS slice and adds its streams with a fixed xor tree.  There
+// is no block barrier, so a CU keeps up to 32 independent tasks in flight.
+constexpr int kWaveKC = 64;
+
+// orders this wave's LDS writes before its later LDS reads (LDS operations of
+// one wave complete in order; the fences keep the compiler from moving them)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int D, int OPT>
+__device__ __forceinline__ void wave_streams_sum(double (&acc)[D]) {
+#pragma unroll
+  for (int off = OPT; off < 64; off <<= 1)
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] += __shfl_xor(acc[k], off, 64);
+}
+
+template <int D, int OPT>
+__global__ __launch_bounds__(kBlock) void k_solve_fwd_wave(const SolveTask* __restrict tasks, int ntasks,
+                                                           const double* __restrict Pcol,
+                                                           const int32_t* __restrict pull_ptr,
+                                                           const int32_t* __restrict pull_idx,
+                                                           const double* __restrict b, double* __restrict y,
+                                                           double* __restrict ub) {
+  constexpr int IS = 64 / OPT;
+  __shared__ double vs[kBlock / 64][kWaveKC][D];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = blockIdx.x * (kBlock / 64) + wave;
+  if (t >= ntasks) return;  // the whole wave leaves; no block barrier follows
+  const SolveTask tk = tasks[t];
+  const int o = lane % OPT, st = lane / OPT;
+  const int i = tk.out0 + o;
+  const bool live = i < tk.nf;
+  double cv[D], acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) cv[k] = acc[k] = 0.0;
+  if (st == 0 && live && i >= tk.c) fwd_carried<D>(tk, i, pull_ptr, pull_idx, ub, cv);
+  const double* __restrict col = Pcol + tk.pf + i;
+  for (int j0 = tk.lo; j0 < tk.hi; j0 += kWaveKC) {
+    const int jn = min(kWaveKC, tk.hi - j0);
+    if (lane < jn) {
+      const int p = j0 + lane;
+      double a[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) a[k] = b[static_cast<int64_t>(tk.first + p) * D + k];
+      fwd_carried<D>(tk, p, pull_ptr, pull_idx, ub, a);
+#pragma unroll
+      for (int k = 0; k < D; ++k) vs[wave][lane][k] = a[k];
+    }
+    wave_lds_sync();
+    if (live) {
+#pragma unroll 8
+      for (int jj = st; jj < jn; jj += IS) {
+        const double pv = col[static_cast<int64_t>(j0 + jj) * tk.ld];
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] += pv * vs[wave][jj][k];
+      }
+    }
+    wave_lds_sync();
+  }
+  wave_streams_sum<D, OPT>(acc);
+  if (st != 0 || !live) return;
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] += cv[k];
+  fwd_store<D>(tk, i, acc, y, ub);
+}
+
+template <int D, int OPT>
+__global__ __launch_bounds__(kBlock) void k_solve_bwd_wave(const SolveTask* __restrict tasks, int ntasks,
+                                                           const double* __restrict Prow,
+                                                           const int32_t* __restrict sidx,
+                                                           const double* __restrict y, double* __restrict x) {
+  constexpr int IS = 64 / OPT;
+  __shared__ double vs[kBlock / 64][kWaveKC][D];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = blockIdx.x * (kBlock / 64) + wave;
+  if (t >= ntasks) return;
+  const SolveTask tk = tasks[t];
+  const int o = lane % OPT, st = lane / OPT;
+  const int j = tk.out0 + o;
+  const bool live = j < tk.c;
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  const double* __restrict rowp = Prow + tk.pf + j;
+  for (int p0 = tk.lo; p0 < tk.hi; p0 += kWaveKC) {
+    const int pn = min(kWaveKC, tk.hi - p0);
+    if (lane < pn) {
+      const int p = p0 + lane;
+      const int64_t src = p < tk.c ? static_cast<int64_t>(tk.first + p) : static_cast<int64_t>(sidx[tk.soff + p - tk.c]);
+      const double* vsrc = p < tk.c ? y : x;
+#pragma unroll
+      for (int k = 0; k < D; ++k) vs[wave][lane][k] = vsrc[src * D + k];
+    }
+    wave_lds_sync();
+    if (live) {
+#pragma unroll 8
+      for (int pp = st; pp < pn; pp += IS) {
+        const double pv = rowp[static_cast<int64_t>(p0 + pp) * tk.ld];
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] += pv * vs[wave][pp][k];
+      }
+    }
+    wave_lds_sync();
+  }
+  wave_streams_sum<D, OPT>(acc);
+  if (st != 0 || !live) return;
+#pragma unroll
+  for (int k = 0; k < D; ++k) x[static_cast<int64_t>(tk.first + j) * D + k] = acc[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -627,15 +776,15 @@ __global__ __launch_bounds__(kBlock) void k_solve_bwd_reduce(const SolveTask* __
 // primaldualerror).  Partials: 0 e_prim^2, 1 e_dual^2, 2 E_P, 3 E_map (over
 // det J > 0), 4 Phi, 5 flips, 6 non-finite Lambda, 7 |GW|^2, 8 |P|^2.
 // ---------------------------------------------------------------------------
-template <int D, typename R, int ENERGY>
-__global__ __launch_bounds__(kBlock) void k_local(int64_t m, int64_t e0, int64_t e1, const int32_t* __restrict T,
+template <int D, typename R, int ENERGY, int BS = kBlock>
+__global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1, const int32_t* __restrict T,
                                                   const R* __restrict Bm_,
                                                   const R* __restrict w, R rho, int h_mode, int store_u,
                                                   const double* __restrict x, const double* __restrict xprev,
                                                   R* __restrict U, R* __restrict P, R* __restrict Lam,
                                                   R* __restrict gnorm2, R* __restrict g,
                                                   double* __restrict partials) {
-  const int64_t e = e0 + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t e = e0 + static_cast<int64_t>(blockIdx.x) * BS + threadIdx.x;
   double part[kNumPartials];
 #pragma unroll
   for (int f = 0; f < kNumPartials; ++f) part[f] = 0.0;
@@ -795,7 +944,25 @@ __global__ __launch_bounds__(kBlock) void k_local(int64_t m, int64_t e0, int64_t
     part[6] = finite ? 0.0 : 1.0;
     part[8] = p2;
   }
-  block_reduce_store<kNumPartials>(part, partials + static_cast<int64_t>(blockIdx.x) * kNumPartials);
+  block_reduce_store<kNumPartials, BS>(part, partials + static_cast<int64_t>(blockIdx.x) * kNumPartials);
+}
+
+// first stage of the partial-sum reduction when the local step ran many small
+// blocks: block j adds rows [j kFinalizeRows, (j + 1) kFinalizeRows) in a fixed
+// order (strided per thread, then the shuffle tree)
+constexpr int kFinalizeRows = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_partials_reduce(const double* __restrict partials, int64_t nb,
+                                                            double* __restrict out) {
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kFinalizeRows;
+  const int64_t r1 = r0 + kFinalizeRows < nb ? r0 + kFinalizeRows : nb;
+  double v[kNumPartials];
+#pragma unroll
+  for (int f = 0; f < kNumPartials; ++f) v[f] = 0.0;
+  for (int64_t bi = r0 + threadIdx.x; bi < r1; bi += kBlock)
+#pragma unroll
+    for (int f = 0; f < kNumPartials; ++f) v[f] += partials[bi * kNumPartials + f];
+  block_reduce_store<kNumPartials>(v, out + static_cast<int64_t>(blockIdx.x) * kNumPartials);
 }
 
 // fixed-order reduction of the block partials into one history record

@@ -81,3 +81,37 @@ def test_batch_full_c4_runs(gpu_lib):
     assert np.all(np.isfinite(h[:, :3]))
     assert h[-1, 0] < h[0, 0]
     assert bool(torch.all(torch.linalg.det(st["Wel"].double()) > 0))
+
+
+def test_autotune_choices_keep_results(gpu_lib, tmp_path):
+    """The autotuner's launch shapes change timing only: the state after
+    the same iterations agrees with the default shapes up to the summation
+    order of the right-hand side and the split solve, and the choice is cached
+    and read back."""
+    import torch
+    from paper_2107_05200_amd.binding import BatchSolver
+    ws = _charts(6, seed_c=9)
+    x0 = np.concatenate([w.x0 for w in ws])
+    say(f"case: autotune on a batch of {len(ws)} charts")
+    a = BatchSolver(ws, precision=64)
+    a.init(x0).iterate(15)
+    sa = {k: v.cpu().numpy() for k, v in a.get_state().items()}
+    b = BatchSolver(ws, precision=64)
+    b.init(x0)
+    cache = str(tmp_path / "tune.txt")
+    ch = b.autotune(cache)
+    assert ch["local_block"] in (64, 128, 256) and ch["wrhs_lanes"] in (2, 4, 8)
+    assert ch["solve_wave_levels"] >= 0 and ch["solve_split_levels"] >= 0
+    assert b.iteration() == 0
+    b.iterate(15)
+    sb = {k: v.cpu().numpy() for k, v in b.get_state().items()}
+    torch.cuda.synchronize()
+    for k in sa:
+        assert np.array_equal(np.isnan(sa[k]), np.isnan(sb[k])), k
+        assert rel(np.nan_to_num(sb[k]), np.nan_to_num(sa[k])) < 1e-9, k
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1
+    c = BatchSolver(ws, precision=64)
+    c.init(x0)
+    assert c.autotune(cache) == ch
+    assert len(open(cache).read().strip().splitlines()) == 1

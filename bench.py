@@ -185,6 +185,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=200000)
     ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and batched legs")
     ap.add_argument("--tune-cache", default=None, help="launch-shape cache file (read, or written after tuning)")
+    ap.add_argument("--no-graph", action="store_true", help="time direct launches instead of replayed HIP graphs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain elementwise copy (negation) of MIB MiB ten times (counter calibration)")
     args = ap.parse_args()
@@ -224,7 +225,7 @@ def main():
     t0 = time.perf_counter()
     launch = s.autotune(args.tune_cache)
     log(f"launch shapes {launch} ({time.perf_counter() - t0:.2f}s)")
-    s.iterate(args.warmup)
+    s.iterate(args.warmup, stream, graph=not args.no_graph)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} done")
 
@@ -236,7 +237,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    s.iterate(args.steps, stream)
+    s.iterate(args.steps, stream, graph=not args.no_graph)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

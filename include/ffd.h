@@ -159,6 +159,14 @@ ffd_status ffd_set_pins(ffd_handle h, const double* pinned_pos_dev, void* stream
 /* Run n_iter iterations of Algorithm 1, appending n_iter history records. */
 ffd_status ffd_iterate(ffd_handle h, int32_t n_iter, void* stream);
 
+/* As ffd_iterate, with the launches of two iterations captured once into a
+ * HIP graph (on a stream of the handle's own) and replayed on `stream`
+ * (Algorithm 1's loop body has a fixed launch sequence, so one capture serves
+ * every replay).  Results are bitwise those of ffd_iterate.  The graph is
+ * captured again after anything that changes launch shapes or buffers
+ * (ffd_autotune, a larger history); an odd iteration is run directly. */
+ffd_status ffd_iterate_graph(ffd_handle h, int32_t n_iter, void* stream);
+
 /* As ffd_iterate, with a HIP event recorded on `stream` between the phases
  * of every iteration; on return (after synchronising the stream)
  * phase_ms_host[0..4] hold the summed milliseconds of the phases
@@ -225,17 +233,21 @@ ffd_status ffd_adjoint_backward(ffd_handle h, const void* Pbar_dev, int32_t ener
  * with HIP events on `stream` from the current state (which is saved before
  * and restored after; the timed iterations are not recorded): the local-step
  * block size (64 / 128 / 256 elements), the lanes per vertex row of the
- * right-hand side (2 / 4 / 8) and, level by level for both triangular-solve
- * passes, the task shape: blocks of four waves or one wave per task, 64 / 32 /
- * 16 outputs per task, and inner-range splitting (none, 2048 .. 256).  With
- * cache_path (may be NULL) the choice is read from / appended to a text file,
- * one line per key "arch|d|energy|precision|element bucket|factor
- * bucket|levels|h" followed by the block size, lanes per row, the level count
- * and three numbers (mode, outputs, chunk) per level and pass.  choice_out
- * (may be NULL): 4 int32 (block size, lanes per row, solve levels run one wave
- * per task, solve levels with split inner ranges; both passes counted).
- * Element results do not depend on the choice; history sums and the solve's
- * rounding order may change in the last bits. */
+ * right-hand side (2 / 4 / 8); level by level for both triangular-solve
+ * passes, the task shape (blocks of 4 / 8 / 16 waves or one wave per task,
+ * 64 / 32 / 16 outputs per task, inner-range splitting: none, 2048 .. 256);
+ * and the
+ * number of streams (1 .. 4, the caller's stream plus streams of the handle,
+ * all of default priority) over which the subtrees below a top level are
+ * spread.  With cache_path (may be NULL) the choice is read from / appended
+ * to a text file, one line per key "arch|d|energy|precision|element
+ * bucket|factor bucket|levels|h" followed by the block size, lanes per row,
+ * level count, stream count, top level and four numbers (mode, outputs,
+ * chunk, waves) per level and pass.  choice_out (may be NULL): 6 int32 (block size,
+ * lanes per row, solve levels run one wave per task, solve levels with split
+ * inner ranges (both passes counted), streams, top level).  Element results
+ * do not depend on the choice; history sums and the solve's rounding order
+ * may change in the last bits. */
 ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int32_t* choice_out);
 
 void ffd_destroy(ffd_handle h);

@@ -61,6 +61,7 @@ _PROTOS = {
     "ffd_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ffd_set_pins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ffd_iterate": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "ffd_iterate_graph": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "ffd_iterate_profiled": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
     "ffd_get_state": (C.c_int, [C.c_void_p] + [C.c_void_p] * 5 + [C.c_void_p]),
     "ffd_set_state": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4 + [C.c_int64, C.c_void_p]),
@@ -201,8 +202,10 @@ class Solver:
         _check(self.lib.ffd_set_pins(self.h, C.c_void_p(p.data_ptr()), _stream(stream)))
         self._keep_pins = p
 
-    def iterate(self, n_iter: int = 1, stream=None):
-        _check(self.lib.ffd_iterate(self.h, int(n_iter), _stream(stream)))
+    def iterate(self, n_iter: int = 1, stream=None, graph: bool = False):
+        """n_iter iterations; graph=True replays a captured HIP graph (same results)."""
+        fn = self.lib.ffd_iterate_graph if graph else self.lib.ffd_iterate
+        _check(fn(self.h, int(n_iter), _stream(stream)))
         return self
 
     def iterate_profiled(self, n_iter: int, stream=None) -> dict:
@@ -255,10 +258,10 @@ class Solver:
 
     def autotune(self, cache_path: str | None = None, stream=None) -> dict:
         """Pick launch shapes by timing them (state saved and restored)."""
-        out = (C.c_int32 * 4)()
+        out = (C.c_int32 * 6)()
         _check(self.lib.ffd_autotune(self.h, cache_path.encode() if cache_path else None, _stream(stream), out))
         return {"local_block": out[0], "wrhs_lanes": out[1], "solve_wave_levels": out[2],
-                "solve_split_levels": out[3]}
+                "solve_split_levels": out[3], "solve_streams": out[4], "solve_top_level": out[5]}
 
     def adjoint_forward(self, n_iter: int, checkpoint_every: int = 10, stream=None):
         """n_iter iterations with checkpoints every checkpoint_every (for adjoint_backward)."""

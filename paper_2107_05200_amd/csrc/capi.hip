@@ -44,15 +44,17 @@ inline unsigned nblk(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) 
 
 }  // namespace
 
-// Launch configuration of one solve level of one pass: mode 0 = blocks of
-// four waves per task, 1 = one wave per task; opt = outputs per task (64, 32,
-// 16); chunk > 0 splits inner ranges longer than chunk (block mode only).
+// Launch configuration of one solve level of one pass: mode 0 = blocks of nw
+// waves per task, 1 = one wave per task; opt = outputs per task (64, 32, 16);
+// chunk > 0 splits inner ranges longer than chunk (block mode only).
 struct LevelCfg {
-  int32_t mode = 0, opt = 64, chunk = 0;
-  bool operator==(const LevelCfg& o) const { return mode == o.mode && opt == o.opt && chunk == o.chunk; }
+  int32_t mode = 0, opt = 64, chunk = 0, nw = 4;  // nw: waves per block (block mode: 4, 8, 16)
+  bool operator==(const LevelCfg& o) const {
+    return mode == o.mode && opt == o.opt && chunk == o.chunk && nw == o.nw;
+  }
 };
 struct LevelRun {
-  int32_t mode = 0, opt = 64, t0 = 0, nt = 0, r0 = 0, nr = 0;  // tasks [t0, t0+nt), reductions [r0, r0+nr)
+  int32_t mode = 0, opt = 64, nw = 4, t0 = 0, nt = 0, r0 = 0, nr = 0;  // tasks [t0, t0+nt), reductions [r0, r0+nr)
 };
 
 struct ffd_ctx {
@@ -92,8 +94,23 @@ struct ffd_ctx {
   int32_t *dt_ptr = nullptr, *dt_idx = nullptr, *pin_ptr = nullptr, *pin_col = nullptr;
   double* pin_val = nullptr;
   std::vector<int64_t> hpoff;  // device panel offset of every node
+  // two captured iterations replayed by ffd_iterate_graph
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool graph_valid = false;      // captured with the current launch shapes and buffers
+  int graph_cur = 0;             // map buffer holding W^k when the graph starts
+  double* graph_hist = nullptr;  // history buffer the graph writes to
+  int64_t* k_dev = nullptr;      // device copy of the iteration counter
   std::vector<LevelCfg> cfg_fwd, cfg_bwd;  // per-level launch configuration of both solve passes
-  std::vector<LevelRun> run_fwd, run_bwd;  // per-level task ranges built from them
+  // The forest below level solve_top is split into solve_groups groups of
+  // whole subtrees, each solved on its own stream (group 0 on the caller's);
+  // levels >= solve_top run on the caller's stream after the join.
+  int solve_groups = 1, solve_top = 0;
+  std::vector<int32_t> hparent;                  // parent node (-1: root)
+  std::vector<std::vector<LevelRun>> grun_fwd, grun_bwd;  // [group][level]; group solve_groups = top levels
+  std::vector<hipStream_t> wstreams;             // worker streams of groups 1..
+  hipEvent_t fork_ev[2] = {nullptr, nullptr}, join_ev[2][8] = {};
   double *Prow = nullptr, *Pcol = nullptr;  // factor panels, row- and column-major copies
   int32_t *sidx = nullptr, *pull_ptr = nullptr, *pull_idx = nullptr;
   SolveTask *tasks_fwd = nullptr, *tasks_bwd = nullptr, *red_fwd = nullptr, *red_bwd = nullptr;
@@ -135,6 +152,15 @@ struct ffd_ctx {
   }
   size_t rsize() const { return prec == 32 ? 4 : 8; }
   ~ffd_ctx() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (hipStream_t w : wstreams) (void)hipStreamDestroy(w);
+    for (int p = 0; p < 2; ++p) {
+      if (fork_ev[p]) (void)hipEventDestroy(fork_ev[p]);
+      for (hipEvent_t e : join_ev[p])
+        if (e) (void)hipEventDestroy(e);
+    }
     for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
     for (void* p : allocs) (void)hipFree(p);
   }
@@ -199,6 +225,7 @@ void launch_local(ffd_ctx* h, const ffd_ctx::Seg& g, const double* xnew, const d
 
 // partial-sum block offsets of the energy ranges for the local-step block size
 void set_local_block(ffd_ctx* h, int bs) {
+  h->graph_valid = false;
   h->local_bs = bs;
   int64_t pb = 0;
   for (auto& g : h->segs) {
@@ -221,14 +248,29 @@ void launch_wrhs(ffd_ctx* h, double* xnew, hipStream_t s) {
   else launch_wrhs_l<D, R, 4>(h, xnew, s);
 }
 
+template <int D, int OPT, int NW>
+void launch_fwd_block(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, const double* b, hipStream_t s) {
+  hipLaunchKernelGGL((k_solve_fwd<D, OPT, NW>), dim3(r.nt), dim3(NW * 64), 0, s, tasks, h->Pcol, h->pull_ptr,
+                     h->pull_idx, b, h->y, h->ub, h->solve_part);
+}
+
+template <int D, int OPT, int NW>
+void launch_bwd_block(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, double* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_solve_bwd<D, OPT, NW>), dim3(r.nt), dim3(NW * 64), 0, s, tasks, h->Prow, h->sidx, h->y, x,
+                     h->solve_part);
+}
+
 template <int D, int OPT>
 void launch_fwd_opt(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, const double* b, hipStream_t s) {
   if (r.mode == 1)
     hipLaunchKernelGGL((k_solve_fwd_wave<D, OPT>), dim3((r.nt + 3) / 4), dim3(kBlock), 0, s, tasks, r.nt, h->Pcol,
                        h->pull_ptr, h->pull_idx, b, h->y, h->ub);
+  else if (r.nw == 16)
+    launch_fwd_block<D, OPT, 16>(h, r, tasks, b, s);
+  else if (r.nw == 8)
+    launch_fwd_block<D, OPT, 8>(h, r, tasks, b, s);
   else
-    hipLaunchKernelGGL((k_solve_fwd<D, OPT>), dim3(r.nt), dim3(kBlock), 0, s, tasks, h->Pcol, h->pull_ptr,
-                       h->pull_idx, b, h->y, h->ub, h->solve_part);
+    launch_fwd_block<D, OPT, 4>(h, r, tasks, b, s);
 }
 
 template <int D, int OPT>
@@ -236,9 +278,12 @@ void launch_bwd_opt(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, doubl
   if (r.mode == 1)
     hipLaunchKernelGGL((k_solve_bwd_wave<D, OPT>), dim3((r.nt + 3) / 4), dim3(kBlock), 0, s, tasks, r.nt, h->Prow,
                        h->sidx, h->y, x);
+  else if (r.nw == 16)
+    launch_bwd_block<D, OPT, 16>(h, r, tasks, x, s);
+  else if (r.nw == 8)
+    launch_bwd_block<D, OPT, 8>(h, r, tasks, x, s);
   else
-    hipLaunchKernelGGL((k_solve_bwd<D, OPT>), dim3(r.nt), dim3(kBlock), 0, s, tasks, h->Prow, h->sidx, h->y, x,
-                       h->solve_part);
+    launch_bwd_block<D, OPT, 4>(h, r, tasks, x, s);
 }
 
 template <int D>
@@ -267,14 +312,43 @@ void launch_bwd_level(ffd_ctx* h, const LevelRun& r, double* x, hipStream_t s) {
                        h->solve_part);
 }
 
+// stream of group g (group 0 and the top levels run on the caller's stream)
+inline hipStream_t group_stream(ffd_ctx* h, int g, hipStream_t s) { return g == 0 ? s : h->wstreams[g - 1]; }
+
 template <int D>
 void launch_solve_fwd(ffd_ctx* h, const double* b, hipStream_t s) {
-  for (const LevelRun& r : h->run_fwd) launch_fwd_level<D>(h, r, b, s);
+  const int G = h->solve_groups, top = h->solve_top;
+  if (G > 1) {
+    (void)hipEventRecord(h->fork_ev[0], s);
+    for (int g = 1; g < G; ++g) (void)hipStreamWaitEvent(h->wstreams[g - 1], h->fork_ev[0], 0);
+  }
+  for (int l = 0; l < top; ++l)
+    for (int g = 0; g < G; ++g) launch_fwd_level<D>(h, h->grun_fwd[g][l], b, group_stream(h, g, s));
+  if (G > 1)
+    for (int g = 1; g < G; ++g) {
+      (void)hipEventRecord(h->join_ev[0][g], h->wstreams[g - 1]);
+      (void)hipStreamWaitEvent(s, h->join_ev[0][g], 0);
+    }
+  const int nlev = static_cast<int>(h->hlevels.size());
+  for (int l = top; l < nlev; ++l) launch_fwd_level<D>(h, h->grun_fwd[G][l], b, s);
 }
 
 template <int D>
 void launch_solve_bwd(ffd_ctx* h, double* x, hipStream_t s) {
-  for (auto it = h->run_bwd.rbegin(); it != h->run_bwd.rend(); ++it) launch_bwd_level<D>(h, *it, x, s);
+  const int G = h->solve_groups, top = h->solve_top;
+  const int nlev = static_cast<int>(h->hlevels.size());
+  for (int l = nlev - 1; l >= top; --l) launch_bwd_level<D>(h, h->grun_bwd[G][l], x, s);
+  if (G > 1) {
+    (void)hipEventRecord(h->fork_ev[1], s);
+    for (int g = 1; g < G; ++g) (void)hipStreamWaitEvent(h->wstreams[g - 1], h->fork_ev[1], 0);
+  }
+  for (int l = top - 1; l >= 0; --l)
+    for (int g = 0; g < G; ++g) launch_bwd_level<D>(h, h->grun_bwd[g][l], x, group_stream(h, g, s));
+  if (G > 1)
+    for (int g = 1; g < G; ++g) {
+      (void)hipEventRecord(h->join_ev[1][g], h->wstreams[g - 1]);
+      (void)hipStreamWaitEvent(s, h->join_ev[1][g], 0);
+    }
 }
 
 template <int D>
@@ -325,10 +399,13 @@ void do_solve(ffd_ctx* h, const double* b, double* x, hipStream_t s) {
 
 // one iteration of Algorithm 1; with ev != nullptr an event is recorded after
 // each of the five phases
-// store_u: write the rotation and |grad f|^2 of this iteration (3D, h = 0, reads
-// neither; they are state outputs, so the last iteration of a call and every
-// iteration whose state is saved store them)
-void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true, bool store_u = true) {
+// store_u: write the rotation and |grad f|^2 of this iteration even where the
+// next iteration does not read them (3D with h = 0); they are state outputs, so
+// the last iteration of a call and every iteration whose state is saved store
+// them (2D and h_mode 1 always store them)
+// dev_k: the history record index comes from the device counter (graph capture)
+void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true, bool store_u = true,
+                   bool dev_k = false) {
   double* xold = h->x[h->cur];
   double* xnew = h->x[1 - h->cur];
   do_wrhs(h, xnew, s);
@@ -345,14 +422,15 @@ void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true
   if (ev) (void)hipEventRecord(ev[2], s);
   do_local(h, xnew, xold, store_u ? 1 : 0, s);
   if (ev) (void)hipEventRecord(ev[3], s);
-  double* rec = record ? h->hist + h->k * FFD_HIST_FIELDS : h->hist_scratch;
+  double* rec = dev_k ? h->hist : record ? h->hist + h->k * FFD_HIST_FIELDS : h->hist_scratch;
+  int64_t* kd = dev_k ? h->k_dev : nullptr;
   if (h->nparts > 2 * kFinalizeRows) {
     const int64_t nb2 = (h->nparts + kFinalizeRows - 1) / kFinalizeRows;
     hipLaunchKernelGGL(k_partials_reduce, dim3(static_cast<unsigned>(nb2)), dim3(kBlock), 0, s, h->partials,
                        h->nparts, h->partials2);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials2, nb2, rec);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials2, nb2, rec, kd, FFD_HIST_FIELDS);
   } else {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials, h->nparts, rec);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials, h->nparts, rec, kd, FFD_HIST_FIELDS);
   }
   if (ev) (void)hipEventRecord(ev[4], s);
   h->cur = 1 - h->cur;
@@ -422,10 +500,34 @@ hipError_t upload_cap(ffd_ctx* h, T_** dst, size_t* cap, const std::vector<T_>& 
   return hipMemcpy(*dst, src.data(), src.size() * sizeof(T_), hipMemcpyHostToDevice);
 }
 
+// worker streams (default priority) and fork / join events for g groups
+hipError_t ensure_workers(ffd_ctx* h, int g) {
+  g = std::min(g, 8);
+  while (static_cast<int>(h->wstreams.size()) < g - 1) {
+    hipStream_t w = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&w, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    h->wstreams.push_back(w);
+  }
+  for (int p = 0; p < 2; ++p) {
+    if (!h->fork_ev[p]) {
+      hipError_t e = hipEventCreateWithFlags(&h->fork_ev[p], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    for (int i = 1; i < g; ++i)
+      if (!h->join_ev[p][i]) {
+        hipError_t e = hipEventCreateWithFlags(&h->join_ev[p][i], hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+      }
+  }
+  return hipSuccess;
+}
+
 // Builds the task lists of both passes from cfg_fwd / cfg_bwd (defaults for
 // levels without one) and uploads them.  Waits for the device first: the
 // task buffers may be in use by earlier launches.
 ffd_status build_solve_schedule(ffd_ctx* h) {
+  h->graph_valid = false;
   const size_t nlev = h->hlevels.size();
   if (h->cfg_fwd.size() != nlev || h->cfg_bwd.size() != nlev) {
     h->cfg_fwd.resize(nlev);
@@ -435,10 +537,6 @@ ffd_status build_solve_schedule(ffd_ctx* h) {
       h->cfg_bwd[l] = default_level_cfg(h, h->hlevels[l], false);
     }
   }
-  std::vector<SolveTask> tf, tb, rf, rb;
-  int64_t max_slots = 1;
-  h->run_fwd.assign(nlev, LevelRun{});
-  h->run_bwd.assign(nlev, LevelRun{});
   auto task_of = [&](const OutBlock& o, bool fwd, int32_t lo, int32_t hi, int32_t slot, int32_t nk) {
     const SolveNode& N = h->hnodes[o.node];
     const int32_t nf = N.c + N.r;
@@ -458,37 +556,85 @@ ffd_status build_solve_schedule(ffd_ctx* h) {
     t.nk = nk;
     return t;
   };
-  auto build = [&](size_t l, bool fwd, const LevelCfg& cfg, std::vector<SolveTask>& tasks,
-                   std::vector<SolveTask>& red, LevelRun& run) {
-    const std::vector<OutBlock> obs = level_blocks(h, h->hlevels[l], fwd, cfg.opt);
-    run.mode = cfg.mode;
-    run.opt = cfg.opt;
-    run.t0 = static_cast<int32_t>(tasks.size());
-    run.r0 = static_cast<int32_t>(red.size());
-    int32_t slots = 0;
-    for (const OutBlock& o : obs) {
-      const int64_t len = o.hi - o.lo;
-      const int32_t nk = (cfg.mode == 0 && cfg.chunk > 0) ? static_cast<int32_t>((len + cfg.chunk - 1) / cfg.chunk) : 1;
-      if (nk <= 1) {
-        tasks.push_back(task_of(o, fwd, o.lo, o.hi, -1, 1));
-        continue;
-      }
-      const int32_t base = slots;
-      slots += nk;
-      for (int32_t q = 0; q < nk; ++q)
-        tasks.push_back(task_of(o, fwd, static_cast<int32_t>(o.lo + q * cfg.chunk),
-                                static_cast<int32_t>(std::min<int64_t>(o.hi, o.lo + static_cast<int64_t>(q + 1) * cfg.chunk)),
-                                base + q, nk));
-      red.push_back(task_of(o, fwd, 0, cfg.opt, base, nk));  // hi: outputs of the block
+  // groups of the forest below solve_top: whole subtrees, balanced greedily
+  // by panel bytes (largest subtree first onto the lightest group)
+  const int G = std::max(1, std::min(h->solve_groups, 1 + static_cast<int>(h->wstreams.size())));
+  const int top = G > 1 ? std::max(0, std::min(h->solve_top, static_cast<int>(nlev))) : static_cast<int>(nlev);
+  const int nn = static_cast<int>(h->hnodes.size());
+  std::vector<int32_t> group(nn, G);
+  if (G == 1) {
+    std::fill(group.begin(), group.end(), 0);
+  } else {
+    std::vector<double> sub(nn, 0.0);
+    for (int i = 0; i < nn; ++i) {  // postorder: children before parents
+      const SolveNode& N = h->hnodes[i];
+      sub[i] += static_cast<double>(N.c + N.r) * N.c;
+      if (h->hparent[i] >= 0) sub[h->hparent[i]] += sub[i];
     }
-    run.nt = static_cast<int32_t>(tasks.size()) - run.t0;
-    run.nr = static_cast<int32_t>(red.size()) - run.r0;
-    max_slots = std::max<int64_t>(max_slots, slots);
-  };
-  for (size_t l = 0; l < nlev; ++l) {
-    build(l, true, h->cfg_fwd[l], tf, rf, h->run_fwd[l]);
-    build(l, false, h->cfg_bwd[l], tb, rb, h->run_bwd[l]);
+    std::vector<int32_t> roots;
+    for (int i = 0; i < nn; ++i)
+      if (h->hnodes[i].level < top && (h->hparent[i] < 0 || h->hnodes[h->hparent[i]].level >= top)) roots.push_back(i);
+    std::stable_sort(roots.begin(), roots.end(), [&](int32_t a, int32_t b) { return sub[a] > sub[b]; });
+    std::vector<double> load(G, 0.0);
+    for (int32_t r : roots) {
+      const int g = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+      group[r] = g;
+      load[g] += sub[r];
+    }
+    for (int i = nn - 1; i >= 0; --i)  // parents before children
+      if (h->hnodes[i].level < top && group[i] == G) group[i] = group[h->hparent[i]];
   }
+  std::vector<SolveTask> tf, tb, rf, rb;
+  int64_t total_slots = 1;
+  h->grun_fwd.assign(G + 1, std::vector<LevelRun>(nlev));
+  h->grun_bwd.assign(G + 1, std::vector<LevelRun>(nlev));
+  for (int g = 0; g <= G; ++g) {
+    int64_t gmax = 0;  // slots of this group: reused level by level, disjoint from other groups
+    for (size_t l = 0; l < nlev; ++l) {
+      if ((g < G) != (static_cast<int>(l) < top)) continue;
+      std::vector<int32_t> nodes;
+      for (int32_t i : h->hlevels[l])
+        if (group[i] == g) nodes.push_back(i);
+      if (nodes.empty()) continue;
+      for (int pass = 0; pass < 2; ++pass) {
+        const bool fwd = pass == 0;
+        const LevelCfg& cfg = fwd ? h->cfg_fwd[l] : h->cfg_bwd[l];
+        std::vector<SolveTask>& tasks = fwd ? tf : tb;
+        std::vector<SolveTask>& red = fwd ? rf : rb;
+        LevelRun& run = fwd ? h->grun_fwd[g][l] : h->grun_bwd[g][l];
+        const std::vector<OutBlock> obs = level_blocks(h, nodes, fwd, cfg.opt);
+        run.mode = cfg.mode;
+        run.opt = cfg.opt;
+        run.nw = cfg.nw;
+        run.t0 = static_cast<int32_t>(tasks.size());
+        run.r0 = static_cast<int32_t>(red.size());
+        int32_t slots = 0;
+        const int32_t base = static_cast<int32_t>(total_slots);
+        for (const OutBlock& o : obs) {
+          const int64_t len = o.hi - o.lo;
+          const int32_t nk = (cfg.mode == 0 && cfg.chunk > 0) ? static_cast<int32_t>((len + cfg.chunk - 1) / cfg.chunk) : 1;
+          if (nk <= 1) {
+            tasks.push_back(task_of(o, fwd, o.lo, o.hi, -1, 1));
+            continue;
+          }
+          const int32_t b0 = base + slots;
+          slots += nk;
+          for (int32_t q = 0; q < nk; ++q)
+            tasks.push_back(task_of(o, fwd, static_cast<int32_t>(o.lo + q * cfg.chunk),
+                                    static_cast<int32_t>(std::min<int64_t>(o.hi, o.lo + static_cast<int64_t>(q + 1) * cfg.chunk)),
+                                    b0 + q, nk));
+          red.push_back(task_of(o, fwd, 0, cfg.opt, b0, nk));  // hi: outputs of the block
+        }
+        run.nt = static_cast<int32_t>(tasks.size()) - run.t0;
+        run.nr = static_cast<int32_t>(red.size()) - run.r0;
+        gmax = std::max<int64_t>(gmax, slots);
+      }
+    }
+    total_slots += gmax;
+  }
+  const int64_t max_slots = total_slots;
+  h->solve_groups = G;
+  h->solve_top = top;
   if (hipDeviceSynchronize() != hipSuccess) return fail(FFD_ERR_DEVICE, "device error before a schedule upload");
   bool ok = upload_cap(h, &h->tasks_fwd, &h->cap_tf, tf) == hipSuccess &&
             upload_cap(h, &h->tasks_bwd, &h->cap_tb, tb) == hipSuccess &&
@@ -761,6 +907,10 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
     h->hpoff = poff;
     h->hnodes = S.nodes;
     h->hlevels = S.level_nodes;
+    h->hparent.assign(S.nodes.size(), -1);
+    for (size_t i = 0; i < S.children.size(); ++i)
+      for (int32_t ch : S.children[i]) h->hparent[ch] = static_cast<int32_t>(i);
+    h->solve_top = static_cast<int>(S.level_nodes.size());
     if (build_solve_schedule(h) != FFD_OK) return cleanup(FFD_ERR_OUT_OF_MEMORY);
   }
   UP(upload(h, &h->sidx, S.struct_idx));
@@ -972,6 +1122,74 @@ ffd_status ffd_iterate(ffd_handle h, int32_t n_iter, void* stream) {
   ffd_status st = ensure_hist(h, h->k + n_iter, s);
   if (st != FFD_OK) return st;
   for (int32_t it = 0; it < n_iter; ++it) one_iteration(h, s, nullptr, true, it == n_iter - 1);
+  HIP_TRY(hipGetLastError());
+  h->last_stream = s;
+  return FFD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Captures two iterations (so the two map buffers return to their roles) on
+// the handle's own stream; history records are addressed through the device
+// counter.  Host bookkeeping changed by the capture is restored.
+ffd_status capture_graph(ffd_ctx* h) {
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->graph_exec = nullptr;
+  h->graph = nullptr;
+  h->graph_valid = false;
+  if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  if (!h->k_dev) HIP_TRY(h->alloc(&h->k_dev, 1));
+  const int cur0 = h->cur;
+  const int64_t k0 = h->k;
+  HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  one_iteration(h, h->cap_stream, nullptr, true, true, true);
+  one_iteration(h, h->cap_stream, nullptr, true, true, true);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  h->cur = cur0;
+  h->k = k0;
+  if (e != hipSuccess || !g) return fail(FFD_ERR_DEVICE, "graph capture failed");
+  h->graph = g;
+  HIP_TRY(hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0));
+  h->graph_cur = cur0;
+  h->graph_hist = h->hist;
+  h->graph_valid = true;
+  return FFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ffd_status ffd_iterate_graph(ffd_handle h, int32_t n_iter, void* stream) {
+  if (!h) return fail(FFD_ERR_INVALID_ARG, "NULL handle");
+  if (!h->initialized) return fail(FFD_ERR_STATE, "ffd_iterate_graph before ffd_init / ffd_set_state");
+  if (n_iter < 0) return fail(FFD_ERR_INVALID_ARG, "negative iteration count");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ffd_status st = ensure_hist(h, h->k + n_iter, s);
+  if (st != FFD_OK) return st;
+  int32_t n = n_iter;
+  if (n >= 2) {
+    if (!h->graph_valid || h->graph_hist != h->hist) {
+      st = capture_graph(h);
+      if (st != FFD_OK) return st;
+    }
+    if (h->cur != h->graph_cur) {
+      one_iteration(h, s, nullptr, true, false);
+      --n;
+    }
+    const int32_t reps = n / 2;
+    if (reps > 0) {
+      hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, s, h->k_dev, h->k);
+      for (int32_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(h->graph_exec, s));
+      h->k += 2 * static_cast<int64_t>(reps);
+      n -= 2 * reps;
+    }
+  }
+  for (int32_t it = 0; it < n; ++it) one_iteration(h, s, nullptr, true, it == n - 1);
   HIP_TRY(hipGetLastError());
   h->last_stream = s;
   return FFD_OK;
@@ -1285,7 +1503,7 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
   hipStream_t s = static_cast<hipStream_t>(stream);
   const std::string key = tune_key(h);
   const size_t nlev = h->hlevels.size();
-  int bs = 0, lpr = 0;
+  int bs = 0, lpr = 0, groups = 1, topl = static_cast<int>(nlev);
   std::vector<LevelCfg> cf, cb;
   bool cached = false;
   if (cache_path) {
@@ -1300,16 +1518,21 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
         std::string k;
         int b2 = 0, l2 = 0;
         size_t n2 = 0;
-        if (!(in >> k >> b2 >> l2 >> n2) || k != key || n2 != nlev) continue;
-        std::vector<LevelCfg> f2(nlev), g2(nlev);
-        bool good = true;
-        for (size_t l = 0; l < nlev && good; ++l) good = static_cast<bool>(in >> f2[l].mode >> f2[l].opt >> f2[l].chunk);
-        for (size_t l = 0; l < nlev && good; ++l) good = static_cast<bool>(in >> g2[l].mode >> g2[l].opt >> g2[l].chunk);
+        int g2 = 1, t2 = 0;
+        if (!(in >> k >> b2 >> l2 >> n2 >> g2 >> t2) || k != key || n2 != nlev) continue;
+        std::vector<LevelCfg> f2(nlev), h2(nlev);
+        bool good = g2 >= 1 && g2 <= 8 && t2 >= 0 && t2 <= static_cast<int>(nlev);
+        for (size_t l = 0; l < nlev && good; ++l)
+          good = static_cast<bool>(in >> f2[l].mode >> f2[l].opt >> f2[l].chunk >> f2[l].nw);
+        for (size_t l = 0; l < nlev && good; ++l)
+          good = static_cast<bool>(in >> h2[l].mode >> h2[l].opt >> h2[l].chunk >> h2[l].nw);
         if (!good) continue;
         bs = b2;
         lpr = l2;
         cf = f2;
-        cb = g2;
+        cb = h2;
+        groups = g2;
+        topl = t2;
         cached = true;
       }
       std::fclose(f);
@@ -1318,7 +1541,7 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
   // a configuration read from a file is checked before use
   auto valid = [](const LevelCfg& c) {
     return (c.mode == 0 || c.mode == 1) && (c.opt == 16 || c.opt == 32 || c.opt == 64) && c.chunk >= 0 &&
-           (c.mode == 0 || c.chunk == 0);
+           (c.mode == 0 || c.chunk == 0) && (c.nw == 4 || c.nw == 8 || c.nw == 16);
   };
   for (size_t l = 0; l < cf.size() && cached; ++l) cached = valid(cf[l]) && valid(cb[l]);
   if (!cached) {
@@ -1340,6 +1563,7 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
     best = 1e300;
     for (int cand : {4, 2, 8}) {
       h->wrhs_lpr = cand;
+      h->graph_valid = false;
       const double t = time_phase(h, s, 0, iters);
       if (t < best) {
         best = t;
@@ -1350,6 +1574,7 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
     // solve levels one at a time, both passes, from the default schedule
     h->cfg_fwd.clear();
     h->cfg_bwd.clear();
+    h->solve_groups = 1;
     ffd_status st = build_solve_schedule(h);
     if (st != FFD_OK) return st;
     for (int pass = 0; pass < 2; ++pass) {
@@ -1361,9 +1586,11 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
           max_inner = std::max<int64_t>(max_inner, o.hi - o.lo);
         std::vector<LevelCfg> cands;
         for (int opt : {64, 32, 16}) {
-          if (max_inner <= 1024) cands.push_back(LevelCfg{1, opt, 0});
-          for (int chunk : {0, 2048, 1024, 512, 256})
-            if (chunk == 0 || chunk < max_inner) cands.push_back(LevelCfg{0, opt, chunk});
+          if (max_inner <= 1024) cands.push_back(LevelCfg{1, opt, 0, 4});
+          for (int nw : {4, 8, 16})
+            for (int chunk : {0, 2048, 1024, 512, 256})
+              if ((chunk == 0 || chunk < max_inner) && (nw == 4 || chunk == 0 || chunk >= 1024))
+                cands.push_back(LevelCfg{0, opt, chunk, nw});
         }
         const LevelCfg keep = cfg[l];
         LevelCfg bestc = keep;
@@ -1383,14 +1610,34 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
     }
     cf = h->cfg_fwd;
     cb = h->cfg_bwd;
+    // then the forest below a top level split over 2..4 streams
+    double tbest = time_solve_pass(h, s, true, 3) + time_solve_pass(h, s, false, 3);
+    groups = 1;
+    topl = static_cast<int>(nlev);
+    HIP_TRY(ensure_workers(h, 4));
+    for (int g = 2; g <= 4; ++g)
+      for (int t = static_cast<int>(nlev) - 1; t >= std::max(1, static_cast<int>(nlev) - 6); --t) {
+        h->solve_groups = g;
+        h->solve_top = t;
+        st = build_solve_schedule(h);
+        if (st != FFD_OK) return st;
+        const double tt = time_solve_pass(h, s, true, 3) + time_solve_pass(h, s, false, 3);
+        if (tt < tbest) {
+          tbest = tt;
+          groups = g;
+          topl = t;
+        }
+      }
+    h->solve_groups = groups;
+    h->solve_top = topl;
     st = build_solve_schedule(h);
     if (st != FFD_OK) return st;
     HIP_TRY(load_state(h, h->adj_fin, s));
     if (cache_path) {
       if (FILE* f = std::fopen(cache_path, "a")) {
-        std::fprintf(f, "%s %d %d %zu", key.c_str(), bs, lpr, nlev);
-        for (const LevelCfg& c : cf) std::fprintf(f, " %d %d %d", c.mode, c.opt, c.chunk);
-        for (const LevelCfg& c : cb) std::fprintf(f, " %d %d %d", c.mode, c.opt, c.chunk);
+        std::fprintf(f, "%s %d %d %zu %d %d", key.c_str(), bs, lpr, nlev, groups, topl);
+        for (const LevelCfg& c : cf) std::fprintf(f, " %d %d %d %d", c.mode, c.opt, c.chunk, c.nw);
+        for (const LevelCfg& c : cb) std::fprintf(f, " %d %d %d %d", c.mode, c.opt, c.chunk, c.nw);
         std::fprintf(f, "\n");
         std::fclose(f);
       }
@@ -1400,8 +1647,12 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
   if (lpr != 2 && lpr != 4 && lpr != 8) lpr = 4;
   set_local_block(h, bs);
   h->wrhs_lpr = lpr;
+  h->graph_valid = false;
   h->cfg_fwd = cf;
   h->cfg_bwd = cb;
+  HIP_TRY(ensure_workers(h, groups));
+  h->solve_groups = groups;
+  h->solve_top = topl;
   ffd_status st = build_solve_schedule(h);
   if (st != FFD_OK) return st;
   HIP_TRY(hipStreamSynchronize(s));
@@ -1416,6 +1667,8 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
     choice_out[1] = lpr;
     choice_out[2] = wave;
     choice_out[3] = split;
+    choice_out[4] = h->solve_groups;
+    choice_out[5] = h->solve_top;
   }
   h->last_stream = s;
   return FFD_OK;

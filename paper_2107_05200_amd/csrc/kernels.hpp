@@ -424,9 +424,10 @@ __global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const in
 //
 // The lanes of a wave sit on OPT consecutive OUTPUTS (OPT = 64, 32 or 16,
 // chosen per level so that the level offers enough blocks) times 64 / OPT
-// inner streams; the four waves of a block add streams, so a block runs
-// NS = 256 / OPT interleaved streams over its inner range and every wave load
-// reads 64 / OPT runs of OPT contiguous doubles (whole 128-byte lines).  The
+// inner streams; the NW waves of a block (4, 8 or 16) add streams, so a block
+// runs NS = NW * 64 / OPT interleaved streams over its inner range and every
+// wave load reads 64 / OPT runs of OPT contiguous doubles (whole 128-byte
+// lines).  The
 // forward reads a column-major copy of the panel (column length ldc = nf
 // rounded up to even), the backward a row-major copy (row length ldr = c
 // rounded up to even).  The first batch of panel loads is issued before the
@@ -516,9 +517,9 @@ __device__ __forceinline__ void solve_stream(const double* __restrict base, int6
 }
 
 // sum of the NS streams of each output in stream order; valid for threads < OPT
-template <int D, int OPT>
+template <int D, int OPT, int NW>
 __device__ __forceinline__ void solve_streams_sum(double (&acc)[D], int o, int st) {
-  constexpr int NS = 4 * (64 / OPT);
+  constexpr int NS = NW * (64 / OPT);
   __shared__ double red[NS][OPT][D];
 #pragma unroll
   for (int k = 0; k < D; ++k) red[st][o][k] = acc[k];
@@ -534,14 +535,14 @@ __device__ __forceinline__ void solve_streams_sum(double (&acc)[D], int o, int s
   }
 }
 
-template <int D, int OPT>
-__global__ __launch_bounds__(kBlock) void k_solve_fwd(const SolveTask* __restrict tasks,
-                                                      const double* __restrict Pcol,
-                                                      const int32_t* __restrict pull_ptr,
-                                                      const int32_t* __restrict pull_idx, const double* __restrict b,
-                                                      double* __restrict y, double* __restrict ub,
-                                                      double* __restrict part) {
-  constexpr int NS = 4 * (64 / OPT);
+template <int D, int OPT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_solve_fwd(const SolveTask* __restrict tasks,
+                                                       const double* __restrict Pcol,
+                                                       const int32_t* __restrict pull_ptr,
+                                                       const int32_t* __restrict pull_idx, const double* __restrict b,
+                                                       double* __restrict y, double* __restrict ub,
+                                                       double* __restrict part) {
+  constexpr int NS = NW * (64 / OPT);
   __shared__ double vs[kSolveKC][D];
   const SolveTask tk = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -553,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd(const SolveTask* __restric
   for (int k = 0; k < D; ++k) cv[k] = acc[k] = 0.0;
   if (tk.slot < 0 && threadIdx.x < OPT && live && i >= tk.c) fwd_carried<D>(tk, i, pull_ptr, pull_idx, ub, cv);
   auto stage = [&](int j0, int jn) {
-    for (int t = threadIdx.x; t < jn; t += kBlock) {
+    for (int t = threadIdx.x; t < jn; t += NW * 64) {
       const int p = j0 + t;
       double a[D];
 #pragma unroll
@@ -564,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd(const SolveTask* __restric
     }
   };
   solve_stream<D, NS>(Pcol + tk.pf + i, tk.ld, live, tk.lo, tk.hi, st, vs, acc, stage);
-  solve_streams_sum<D, OPT>(acc, o, st);
+  solve_streams_sum<D, OPT, NW>(acc, o, st);
   if (threadIdx.x >= OPT || !live) return;
   if (tk.slot >= 0) {
 #pragma unroll
@@ -599,12 +600,12 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd_reduce(const SolveTask* __
   fwd_store<D>(tk, i, acc, y, ub);
 }
 
-template <int D, int OPT>
-__global__ __launch_bounds__(kBlock) void k_solve_bwd(const SolveTask* __restrict tasks,
-                                                      const double* __restrict Prow, const int32_t* __restrict sidx,
-                                                      const double* __restrict y, double* __restrict x,
-                                                      double* __restrict part) {
-  constexpr int NS = 4 * (64 / OPT);
+template <int D, int OPT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_solve_bwd(const SolveTask* __restrict tasks,
+                                                       const double* __restrict Prow, const int32_t* __restrict sidx,
+                                                       const double* __restrict y, double* __restrict x,
+                                                       double* __restrict part) {
+  constexpr int NS = NW * (64 / OPT);
   __shared__ double vs[kSolveKC][D];
   const SolveTask tk = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -615,7 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_bwd(const SolveTask* __restric
 #pragma unroll
   for (int k = 0; k < D; ++k) acc[k] = 0.0;
   auto stage = [&](int p0, int pn) {
-    for (int t = threadIdx.x; t < pn; t += kBlock) {
+    for (int t = threadIdx.x; t < pn; t += NW * 64) {
       const int p = p0 + t;
       const int64_t src = p < tk.c ? static_cast<int64_t>(tk.first + p) : static_cast<int64_t>(sidx[tk.soff + p - tk.c]);
       const double* vsrc = p < tk.c ? y : x;
@@ -624,7 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_bwd(const SolveTask* __restric
     }
   };
   solve_stream<D, NS>(Prow + tk.pf + j, tk.ld, live, tk.lo, tk.hi, st, vs, acc, stage);
-  solve_streams_sum<D, OPT>(acc, o, st);
+  solve_streams_sum<D, OPT, NW>(acc, o, st);
   if (threadIdx.x >= OPT || !live) return;
   if (tk.slot >= 0) {
 #pragma unroll
@@ -919,7 +920,7 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
         res2 += static_cast<double>(dv + ln) * (dv + ln);
         finite = finite && (ln - ln == R(0));
       }
-    if (D == 2 || store_u) store_U<D, R>(U, m, e, Ur);
+    if (D == 2 || h_mode == 1 || store_u) store_U<D, R>(U, m, e, Ur);
     store_P<D, R>(P, m, e, Pm);
 #pragma unroll
     for (int i = 0; i < D * D; ++i) Lam[i * m + e] = L[i / D][i % D];
@@ -965,9 +966,12 @@ __global__ __launch_bounds__(kBlock) void k_partials_reduce(const double* __rest
   block_reduce_store<kNumPartials>(v, out + static_cast<int64_t>(blockIdx.x) * kNumPartials);
 }
 
-// fixed-order reduction of the block partials into one history record
+// fixed-order reduction of the block partials into one history record: at
+// hist, or (k_dev != nullptr) at record *k_dev of hist, after which *k_dev is
+// advanced (an iteration counter kept on the device for replayed graphs)
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict partials, int64_t nb,
-                                                     double* __restrict hist) {
+                                                     double* __restrict hist, int64_t* __restrict k_dev,
+                                                     int fields) {
   double v[kNumPartials];
 #pragma unroll
   for (int f = 0; f < kNumPartials; ++f) v[f] = 0.0;
@@ -978,6 +982,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict pa
   block_reduce_store<kNumPartials>(v, out);
   __syncthreads();
   if (threadIdx.x == 0) {
+    if (k_dev) hist += *k_dev * fields;
     const double flips = out[5];
     hist[0] = sqrt(out[0]);
     hist[1] = sqrt(out[1]);
@@ -989,7 +994,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict pa
     hist[7] = sqrt(out[7]);
     hist[8] = sqrt(out[8]);
     hist[9] = __longlong_as_double(0x7ff8000000000000LL);
+    if (k_dev) *k_dev += 1;
   }
+}
+
+__global__ void k_set_counter(int64_t* __restrict p, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 // ---------------------------------------------------------------------------

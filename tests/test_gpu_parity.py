@@ -250,3 +250,29 @@ def test_pins_change_between_iterations(gpu_lib):
     st = g.get_state()
     torch.cuda.synchronize()
     assert rel(host(st["map"]), r.x) < 1e-8
+
+
+@pytest.mark.parametrize("h_mode", [0, 1])
+def test_cube_fp64_multi_iteration_calls(gpu_lib, h_mode):
+    """Twelve float64 iterations of a tet cube in one call and in twelve calls
+    against the oracle: how iterations are grouped into calls is invisible
+    (bitwise), and the map and W_el follow the oracle to 1e-9 (the proximal
+    term of h_mode 1 reads the previous rotation every iteration)."""
+    import torch
+    w = mg.twisted_cube(6)
+    say(f"case: cube6 fp64 h_mode={h_mode} 12 iterations, one call vs twelve calls")
+    a = make(w, 64, h_mode)
+    a.init(w.x0).iterate(12)
+    b = make(w, 64, h_mode)
+    b.init(w.x0)
+    for _ in range(12):
+        b.iterate(1)
+    sa, sb = a.get_state(), b.get_state()
+    torch.cuda.synchronize()
+    for k in sa:
+        assert np.array_equal(host(sa[k]), host(sb[k]), equal_nan=True), k
+    r = oracle_for(w, h_mode)
+    r.iterate(12)
+    ex, ew = rel(host(sa["map"]), r.x), rel(host(sa["Wel"]), r.wel())
+    say(f"  rel err map {ex:.2e} Wel {ew:.2e}")
+    assert ex < 1e-9 and ew < 1e-9

@@ -235,15 +235,16 @@ ffd_status ffd_adjoint_backward(ffd_handle h, const void* Pbar_dev, int32_t ener
  * block size (64 / 128 / 256 elements), the lanes per vertex row of the
  * right-hand side (2 / 4 / 8); level by level for both triangular-solve
  * passes, the task shape (blocks of 4 / 8 / 16 waves or one wave per task,
- * 64 / 32 / 16 outputs per task, inner-range splitting: none, 2048 .. 256);
- * and the
+ * 64 / 32 / 16 outputs per task, inner-range splitting: none, 2048 .. 256,
+ * with the partials added right away or, for forward blocks of y rows, by
+ * the backward pass); and the
  * number of streams (1 .. 4, the caller's stream plus streams of the handle,
  * all of default priority) over which the subtrees below a top level are
  * spread.  With cache_path (may be NULL) the choice is read from / appended
  * to a text file, one line per key "arch|d|energy|precision|element
  * bucket|factor bucket|levels|h" followed by the block size, lanes per row,
- * level count, stream count, top level and four numbers (mode, outputs,
- * chunk, waves) per level and pass.  choice_out (may be NULL): 6 int32 (block size,
+ * level count, stream count, top level and five numbers (mode, outputs,
+ * chunk, waves, deferred) per level and pass.  choice_out (may be NULL): 6 int32 (block size,
  * lanes per row, solve levels run one wave per task, solve levels with split
  * inner ranges (both passes counted), streams, top level).  Element results
  * do not depend on the choice; history sums and the solve's rounding order

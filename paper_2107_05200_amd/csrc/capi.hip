@@ -46,15 +46,20 @@ inline unsigned nblk(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) 
 
 // Launch configuration of one solve level of one pass: mode 0 = blocks of nw
 // waves per task, 1 = one wave per task; opt = outputs per task (64, 32, 16);
-// chunk > 0 splits inner ranges longer than chunk (block mode only).
+// chunk > 0 splits inner ranges longer than chunk (block mode only); the
+// partials are added right after the level, or (forward, defer) only for
+// blocks of y rows, by the backward pass.
 struct LevelCfg {
   int32_t mode = 0, opt = 64, chunk = 0, nw = 4;  // nw: waves per block (block mode: 4, 8, 16)
+  int32_t defer = 0;  // forward only: split y-row blocks only and add their partials in the backward pass
   bool operator==(const LevelCfg& o) const {
-    return mode == o.mode && opt == o.opt && chunk == o.chunk && nw == o.nw;
+    return mode == o.mode && opt == o.opt && chunk == o.chunk && nw == o.nw && defer == o.defer;
   }
 };
 struct LevelRun {
   int32_t mode = 0, opt = 64, nw = 4, t0 = 0, nt = 0, r0 = 0, nr = 0;  // tasks [t0, t0+nt), reductions [r0, r0+nr)
+  int32_t y0 = 0, ny = 0;  // backward runs: pending forward y-row reductions [y0, y0+ny) of yred
+  bool reduce_now = true;  // forward runs: add the split partials right after the level
 };
 
 struct ffd_ctx {
@@ -115,6 +120,9 @@ struct ffd_ctx {
   int32_t *sidx = nullptr, *pull_ptr = nullptr, *pull_idx = nullptr;
   SolveTask *tasks_fwd = nullptr, *tasks_bwd = nullptr, *red_fwd = nullptr, *red_bwd = nullptr;
   size_t cap_tf = 0, cap_tb = 0, cap_rf = 0, cap_rb = 0, cap_slots = 0;  // capacities (entries)
+  SolveTask* yred = nullptr;  // forward y-row reductions, in the order the backward launches run them
+  double* fpart = nullptr;    // forward split partials (kept until the backward pass adds them)
+  size_t cap_yr = 0, cap_fslots = 0;
   double* solve_part = nullptr;                   // split-K partials (reused level by level)
   int64_t device_bytes = 0;
   std::vector<void*> allocs;
@@ -251,13 +259,14 @@ void launch_wrhs(ffd_ctx* h, double* xnew, hipStream_t s) {
 template <int D, int OPT, int NW>
 void launch_fwd_block(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, const double* b, hipStream_t s) {
   hipLaunchKernelGGL((k_solve_fwd<D, OPT, NW>), dim3(r.nt), dim3(NW * 64), 0, s, tasks, h->Pcol, h->pull_ptr,
-                     h->pull_idx, b, h->y, h->ub, h->solve_part);
+                     h->pull_idx, b, h->y, h->ub, h->fpart);
 }
 
 template <int D, int OPT, int NW>
 void launch_bwd_block(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, double* x, hipStream_t s) {
-  hipLaunchKernelGGL((k_solve_bwd<D, OPT, NW>), dim3(r.nt), dim3(NW * 64), 0, s, tasks, h->Prow, h->sidx, h->y, x,
-                     h->solve_part);
+  const int grid = r.nt + (r.ny + NW - 1) / NW;
+  hipLaunchKernelGGL((k_solve_bwd<D, OPT, NW>), dim3(grid), dim3(NW * 64), 0, s, tasks, r.nt, h->Prow, h->sidx, h->y,
+                     x, h->solve_part, h->yred + r.y0, r.ny, h->fpart);
 }
 
 template <int D, int OPT>
@@ -276,8 +285,8 @@ void launch_fwd_opt(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, const
 template <int D, int OPT>
 void launch_bwd_opt(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, double* x, hipStream_t s) {
   if (r.mode == 1)
-    hipLaunchKernelGGL((k_solve_bwd_wave<D, OPT>), dim3((r.nt + 3) / 4), dim3(kBlock), 0, s, tasks, r.nt, h->Prow,
-                       h->sidx, h->y, x);
+    hipLaunchKernelGGL((k_solve_bwd_wave<D, OPT>), dim3((r.nt + r.ny + 3) / 4), dim3(kBlock), 0, s, tasks, r.nt,
+                       h->Prow, h->sidx, h->y, x, h->yred + r.y0, r.ny, h->fpart);
   else if (r.nw == 16)
     launch_bwd_block<D, OPT, 16>(h, r, tasks, x, s);
   else if (r.nw == 8)
@@ -286,23 +295,24 @@ void launch_bwd_opt(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, doubl
     launch_bwd_block<D, OPT, 4>(h, r, tasks, x, s);
 }
 
+// reduce: add the split partials now (otherwise a backward launch adds them)
 template <int D>
-void launch_fwd_level(ffd_ctx* h, const LevelRun& r, const double* b, hipStream_t s) {
+void launch_fwd_level(ffd_ctx* h, const LevelRun& r, const double* b, hipStream_t s, bool reduce) {
   const SolveTask* tasks = h->tasks_fwd + r.t0;
   if (r.nt > 0) {
     if (r.opt == 16) launch_fwd_opt<D, 16>(h, r, tasks, b, s);
     else if (r.opt == 32) launch_fwd_opt<D, 32>(h, r, tasks, b, s);
     else launch_fwd_opt<D, 64>(h, r, tasks, b, s);
   }
-  if (r.nr > 0)
+  if (reduce && r.nr > 0)
     hipLaunchKernelGGL((k_solve_fwd_reduce<D>), dim3((r.nr + 3) / 4), dim3(kBlock), 0, s, h->red_fwd + r.r0, r.nr,
-                       h->pull_ptr, h->pull_idx, h->y, h->ub, h->solve_part);
+                       h->pull_ptr, h->pull_idx, h->y, h->ub, h->fpart);
 }
 
 template <int D>
 void launch_bwd_level(ffd_ctx* h, const LevelRun& r, double* x, hipStream_t s) {
   const SolveTask* tasks = h->tasks_bwd + r.t0;
-  if (r.nt > 0) {
+  if (r.nt > 0 || r.ny > 0) {
     if (r.opt == 16) launch_bwd_opt<D, 16>(h, r, tasks, x, s);
     else if (r.opt == 32) launch_bwd_opt<D, 32>(h, r, tasks, x, s);
     else launch_bwd_opt<D, 64>(h, r, tasks, x, s);
@@ -322,15 +332,16 @@ void launch_solve_fwd(ffd_ctx* h, const double* b, hipStream_t s) {
     (void)hipEventRecord(h->fork_ev[0], s);
     for (int g = 1; g < G; ++g) (void)hipStreamWaitEvent(h->wstreams[g - 1], h->fork_ev[0], 0);
   }
+  const int nlev = static_cast<int>(h->hlevels.size());
   for (int l = 0; l < top; ++l)
-    for (int g = 0; g < G; ++g) launch_fwd_level<D>(h, h->grun_fwd[g][l], b, group_stream(h, g, s));
+    for (int g = 0; g < G; ++g)
+      launch_fwd_level<D>(h, h->grun_fwd[g][l], b, group_stream(h, g, s), h->grun_fwd[g][l].reduce_now);
   if (G > 1)
     for (int g = 1; g < G; ++g) {
       (void)hipEventRecord(h->join_ev[0][g], h->wstreams[g - 1]);
       (void)hipStreamWaitEvent(s, h->join_ev[0][g], 0);
     }
-  const int nlev = static_cast<int>(h->hlevels.size());
-  for (int l = top; l < nlev; ++l) launch_fwd_level<D>(h, h->grun_fwd[G][l], b, s);
+  for (int l = top; l < nlev; ++l) launch_fwd_level<D>(h, h->grun_fwd[G][l], b, s, h->grun_fwd[G][l].reduce_now);
 }
 
 template <int D>
@@ -585,7 +596,8 @@ ffd_status build_solve_schedule(ffd_ctx* h) {
       if (h->hnodes[i].level < top && group[i] == G) group[i] = group[h->hparent[i]];
   }
   std::vector<SolveTask> tf, tb, rf, rb;
-  int64_t total_slots = 1;
+  int64_t total_slots = 1;  // backward split partials: per group, reused level by level
+  int64_t fslots = 1;       // forward split partials: kept until the backward pass
   h->grun_fwd.assign(G + 1, std::vector<LevelRun>(nlev));
   h->grun_bwd.assign(G + 1, std::vector<LevelRun>(nlev));
   for (int g = 0; g <= G; ++g) {
@@ -609,10 +621,14 @@ ffd_status build_solve_schedule(ffd_ctx* h) {
         run.t0 = static_cast<int32_t>(tasks.size());
         run.r0 = static_cast<int32_t>(red.size());
         int32_t slots = 0;
-        const int32_t base = static_cast<int32_t>(total_slots);
+        const int32_t base = static_cast<int32_t>(fwd ? fslots : total_slots);
         for (const OutBlock& o : obs) {
           const int64_t len = o.hi - o.lo;
-          const int32_t nk = (cfg.mode == 0 && cfg.chunk > 0) ? static_cast<int32_t>((len + cfg.chunk - 1) / cfg.chunk) : 1;
+          // forward: only blocks of y rows split (update rows feed the parents
+          // within the pass and stay whole)
+          const bool may_split =
+              cfg.mode == 0 && cfg.chunk > 0 && (!fwd || !cfg.defer || o.out0 + cfg.opt <= h->hnodes[o.node].c);
+          const int32_t nk = may_split ? static_cast<int32_t>((len + cfg.chunk - 1) / cfg.chunk) : 1;
           if (nk <= 1) {
             tasks.push_back(task_of(o, fwd, o.lo, o.hi, -1, 1));
             continue;
@@ -627,19 +643,55 @@ ffd_status build_solve_schedule(ffd_ctx* h) {
         }
         run.nt = static_cast<int32_t>(tasks.size()) - run.t0;
         run.nr = static_cast<int32_t>(red.size()) - run.r0;
-        gmax = std::max<int64_t>(gmax, slots);
+        run.reduce_now = !fwd || !cfg.defer || l + 1 == nlev;
+        if (fwd) fslots += slots;
+        else gmax = std::max<int64_t>(gmax, slots);
       }
     }
     total_slots += gmax;
   }
   const int64_t max_slots = total_slots;
+  // forward y-row reductions of level l run in the backward launch of level
+  // l + 1 of the same stream group; those of the forest groups' level top - 1
+  // in the top group's launch of level top (before the fork); the highest
+  // level's in a launch of their own at the end of the forward pass
+  std::vector<SolveTask> yr;
+  auto attach = [&](LevelRun& br, int gsrc, size_t lsrc) {
+    const LevelRun& fr = h->grun_fwd[gsrc][lsrc];
+    if (fr.reduce_now) return;
+    for (int32_t q = 0; q < fr.nr; ++q) yr.push_back(rf[fr.r0 + q]);
+    br.ny += fr.nr;
+  };
+  for (int g = 0; g <= G; ++g)
+    for (size_t l = 1; l < nlev; ++l) {
+      if ((g < G) != (static_cast<int>(l) < top)) continue;
+      LevelRun& br = h->grun_bwd[g][l];
+      br.y0 = static_cast<int32_t>(yr.size());
+      br.ny = 0;
+      if (g == G && static_cast<int>(l) == top) {
+        for (int gf = 0; gf < G; ++gf) attach(br, gf, l - 1);
+      } else {
+        attach(br, g, l - 1);
+      }
+    }
   h->solve_groups = G;
   h->solve_top = top;
   if (hipDeviceSynchronize() != hipSuccess) return fail(FFD_ERR_DEVICE, "device error before a schedule upload");
   bool ok = upload_cap(h, &h->tasks_fwd, &h->cap_tf, tf) == hipSuccess &&
             upload_cap(h, &h->tasks_bwd, &h->cap_tb, tb) == hipSuccess &&
             upload_cap(h, &h->red_fwd, &h->cap_rf, rf) == hipSuccess &&
-            upload_cap(h, &h->red_bwd, &h->cap_rb, rb) == hipSuccess;
+            upload_cap(h, &h->red_bwd, &h->cap_rb, rb) == hipSuccess &&
+            upload_cap(h, &h->yred, &h->cap_yr, yr) == hipSuccess;
+  if (ok && static_cast<size_t>(fslots) > h->cap_fslots) {
+    if (h->fpart) {
+      for (auto& a : h->allocs)
+        if (a == h->fpart) a = nullptr;
+      (void)hipFree(h->fpart);
+      h->fpart = nullptr;
+    }
+    ok = h->alloc(&h->fpart, static_cast<size_t>(fslots) * kSolveOutMax * h->d) == hipSuccess;
+    h->cap_fslots = ok ? static_cast<size_t>(fslots) : 0;
+  }
   if (ok && static_cast<size_t>(max_slots) > h->cap_slots) {
     if (h->solve_part) {
       for (auto& a : h->allocs)
@@ -1523,9 +1575,9 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
         std::vector<LevelCfg> f2(nlev), h2(nlev);
         bool good = g2 >= 1 && g2 <= 8 && t2 >= 0 && t2 <= static_cast<int>(nlev);
         for (size_t l = 0; l < nlev && good; ++l)
-          good = static_cast<bool>(in >> f2[l].mode >> f2[l].opt >> f2[l].chunk >> f2[l].nw);
+          good = static_cast<bool>(in >> f2[l].mode >> f2[l].opt >> f2[l].chunk >> f2[l].nw >> f2[l].defer);
         for (size_t l = 0; l < nlev && good; ++l)
-          good = static_cast<bool>(in >> h2[l].mode >> h2[l].opt >> h2[l].chunk >> h2[l].nw);
+          good = static_cast<bool>(in >> h2[l].mode >> h2[l].opt >> h2[l].chunk >> h2[l].nw >> h2[l].defer);
         if (!good) continue;
         bs = b2;
         lpr = l2;
@@ -1541,7 +1593,7 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
   // a configuration read from a file is checked before use
   auto valid = [](const LevelCfg& c) {
     return (c.mode == 0 || c.mode == 1) && (c.opt == 16 || c.opt == 32 || c.opt == 64) && c.chunk >= 0 &&
-           (c.mode == 0 || c.chunk == 0) && (c.nw == 4 || c.nw == 8 || c.nw == 16);
+           (c.mode == 0 || c.chunk == 0) && (c.nw == 4 || c.nw == 8 || c.nw == 16) && (c.defer == 0 || c.defer == 1);
   };
   for (size_t l = 0; l < cf.size() && cached; ++l) cached = valid(cf[l]) && valid(cb[l]);
   if (!cached) {
@@ -1577,20 +1629,27 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
     h->solve_groups = 1;
     ffd_status st = build_solve_schedule(h);
     if (st != FFD_OK) return st;
+    // forward levels are timed with the backward pass too: deferred forward
+    // partials are added there
+    auto timed = [&](int pass) {
+      const double tb = time_solve_pass(h, s, false, 3);
+      return pass == 0 ? time_solve_pass(h, s, true, 3) + tb : tb;
+    };
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<LevelCfg>& cfg = pass == 0 ? h->cfg_fwd : h->cfg_bwd;
-      double tcur = time_solve_pass(h, s, pass == 0, 3);
+      double tcur = timed(pass);
       for (size_t l = 0; l < nlev; ++l) {
         int64_t max_inner = 0;
         for (const OutBlock& o : level_blocks(h, h->hlevels[l], pass == 0, 64))
           max_inner = std::max<int64_t>(max_inner, o.hi - o.lo);
         std::vector<LevelCfg> cands;
         for (int opt : {64, 32, 16}) {
-          if (max_inner <= 1024) cands.push_back(LevelCfg{1, opt, 0, 4});
+          if (max_inner <= 1024) cands.push_back(LevelCfg{1, opt, 0, 4, 0});
           for (int nw : {4, 8, 16})
             for (int chunk : {0, 2048, 1024, 512, 256})
               if ((chunk == 0 || chunk < max_inner) && (nw == 4 || chunk == 0 || chunk >= 1024))
-                cands.push_back(LevelCfg{0, opt, chunk, nw});
+                for (int defer : {0, 1})
+                  if (defer == 0 || (pass == 0 && chunk > 0)) cands.push_back(LevelCfg{0, opt, chunk, nw, defer});
         }
         const LevelCfg keep = cfg[l];
         LevelCfg bestc = keep;
@@ -1599,7 +1658,7 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
           cfg[l] = c;
           st = build_solve_schedule(h);
           if (st != FFD_OK) return st;
-          const double t = time_solve_pass(h, s, pass == 0, 3);
+          const double t = timed(pass);
           if (t < tcur) {
             tcur = t;
             bestc = c;
@@ -1636,8 +1695,8 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
     if (cache_path) {
       if (FILE* f = std::fopen(cache_path, "a")) {
         std::fprintf(f, "%s %d %d %zu %d %d", key.c_str(), bs, lpr, nlev, groups, topl);
-        for (const LevelCfg& c : cf) std::fprintf(f, " %d %d %d %d", c.mode, c.opt, c.chunk, c.nw);
-        for (const LevelCfg& c : cb) std::fprintf(f, " %d %d %d %d", c.mode, c.opt, c.chunk, c.nw);
+        for (const LevelCfg& c : cf) std::fprintf(f, " %d %d %d %d %d", c.mode, c.opt, c.chunk, c.nw, c.defer);
+        for (const LevelCfg& c : cb) std::fprintf(f, " %d %d %d %d %d", c.mode, c.opt, c.chunk, c.nw, c.defer);
         std::fprintf(f, "\n");
         std::fclose(f);
       }

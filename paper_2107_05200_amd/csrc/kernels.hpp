@@ -600,13 +600,38 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd_reduce(const SolveTask* __
   fwd_store<D>(tk, i, acc, y, ub);
 }
 
+// A split forward task only ever covers y rows (outputs < c), so its chunk
+// partials are added lazily: by one wave of a later backward launch that
+// precedes the backward pass over the same node (extra blocks or waves at the
+// end of that launch's grid).
+template <int D>
+__device__ __forceinline__ void fwd_y_reduce(const SolveTask& tk, int lane, const double* __restrict fpart,
+                                             double* y) {
+  const int i = tk.out0 + lane;
+  if (lane >= tk.hi || i >= tk.c) return;
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  for (int q = 0; q < tk.nk; ++q)
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] += fpart[(static_cast<int64_t>(tk.slot + q) * kSolveOutMax + lane) * D + k];
+#pragma unroll
+  for (int k = 0; k < D; ++k) y[static_cast<int64_t>(tk.first + i) * D + k] = acc[k];
+}
+
 template <int D, int OPT, int NW>
-__global__ __launch_bounds__(NW * 64) void k_solve_bwd(const SolveTask* __restrict tasks,
+__global__ __launch_bounds__(NW * 64) void k_solve_bwd(const SolveTask* __restrict tasks, int nmain,
                                                        const double* __restrict Prow, const int32_t* __restrict sidx,
-                                                       const double* __restrict y, double* __restrict x,
-                                                       double* __restrict part) {
+                                                       double* y, double* __restrict x, double* __restrict part,
+                                                       const SolveTask* __restrict yred, int nyred,
+                                                       const double* __restrict fpart) {
   constexpr int NS = NW * (64 / OPT);
   __shared__ double vs[kSolveKC][D];
+  if (static_cast<int>(blockIdx.x) >= nmain) {  // the whole block: pending forward y-row reductions
+    const int t = (static_cast<int>(blockIdx.x) - nmain) * NW + static_cast<int>(threadIdx.x >> 6);
+    if (t < nyred) fwd_y_reduce<D>(yred[t], threadIdx.x & 63, fpart, y);
+    return;
+  }
   const SolveTask tk = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int o = lane % OPT, st = wave * (64 / OPT) + lane / OPT;
@@ -730,13 +755,17 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd_wave(const SolveTask* __re
 template <int D, int OPT>
 __global__ __launch_bounds__(kBlock) void k_solve_bwd_wave(const SolveTask* __restrict tasks, int ntasks,
                                                            const double* __restrict Prow,
-                                                           const int32_t* __restrict sidx,
-                                                           const double* __restrict y, double* __restrict x) {
+                                                           const int32_t* __restrict sidx, double* y,
+                                                           double* __restrict x, const SolveTask* __restrict yred,
+                                                           int nyred, const double* __restrict fpart) {
   constexpr int IS = 64 / OPT;
   __shared__ double vs[kBlock / 64][kWaveKC][D];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t = blockIdx.x * (kBlock / 64) + wave;
-  if (t >= ntasks) return;
+  if (t >= ntasks) {  // the whole wave: a pending forward y-row reduction, if any
+    if (t - ntasks < nyred) fwd_y_reduce<D>(yred[t - ntasks], lane, fpart, y);
+    return;
+  }
   const SolveTask tk = tasks[t];
   const int o = lane % OPT, st = lane / OPT;
   const int j = tk.out0 + o;

@@ -136,3 +136,58 @@ def test_solve_streams_are_invisible(gpu_lib, case, tmp_path):
                 ref = st
             else:
                 _same(ref, st)
+
+
+def _forced(line, fwd, bwd):
+    """the cached choice with every level's (mode, outputs, chunk, waves, deferred) replaced"""
+    f = line.split()
+    nlev = int(f[3])
+    head = f[:6]
+    return " ".join(head + list(map(str, fwd)) * nlev + list(map(str, bwd)) * nlev) + "\n"
+
+
+@pytest.mark.parametrize("fwd,bwd", [((0, 64, 256, 4, 1), (0, 64, 256, 4, 0)),
+                                     ((0, 32, 256, 8, 0), (0, 16, 256, 16, 0)),
+                                     ((0, 16, 512, 4, 1), (1, 32, 0, 4, 0))])
+def test_forced_split_schedules(gpu_lib, fwd, bwd, tmp_path):
+    """Every level split (forward partials added right away or by the backward
+    pass): the solve matches SciPy's sparse LU and twelve iterations match
+    the default schedule to rounding."""
+    import torch
+    import scipy.sparse.linalg as spla
+    from paper_2107_05200_amd.binding import Solver
+    import oracle as O
+    w = mg.twisted_cube(9)
+    say(f"case: forced schedule fwd {fwd} bwd {bwd}")
+    base = str(tmp_path / "t0.txt")
+    a = Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=64)
+    a.init(w.x0)
+    a.autotune(base)
+    line = open(base).read().strip().splitlines()[-1]
+    c = str(tmp_path / "t1.txt")
+    open(c, "w").write(_forced(line, fwd, bwd))
+    b = Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=64)
+    b.init(w.x0)
+    b.autotune(c)
+    # the solve against SciPy's sparse LU of the oracle's L_FF, in the
+    # library's internal vertex order
+    order = b.vertex_order()
+    nF = w.n - len(w.pinned_idx)
+    B, wt = O.element_geometry(w.V, w.T)
+    L = O.global_matrix(O.gradient_operator(B, w.T, w.n), w.rho * wt, w.d)
+    LFF = L[order[:nF]][:, order[:nF]].tocsc()
+    rng = np.random.default_rng(0)
+    rhs = rng.normal(size=(nF, w.d))
+    x = b.solve(torch.tensor(rhs, device="cuda")).cpu().numpy()
+    ref = spla.splu(LFF).solve(rhs)
+    err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+    say(f"  solve rel err {err:.2e}")
+    assert err < 1e-10
+    a2 = Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=64)
+    a2.init(w.x0)
+    a2.iterate(12)
+    b.iterate(12)
+    sa, sb = _state(a2), _state(b)
+    for k in sa:
+        nrm = np.linalg.norm(np.nan_to_num(sa[k]))
+        assert np.linalg.norm(np.nan_to_num(sa[k]) - np.nan_to_num(sb[k])) <= 1e-10 * max(nrm, 1e-300), k

@@ -22,14 +22,15 @@ if ROOT not in sys.path:
 
 METRIC = "ADMM iters/s + local-step elems/s at 1.5M tets; fwd+bwd s/iter vs plain"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS = 78.6  # no packed FP32: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (scaled by a plain copy of known size) on the benchmark workload, keyed by a
 # hash of the kernel sources they were measured on: a changed kernel reports
 # no traffic until it is measured again.
 MEASURED_TRAFFIC = {
-    "762e7a294a5a1a33": {"solve": 3807.6e6, "local": 508.4e6},
+    "5e9e77b9b2216665": {"solve": 3780.9e6, "local": 527.3e6,
+                         "local_flop_per_elem": 2266.1, "local_valu_per_wave": 2636.2},
 }
 
 
@@ -101,32 +102,38 @@ def cpu_baseline(w, state, n_sample: int, passes: int):
             "host_cpu": _cpu_name(), "host_nproc": os.cpu_count()}
 
 
-def adjoint_leg(K: int = 100, every: int = 10):
+def adjoint_leg(K: int = 100, every: int = 10, reps: int = 3):
     """Disk deformation (99,846 triangles, 16 handles): fwd+bwd seconds per
-    iteration of the checkpointed adjoint divided by plain seconds per iteration."""
+    iteration of the checkpointed adjoint divided by plain seconds per
+    iteration (best of `reps` runs of each)."""
     import torch
     from paper_2107_05200_amd import binding, meshgen
     w = meshgen.disk_deformation()
     s = binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32)
     s.init(w.V).iterate(10)
+    s.init(w.V).adjoint_forward(10, every)
+    s.adjoint_backward(energy_loss=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.init(w.V).iterate(K)
-    torch.cuda.synchronize()
-    plain = (time.perf_counter() - t0) / K
-    t0 = time.perf_counter()
-    s.init(w.V).adjoint_forward(K, every)
-    pb, vb = s.adjoint_backward(energy_loss=True)
-    torch.cuda.synchronize()
-    fb = (time.perf_counter() - t0) / K
+    plain, fb = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        s.init(w.V).iterate(K)
+        torch.cuda.synchronize()
+        plain.append((time.perf_counter() - t0) / K)
+        t0 = time.perf_counter()
+        s.init(w.V).adjoint_forward(K, every)
+        pb, vb = s.adjoint_backward(energy_loss=True)
+        torch.cuda.synchronize()
+        fb.append((time.perf_counter() - t0) / K)
     s.close()
     return {"workload": f"disk deformation, {w.m:,} triangles, 16 handles, K={K}, checkpoint every {every}",
-            "plain_s_per_iter": plain, "fwd_bwd_s_per_iter": fb, "ratio": fb / plain}
+            "plain_s_per_iter": min(plain), "fwd_bwd_s_per_iter": min(fb), "ratio": min(fb) / min(plain)}
 
 
 def batched_leg(iters: int = 200):
     """256 height-field charts (200..50k triangles, SD/SG mixed): one batched
-    handle vs the same charts run one handle at a time."""
+    handle (autotuned, replayed graphs) vs the same charts run one handle at a
+    time (default launch shapes, replayed graphs)."""
     import numpy as np
     import torch
     from paper_2107_05200_amd import binding, meshgen
@@ -136,32 +143,37 @@ def batched_leg(iters: int = 200):
     bs = binding.BatchSolver(ws, precision=32)
     setup = time.perf_counter() - t0
     x0 = np.concatenate([w.x0 for w in ws])
-    bs.init(x0).iterate(5)
+    bs.init(x0)
+    t0 = time.perf_counter()
+    launch = bs.autotune()
+    tune = time.perf_counter() - t0
+    bs.iterate(6, graph=True)
     torch.cuda.synchronize()
     bs.init(x0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    bs.iterate(iters)
+    bs.iterate(iters, graph=True)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     bs.close()
     solvers = [binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32) for w in ws]
     for s_, w in zip(solvers, ws):
-        s_.init(w.x0).iterate(2)
+        s_.init(w.x0).iterate(2, graph=True)
     torch.cuda.synchronize()
     for s_, w in zip(solvers, ws):
         s_.init(w.x0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s_ in solvers:
-        s_.iterate(iters)
+        s_.iterate(iters, graph=True)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     for s_ in solvers:
         s_.close()
     return {"workload": f"{len(ws)} height-field charts, {m:,} triangles total, SD/SG mixed, {iters} iterations",
             "batched_elem_iters_per_s": m * iters / tb, "plain_elem_iters_per_s": m * iters / tp,
-            "speedup": tp / tb, "batched_ms_per_iter": tb / iters * 1e3, "setup_s": setup}
+            "speedup": tp / tb, "batched_ms_per_iter": tb / iters * 1e3, "setup_s": setup,
+            "autotune_s": tune, "launch": launch}
 
 
 def _cpu_name():
@@ -271,6 +283,14 @@ def main():
                   "algorithmic_bytes": local_bytes, "bytes_per_element": round(lb, 2),
                   "ms_per_launch": round(local_ms, 5),
                   "timing": "HIP events around each phase of a second pass of K iterations on the same stream"}
+    roof_local_alu = None
+    if traffic.get("local_flop_per_elem"):
+        tf = traffic["local_flop_per_elem"] * m / (local_ms * 1e-3) / 1e12
+        roof_local_alu = {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": round(tf / FP32_PEAK_TFLOPS, 4), "kernel": "k_local",
+                          "flop_per_element": traffic["local_flop_per_elem"],
+                          "valu_instructions_per_wave": traffic["local_valu_per_wave"],
+                          "note": "flop = (ADD + MUL + 2 FMA + TRANS) x 64 from the SQ_INSTS_VALU_* counters"}
     out = {
         "metric": METRIC,
         "value": round(1000.0 / ms_per_step, 2),
@@ -295,6 +315,7 @@ def main():
         "factor": {"nnz": info["factor_nnz"], "levels": info["n_levels"], "numeric_s": round(info["t_numeric"], 2)},
         "roofline": roof_solve if dominant == "solve" else roof_local,
         "roofline_local_step": roof_local,
+        "roofline_local_step_alu": roof_local_alu,
         "roofline_solve": roof_solve,
         "wrhs_gbs": round(wrhs_bytes(d, args.precision, m, nF, n) / (ph["wrhs"] / K * 1e-3) / 1e9, 1),
     }

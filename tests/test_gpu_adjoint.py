@@ -183,3 +183,65 @@ def test_adjoint_fullsize_disk_k100_checkpoints(gpu_lib):
     assert np.all(np.isfinite(pb10)) and np.all(np.isfinite(vb10))
     assert l10 == l25
     assert np.array_equal(pb10, pb25) and np.array_equal(vb10, vb25)
+
+
+def _gpu_loss(w, V, pins, K):
+    """float64 GPU loss sum_i w_i f(P_i^K) from W^0 = V (a fresh handle: V fixes
+    the frames, the weights and the factor)"""
+    import torch
+    from paper_2107_05200_amd.binding import Solver
+    s = Solver(V, w.T, w.energy, w.rho, w.pinned_idx, pins, precision=64)
+    s.init(V).iterate(K)
+    torch.cuda.synchronize()
+    L = float(s.history(K - 1, 1)[0, 2])
+    s.close()
+    return L
+
+
+def _fd_check(w, K, every, ndir, h, gate, seed, max_draws):
+    import torch
+    s, loss, pb, vb = _gpu_grads(w, 64, K, every)
+    rng = np.random.default_rng(seed)
+    worst, accepted, redrawn = 0.0, 0, 0
+    for _ in range(max_draws):
+        if accepted == ndir:
+            break
+        dV = rng.normal(size=w.V.shape)
+        dp = rng.normal(size=w.pinned_pos.shape)
+        nrm = math.sqrt((dV ** 2).sum() + (dp ** 2).sum())
+        dV, dp = dV / nrm, dp / nrm
+        fd = []
+        for hh in (h, 10 * h):
+            lp = _gpu_loss(w, w.V + hh * dV, w.pinned_pos + hh * dp, K)
+            lm = _gpu_loss(w, w.V - hh * dV, w.pinned_pos - hh * dp, K)
+            fd.append((lp - lm) / (2 * hh))
+        if abs(fd[0] - fd[1]) > 1e-3 * abs(fd[0]):
+            redrawn += 1  # a kink between the two step sizes: not a smooth direction
+            continue
+        g = float(np.sum(pb * dp) + np.sum(vb * dV))
+        worst = max(worst, abs(g - fd[0]) / abs(fd[0]))
+        accepted += 1
+    say(f"  {accepted} directions, worst rel err vs central differences (h={h:g}) {worst:.2e}; "
+        f"{redrawn} directions redrawn")
+    assert accepted == ndir and worst < gate
+
+
+def test_adjoint_central_differences_20_directions(gpu_lib):
+    """The float64 GPU gradient after K = 100 iterations (checkpoints every 10)
+    against float64 central differences of the GPU loss, h = 1e-6, on 20 random
+    unit directions over (pinned targets, rest vertices) of a 3,456-triangle
+    disk; directions on which steps 1e-6 and 1e-5 disagree (a kink) are
+    redrawn and counted."""
+    w = mg.disk_deformation(R=24)
+    say(f"case: adjoint vs central differences, disk m={w.m} K=100")
+    _fd_check(w, 100, 10, 20, 1e-6, 1e-5, 21, 40)
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_fullsize_central_differences(gpu_lib):
+    """The full 99,846-triangle disk at K = 10 (where the loss is smooth along
+    random directions): float64 GPU gradient against float64 central
+    differences of the GPU loss, h = 1e-6, 5 directions."""
+    w = mg.disk_deformation()
+    say(f"case: adjoint vs central differences, full disk m={w.m} K=10")
+    _fd_check(w, 10, 10, 5, 1e-6, 1e-5, 22, 10)

@@ -88,3 +88,83 @@ def test_fullsize_invariants(cube64):
     assert np.all(d > 0)
     # pinned vertices sit at their targets
     assert np.abs(st4["map"][w.pinned_idx] - w.pinned_pos).max() == 0.0
+
+
+def test_cube_config_300_iterations(gpu_lib):
+    """The benchmark configuration as stated: 300 iterations from the rest pose
+    (float32 element steps): every W_el keeps det > 0, no non-finite values,
+    the map is flip-free at the end, the residuals fall and the energy of the
+    map equals the energy of P to the primal residual's order."""
+    import torch
+    from paper_2107_05200_amd.binding import Solver
+    w = mg.twisted_cube(64)
+    say(f"case: full cube config, m={w.m}, 300 iterations")
+    s = Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32)
+    s.init(w.x0).iterate(300, graph=True)
+    st = {k: v.cpu().numpy() for k, v in s.get_state().items()}
+    torch.cuda.synchronize()
+    h = s.history()
+    s.close()
+    assert h.shape[0] == 300 and np.all(h[:, 6] == 0)
+    assert np.all(np.linalg.det(st["Wel"].astype(np.float64)) > 0)
+    assert h[-1, 5] == 0 and np.isfinite(h[-1, 3])
+    assert h[-1, 0] < 0.1 * h[0, 0] and h[-1, 1] < 0.1 * h[1, 1]
+    say(f"  e_prim {h[0, 0]:.3e} -> {h[-1, 0]:.3e}; e_dual {h[1, 1]:.3e} -> {h[-1, 1]:.3e}; "
+        f"E_P {h[-1, 2]:.6f} E_map {h[-1, 3]:.6f}")
+    assert abs(h[-1, 3] - h[-1, 2]) <= 1e-3 * h[-1, 2]
+
+
+@pytest.fixture(scope="module")
+def cap289(gpu_lib):
+    import torch
+    from paper_2107_05200_amd.binding import Solver
+    w = mg.sphere_cap_uv()
+    say(f"case: full-size {w.name} m={w.m}")
+    s = Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32)
+    s.init(w.x0).iterate(3)
+    st3 = {k: v.cpu().numpy() for k, v in s.get_state().items()}
+    s.iterate(1)
+    st4 = {k: v.cpu().numpy() for k, v in s.get_state().items()}
+    torch.cuda.synchronize()
+    yield w, s, st3, st4
+    s.close()
+
+
+def test_sphere_cap_sampled_local_step(cap289):
+    """The 501,126-triangle sphere cap (symmetric gradient, float32): one local
+    step of 3,000 sampled triangles against the oracle from the GPU's state."""
+    w, s, st3, st4 = cap289
+    rng = np.random.default_rng(8)
+    sel = np.sort(rng.choice(w.m, size=3000, replace=False))
+    T = w.T[sel]
+    verts, Tl = np.unique(T, return_inverse=True)
+    Tl = Tl.reshape(T.shape)
+    B, wt = O.element_geometry(w.V[verts], Tl)
+    G = O.gradient_operator(B, Tl, len(verts))
+    J = O.jacobians(G, st4["map"][verts], 2)
+    U3 = st3["U"][sel].astype(np.float64)
+    P3 = st3["P"][sel].astype(np.float64)
+    L3 = st3["Lam"][sel].astype(np.float64)
+    A = J + L3
+    U4 = O.rotation_step(A @ P3, U3)
+    At = np.transpose(U4, (0, 2, 1)) @ A
+    P4, _ = O.p_step(0.5 * (At + np.transpose(At, (0, 2, 1))), wt, w.rho * wt, w.energy)
+    L4 = L3 + J - U4 @ P4
+    eW, eL = rel(st4["Wel"][sel], U4 @ P4), rel(st4["Lam"][sel], L4)
+    say(f"  sampled local step: Wel {eW:.2e} Lam {eL:.2e}")
+    assert eW < 1e-5 and eL < 1e-3
+
+
+def test_sphere_cap_config_500_iterations(cap289):
+    """The sphere-cap configuration as stated (500 iterations): W_el stays
+    flip-free, no non-finite values, the residuals fall."""
+    import torch
+    w, s, _, _ = cap289
+    s.iterate(496, graph=True)
+    st = {k: v.cpu().numpy() for k, v in s.get_state().items()}
+    torch.cuda.synchronize()
+    h = s.history()
+    assert h.shape[0] == 500 and np.all(h[:, 6] == 0)
+    assert np.all(np.linalg.det(st["Wel"].astype(np.float64)) > 0)
+    assert h[-1, 0] < 0.1 * h[0, 0] and h[-1, 1] < 0.1 * h[1, 1]
+    say(f"  e_prim {h[0, 0]:.3e} -> {h[-1, 0]:.3e}; flips of the map at the end {h[-1, 5]:.0f}; E_P {h[-1, 2]:.6f}")

@@ -167,6 +167,23 @@ ffd_status ffd_iterate(ffd_handle h, int32_t n_iter, void* stream);
  * (ffd_autotune, a larger history); an odd iteration is run directly. */
 ffd_status ffd_iterate_graph(ffd_handle h, int32_t n_iter, void* stream);
 
+/* Algorithm 2's loop with its termination test: up to max_iter iterations;
+ * every check_every-th iteration (and the last) also records |G^T Lambda|
+ * (history field 9, otherwise NaN) and the loop stops once that record meets
+ * both thresholds of eq. primaldualthresholds,
+ *   e_prim < eps_abs sqrt(d m) + eps_rel max(|G W|, |P|),
+ *   e_dual < eps_abs sqrt(d m) + eps_rel |G^T Lambda|,
+ * and, with require_flip_free, no element of the map has det J <= 0 (the
+ * paper's added condition).  The paper uses eps_abs = 1e-6, eps_rel = 1e-5
+ * (5e-10, 5e-9 for deformations).  use_graph: the iterations between checks
+ * replay the captured graph (ffd_iterate_graph).  Synchronises `stream` at
+ * every check.  iters_done / converged (host, may be NULL): iterations run,
+ * 1 if the test was met.  Errors: FFD_ERR_INVALID_ARG for max_iter < 0,
+ * check_every < 1 or negative tolerances. */
+ffd_status ffd_iterate_until(ffd_handle h, int32_t max_iter, int32_t check_every, double eps_abs, double eps_rel,
+                             int32_t require_flip_free, int32_t use_graph, void* stream, int32_t* iters_done,
+                             int32_t* converged);
+
 /* As ffd_iterate, with a HIP event recorded on `stream` between the phases
  * of every iteration; on return (after synchronising the stream)
  * phase_ms_host[0..4] hold the summed milliseconds of the phases

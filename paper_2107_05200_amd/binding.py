@@ -62,6 +62,8 @@ _PROTOS = {
     "ffd_set_pins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ffd_iterate": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "ffd_iterate_graph": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "ffd_iterate_until": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                    C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ffd_iterate_profiled": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
     "ffd_get_state": (C.c_int, [C.c_void_p] + [C.c_void_p] * 5 + [C.c_void_p]),
     "ffd_set_state": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4 + [C.c_int64, C.c_void_p]),
@@ -207,6 +209,17 @@ class Solver:
         fn = self.lib.ffd_iterate_graph if graph else self.lib.ffd_iterate
         _check(fn(self.h, int(n_iter), _stream(stream)))
         return self
+
+    def iterate_until(self, max_iter: int, check_every: int = 10, eps_abs: float = 1e-6, eps_rel: float = 1e-5,
+                      flip_free: bool = True, graph: bool = True, stream=None):
+        """Iterate until the thresholds of eq. primaldualthresholds hold at a
+        check (every check_every iterations) or max_iter is reached; returns
+        (iterations run, converged)."""
+        done, conv = C.c_int32(0), C.c_int32(0)
+        _check(self.lib.ffd_iterate_until(self.h, int(max_iter), int(check_every), float(eps_abs), float(eps_rel),
+                                          int(bool(flip_free)), int(bool(graph)), _stream(stream),
+                                          C.byref(done), C.byref(conv)))
+        return done.value, bool(conv.value)
 
     def iterate_profiled(self, n_iter: int, stream=None) -> dict:
         """Iterate with per-phase HIP events; returns summed milliseconds per phase."""

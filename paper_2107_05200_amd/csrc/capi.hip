@@ -107,6 +107,8 @@ struct ffd_ctx {
   int graph_cur = 0;             // map buffer holding W^k when the graph starts
   double* graph_hist = nullptr;  // history buffer the graph writes to
   int64_t* k_dev = nullptr;      // device copy of the iteration counter
+  void* glam = nullptr;          // corner vectors of Lambda (diagnostic iterations)
+  double* gtl_part = nullptr;    // per-block partial sums of |G^T Lambda|^2
   std::vector<LevelCfg> cfg_fwd, cfg_bwd;  // per-level launch configuration of both solve passes
   // The forest below level solve_top is split into solve_groups groups of
   // whole subtrees, each solved on its own stream (group 0 on the caller's);
@@ -215,20 +217,20 @@ void launch_prepare(ffd_ctx* h, const ffd_ctx::Seg& g, hipStream_t s) {
 
 template <int D, typename R, int E, int BS>
 void launch_local_bs(ffd_ctx* h, const ffd_ctx::Seg& g, const double* xnew, const double* xold, int store_u,
-                     hipStream_t s) {
+                     void* glam, hipStream_t s) {
   hipLaunchKernelGGL((k_local<D, R, E, BS>), dim3(static_cast<unsigned>((g.e1 - g.e0 + BS - 1) / BS)), dim3(BS), 0, s,
                      h->m, g.e0, g.e1, h->T, static_cast<const R*>(h->B), static_cast<const R*>(h->w),
                      static_cast<R>(h->rho), h->h_mode, store_u, xnew, xold, static_cast<R*>(h->U),
                      static_cast<R*>(h->P), static_cast<R*>(h->L), static_cast<R*>(h->gn), static_cast<R*>(h->g),
-                     h->partials + g.pb0 * kNumPartials);
+                     h->partials + g.pb0 * kNumPartials, static_cast<R*>(glam));
 }
 
 template <int D, typename R, int E>
 void launch_local(ffd_ctx* h, const ffd_ctx::Seg& g, const double* xnew, const double* xold, int store_u,
-                  hipStream_t s) {
-  if (h->local_bs == 64) launch_local_bs<D, R, E, 64>(h, g, xnew, xold, store_u, s);
-  else if (h->local_bs == 128) launch_local_bs<D, R, E, 128>(h, g, xnew, xold, store_u, s);
-  else launch_local_bs<D, R, E, 256>(h, g, xnew, xold, store_u, s);
+                  void* glam, hipStream_t s) {
+  if (h->local_bs == 64) launch_local_bs<D, R, E, 64>(h, g, xnew, xold, store_u, glam, s);
+  else if (h->local_bs == 128) launch_local_bs<D, R, E, 128>(h, g, xnew, xold, store_u, glam, s);
+  else launch_local_bs<D, R, E, 256>(h, g, xnew, xold, store_u, glam, s);
 }
 
 // partial-sum block offsets of the energy ranges for the local-step block size
@@ -388,8 +390,9 @@ void do_prepare(ffd_ctx* h, hipStream_t s) {
   for (const auto& g : h->segs) SEG_CASES(launch_prepare, h, g, s)
 }
 
-void do_local(ffd_ctx* h, const double* xnew, const double* xold, int store_u, hipStream_t s) {
-  for (const auto& g : h->segs) SEG_CASES(launch_local, h, g, xnew, xold, store_u, s)
+void do_local(ffd_ctx* h, const double* xnew, const double* xold, int store_u, hipStream_t s,
+              void* glam = nullptr) {
+  for (const auto& g : h->segs) SEG_CASES(launch_local, h, g, xnew, xold, store_u, glam, s)
 }
 
 void do_wrhs(ffd_ctx* h, double* xnew, hipStream_t s) {
@@ -415,8 +418,9 @@ void do_solve(ffd_ctx* h, const double* b, double* x, hipStream_t s) {
 // the last iteration of a call and every iteration whose state is saved store
 // them (2D and h_mode 1 always store them)
 // dev_k: the history record index comes from the device counter (graph capture)
+// diag: also record |G^T Lambda| (history field 9; needs h->glam and h->gtl_part)
 void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true, bool store_u = true,
-                   bool dev_k = false) {
+                   bool dev_k = false, bool diag = false) {
   double* xold = h->x[h->cur];
   double* xnew = h->x[1 - h->cur];
   do_wrhs(h, xnew, s);
@@ -431,7 +435,7 @@ void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true
     else launch_solve_bwd<3>(h, xnew, s);
   }
   if (ev) (void)hipEventRecord(ev[2], s);
-  do_local(h, xnew, xold, store_u ? 1 : 0, s);
+  do_local(h, xnew, xold, store_u ? 1 : 0, s, diag ? h->glam : nullptr);
   if (ev) (void)hipEventRecord(ev[3], s);
   double* rec = dev_k ? h->hist : record ? h->hist + h->k * FFD_HIST_FIELDS : h->hist_scratch;
   int64_t* kd = dev_k ? h->k_dev : nullptr;
@@ -442,6 +446,25 @@ void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials2, nb2, rec, kd, FFD_HIST_FIELDS);
   } else {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials, h->nparts, rec, kd, FFD_HIST_FIELDS);
+  }
+  if (diag && !dev_k) {
+    const int64_t nb = (4 * h->n + kBlock - 1) / kBlock;
+    if (h->d == 2) {
+      if (h->prec == 32)
+        hipLaunchKernelGGL((k_gtlam<2, float>), dim3(nb), dim3(kBlock), 0, s, h->n, h->av_ptr, h->av_idx,
+                           static_cast<const float*>(h->glam), h->gtl_part);
+      else
+        hipLaunchKernelGGL((k_gtlam<2, double>), dim3(nb), dim3(kBlock), 0, s, h->n, h->av_ptr, h->av_idx,
+                           static_cast<const double*>(h->glam), h->gtl_part);
+    } else {
+      if (h->prec == 32)
+        hipLaunchKernelGGL((k_gtlam<3, float>), dim3(nb), dim3(kBlock), 0, s, h->n, h->av_ptr, h->av_idx,
+                           static_cast<const float*>(h->glam), h->gtl_part);
+      else
+        hipLaunchKernelGGL((k_gtlam<3, double>), dim3(nb), dim3(kBlock), 0, s, h->n, h->av_ptr, h->av_idx,
+                           static_cast<const double*>(h->glam), h->gtl_part);
+    }
+    hipLaunchKernelGGL(k_gtlam_finalize, dim3(1), dim3(kBlock), 0, s, h->gtl_part, nb, rec);
   }
   if (ev) (void)hipEventRecord(ev[4], s);
   h->cur = 1 - h->cur;
@@ -1243,6 +1266,50 @@ ffd_status ffd_iterate_graph(ffd_handle h, int32_t n_iter, void* stream) {
   }
   for (int32_t it = 0; it < n; ++it) one_iteration(h, s, nullptr, true, it == n - 1);
   HIP_TRY(hipGetLastError());
+  h->last_stream = s;
+  return FFD_OK;
+}
+
+ffd_status ffd_iterate_until(ffd_handle h, int32_t max_iter, int32_t check_every, double eps_abs, double eps_rel,
+                             int32_t require_flip_free, int32_t use_graph, void* stream, int32_t* iters_done,
+                             int32_t* converged) {
+  if (!h) return fail(FFD_ERR_INVALID_ARG, "NULL handle");
+  if (!h->initialized) return fail(FFD_ERR_STATE, "ffd_iterate_until before ffd_init / ffd_set_state");
+  if (max_iter < 0 || check_every < 1 || !(eps_abs >= 0.0) || !(eps_rel >= 0.0))
+    return fail(FFD_ERR_INVALID_ARG, "max_iter >= 0, check_every >= 1 and eps_abs, eps_rel >= 0 required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ffd_status st = ensure_hist(h, h->k + max_iter, s);
+  if (st != FFD_OK) return st;
+  if (!h->glam) HIP_TRY(h->alloc(reinterpret_cast<char**>(&h->glam), h->rsize() * h->m * (h->d + 1) * h->d));
+  if (!h->gtl_part) HIP_TRY(h->alloc(&h->gtl_part, static_cast<size_t>((4 * h->n + kBlock - 1) / kBlock)));
+  const double base = eps_abs * std::sqrt(static_cast<double>(h->d) * static_cast<double>(h->m));
+  int32_t done = 0, conv = 0;
+  double rec[FFD_HIST_FIELDS];
+  while (done < max_iter) {
+    const int32_t blk = std::min(check_every, max_iter - done);
+    if (blk > 1) {
+      if (use_graph) {
+        st = ffd_iterate_graph(h, blk - 1, stream);
+        if (st != FFD_OK) return st;
+      } else {
+        for (int32_t it = 0; it < blk - 1; ++it) one_iteration(h, s, nullptr, true, false);
+      }
+    }
+    one_iteration(h, s, nullptr, true, true, false, true);
+    done += blk;
+    HIP_TRY(hipMemcpyAsync(rec, h->hist + (h->k - 1) * FFD_HIST_FIELDS, sizeof rec, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const bool prim = rec[0] < base + eps_rel * std::max(rec[7], rec[8]);
+    const bool dual = rec[1] < base + eps_rel * rec[9];
+    const bool flips = !require_flip_free || rec[5] == 0.0;
+    if (prim && dual && flips) {
+      conv = 1;
+      break;
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  if (iters_done) *iters_done = done;
+  if (converged) *converged = conv;
   h->last_stream = s;
   return FFD_OK;
 }

@@ -813,7 +813,7 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
                                                   const double* __restrict x, const double* __restrict xprev,
                                                   R* __restrict U, R* __restrict P, R* __restrict Lam,
                                                   R* __restrict gnorm2, R* __restrict g,
-                                                  double* __restrict partials) {
+                                                  double* __restrict partials, R* __restrict glam) {
   const int64_t e = e0 + static_cast<int64_t>(blockIdx.x) * BS + threadIdx.x;
   double part[kNumPartials];
 #pragma unroll
@@ -957,6 +957,7 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
       R Bm[D][D];
       load_B<D, R>(Bm_, m, e, Bm);
       store_g<D, R>(g, e, Bm, r);
+      if (glam) store_g<D, R>(glam, e, Bm, L);  // corner vectors of Lambda (|G^T Lambda|)
     }
     double fP = 0.0, p2 = 0.0;
     R gn = R(0);
@@ -1025,6 +1026,48 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict pa
     hist[9] = __longlong_as_double(0x7ff8000000000000LL);
     if (k_dev) *k_dev += 1;
   }
+}
+
+// |G^T Lambda|^2 over all vertex rows (the dual threshold of eq.
+// primaldualthresholds): row j adds the corner vectors of Lambda of its
+// incident elements (four lanes per row, fixed shuffle tree); per-block sums.
+template <int D, typename R>
+__global__ __launch_bounds__(kBlock) void k_gtlam(int64_t n, const int32_t* __restrict av_ptr,
+                                                  const int32_t* __restrict av_idx, const R* __restrict glam,
+                                                  double* __restrict partials) {
+  constexpr int LPR = 4;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t j = t / LPR;
+  const int sub = static_cast<int>(t % LPR);
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  if (j < n)
+    for (int32_t q = av_ptr[j] + sub; q < av_ptr[j + 1]; q += LPR) {
+      const int64_t o = static_cast<int64_t>(av_idx[q]) * D;
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc[k] += static_cast<double>(glam[o + k]);
+    }
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (int off = 1; off < LPR; off <<= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+  double v[1] = {0.0};
+  if (sub == 0 && j < n)
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[0] += acc[k] * acc[k];
+  block_reduce_store<1>(v, partials + blockIdx.x);
+}
+
+// history field 9 of one record: sqrt of the fixed-order sum of the partials
+__global__ __launch_bounds__(kBlock) void k_gtlam_finalize(const double* __restrict partials, int64_t nb,
+                                                           double* __restrict rec) {
+  double v[1] = {0.0};
+  for (int64_t bi = threadIdx.x; bi < nb; bi += kBlock) v[0] += partials[bi];
+  __shared__ double out[1];
+  block_reduce_store<1>(v, out);
+  __syncthreads();
+  if (threadIdx.x == 0) rec[9] = sqrt(out[0]);
 }
 
 __global__ void k_set_counter(int64_t* __restrict p, int64_t v) {

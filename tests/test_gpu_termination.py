@@ -1,0 +1,83 @@
+"""Algorithm 2's termination test on the device (ffd_iterate_until): the
+recorded |G^T Lambda| against the oracle, and the iteration at which the
+thresholds of eq. primaldualthresholds (plus the flip-free condition) are
+first met at a check, against the oracle's history.  Float64: 1e-9 relative;
+float32 element steps: 1e-4."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2107_05200_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _solver(w, prec):
+    from paper_2107_05200_amd.binding import Solver
+    return Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=prec)
+
+
+@pytest.mark.parametrize("case", ["height_field_fp64", "cube_fp32"])
+def test_gtlam_records_match_oracle(gpu_lib, case):
+    w = mg.height_field_uv() if case == "height_field_fp64" else mg.twisted_cube(6)
+    prec, every, K = (64, 1, 30) if case == "height_field_fp64" else (32, 3, 12)
+    say(f"case: |G^T Lambda| records {case}")
+    g = _solver(w, prec)
+    g.init(w.x0)
+    done, conv = g.iterate_until(K, check_every=every, eps_abs=0.0, eps_rel=0.0)
+    assert done == K and not conv
+    h = g.history()
+    r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+    r.init(w.x0)
+    r.iterate(K)
+    hr = r.history.array()
+    checks = [k for k in range(K) if (k + 1) % every == 0]
+    tol = 1e-9 if prec == 64 else 1e-4
+    worst = max(abs(h[k, 9] - hr[k, 9]) / abs(hr[k, 9]) for k in checks)
+    say(f"  worst rel err of |G^T Lambda| over {len(checks)} checks {worst:.2e}")
+    assert worst < tol
+    others = [k for k in range(K) if k not in checks]
+    assert all(np.isnan(h[k, 9]) for k in others)
+
+
+@pytest.mark.parametrize("every", [1, 7, 10])
+def test_stops_where_the_oracle_stops(gpu_lib, every):
+    """Float64 height field with the paper's thresholds (1e-6, 1e-5) and the
+    flip-free condition: the first check iteration at which the oracle's
+    history meets the test is where the device loop stops."""
+    w = mg.height_field_uv()
+    say(f"case: termination, check every {every}")
+    r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+    r.init(w.x0)
+    met = []
+    for k in range(1, 241):
+        r.iterate(1)
+        pr, du = r.thresholds(1e-6, 1e-5)
+        hk = r.history.array()[-1]
+        met.append(hk[0] < pr and hk[1] < du and hk[5] == 0)
+    expect = next(k for k in range(1, 241) if k % every == 0 and met[k - 1])
+    g = _solver(w, 64)
+    g.init(w.x0)
+    done, conv = g.iterate_until(240, check_every=every, eps_abs=1e-6, eps_rel=1e-5, flip_free=True)
+    say(f"  device stopped after {done} iterations (oracle: {expect})")
+    assert conv and done == expect == g.iteration()
+
+
+def test_iterate_until_argument_errors(gpu_lib):
+    from paper_2107_05200_amd.binding import FFDError
+    w = mg.height_field_uv()
+    g = _solver(w, 32)
+    g.init(w.x0)
+    for kw in ({"check_every": 0}, {"eps_abs": -1.0}, {"max_iter": -1}):
+        args = {"max_iter": 5, **kw}
+        with pytest.raises(FFDError):
+            g.iterate_until(**args)
+    done, conv = g.iterate_until(0)
+    assert done == 0 and not conv

@@ -184,6 +184,30 @@ ffd_status ffd_iterate_until(ffd_handle h, int32_t max_iter, int32_t check_every
                              int32_t require_flip_free, int32_t use_graph, void* stream, int32_t* iters_done,
                              int32_t* converged);
 
+/* One penalty rescaling event (Section "Implementation", "Rescaling mu_i and
+ * Lambda") after the last iteration: per element, mu_i is multiplied by
+ * rho_r / 2 if e_prim_i > rho_r e_dual_i and divided by it if e_dual_i >
+ * rho_r e_prim_i (the paper uses rho_r = 5), never below half the bound of
+ * Prop. "Sufficient decrease" (gamma = 1, epsilon = 0; F_i of the Lipschitz
+ * lemma with B_i = sqrt(5 (1 + |grad f(P_i)|^2)), F_i^2 capped at
+ * eps_m^(-1/4)); Lambda_i is divided by the same factor, and L = G^T M G is
+ * factorised again on the host (same ordering and structure) and uploaded.
+ * Synchronous.  From then on the handle uses the per-element penalties until
+ * the next ffd_init, which returns to mu_i = rho w_i; the adjoint entry
+ * points refuse a rescaled handle (FFD_ERR_STATE).  Errors: FFD_ERR_STATE
+ * before the first iteration, FFD_ERR_INVALID_ARG for rho_r <= 2. */
+ffd_status ffd_rescale(ffd_handle h, double rho_r, void* stream);
+
+/* Algorithm 2: up to max_iter iterations from the current state with
+ * rescaling events (rescale_rho > 2; 0 = none) after iterations 1..5 of the
+ * run and then every 5 (3/2)^p iterations (p = past events, rounded half up),
+ * and the termination test of ffd_iterate_until at every check_every-th
+ * iteration that is not a rescaling one.  iters_done / converged /
+ * rescales_done (host, may be NULL). */
+ffd_status ffd_run(ffd_handle h, int32_t max_iter, int32_t check_every, double eps_abs, double eps_rel,
+                   int32_t require_flip_free, double rescale_rho, int32_t use_graph, void* stream, int32_t* iters_done,
+                   int32_t* converged, int32_t* rescales_done);
+
 /* As ffd_iterate, with a HIP event recorded on `stream` between the phases
  * of every iteration; on return (after synchronising the stream)
  * phase_ms_host[0..4] hold the summed milliseconds of the phases

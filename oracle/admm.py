@@ -23,6 +23,7 @@ __all__ = [
     "jacobians", "energy_density", "energy_of_spd_eigs", "grad_norm_sq_of_spd_eigs",
     "root_sg", "root_sd", "rot2", "rot3", "rotation_step", "p_step", "polar_init",
     "init_epsilon", "OracleSolver", "History", "HIST_FIELDS",
+    "c_l", "c_lg", "lipschitz_f", "mu_min", "rescale_rule", "rescale_schedule",
 ]
 
 # Reading: the machine epsilon of the supplement is taken as the float64 one
@@ -295,6 +296,73 @@ class History:
         return self.array()[:, HIST_FIELDS.index(name)]
 
 
+# ----------------------------------------------------------------------------
+# penalty rescaling (Section "Implementation", "Rescaling mu_i and Lambda";
+# Lemma "local Lipschitz constant" and Prop. "Sufficient decrease")
+# ----------------------------------------------------------------------------
+
+def c_l(B):
+    """C^L of the Lipschitz lemma, (-B + sqrt(4 + B^2)) / 2: the positive root
+    of x^2 + B x - 1 = 0, evaluated as 2 / (B + sqrt(4 + B^2)) (the same
+    number without the cancellation of the printed form at large B)."""
+    B = np.asarray(B, dtype=np.float64)
+    return 2.0 / (B + np.sqrt(4.0 + B * B))
+
+
+def c_lg(B, iters: int = 200):
+    """C^LG of the Lipschitz lemma: the positive root of x^4 + B x^3 - 1 = 0
+    (bisection on [0, 1]: the polynomial is -1 at 0 and B >= 0 at 1)."""
+    B = np.asarray(B, dtype=np.float64)
+    lo, hi = np.zeros_like(B), np.ones_like(B)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        neg = mid ** 4 + B * mid ** 3 - 1.0 < 0.0
+        lo = np.where(neg, mid, lo)
+        hi = np.where(neg, hi, mid)
+    return 0.5 * (lo + hi)
+
+
+def lipschitz_f(B, d: int, energy: int):
+    """F_i of the Lipschitz lemma (SG: 1 + sqrt(d) / C^L^2, SD: 1 + 3 sqrt(d) /
+    C^LG^4), with F_i^2 capped at eps_m^(-1/4) as the rescaling passage does."""
+    F = 1.0 + math.sqrt(d) / c_l(B) ** 2 if energy == SG else 1.0 + 3.0 * math.sqrt(d) / c_lg(B) ** 4
+    return np.minimum(F, math.sqrt(EPS_M ** -0.25))
+
+
+def mu_min(w, F):
+    """The penalty bound of Prop. "Sufficient decrease" with gamma = 1 and
+    epsilon = 0: 1/2 (-w + sqrt(w^2 + 16 w^2 F^2))."""
+    w = np.asarray(w, dtype=np.float64)
+    return 0.5 * (-w + np.sqrt(w * w + 16.0 * w * w * F * F))
+
+
+def rescale_rule(mu, e_prim, e_dual, floor, rho_r: float = 5.0):
+    """One rescaling event per element: e_prim > rho_r e_dual multiplies mu by
+    rho_r / 2 (and divides the scaled dual Lambda by it); e_dual > rho_r e_prim
+    divides mu by rho_r / 2 (multiplies Lambda); mu never goes below floor
+    (half the bound of Prop. "Sufficient decrease").  Returns (new mu, the
+    factor s with Lambda_new = Lambda / s, s = mu_new / mu)."""
+    mu = np.asarray(mu, dtype=np.float64)
+    up = e_prim > rho_r * e_dual
+    down = e_dual > rho_r * e_prim
+    new = np.where(up, mu * (0.5 * rho_r), np.where(down, mu / (0.5 * rho_r), mu))
+    new = np.maximum(new, floor)
+    return new, new / mu
+
+
+def rescale_schedule(max_iter: int):
+    """Iterations after which Algorithm 2 rescales: five directly after the
+    initialisation (after iterations 1..5), then every 5 (3/2)^p iterations
+    with p the number of past events (rounded half up)."""
+    ks, k, p = [], 0, 0
+    while True:
+        k = k + 1 if p < 5 else k + int(math.floor(5.0 * 1.5 ** p + 0.5))
+        if k > max_iter:
+            return ks
+        ks.append(k)
+        p += 1
+
+
 class OracleSolver:
     """Plain FP64 reference of the per-iteration ADMM loop.
 
@@ -372,6 +440,51 @@ class OracleSolver:
         p = np.linalg.eigvalsh(P)
         Bsq = 5.0 * (1.0 + grad_norm_sq_of_spd_eigs(p, self.energy))
         return 4.0 * self.w ** 2 * Bsq / self.mu
+
+    def rescale(self, rho_r: float = 5.0):
+        """One rescaling event after the last iteration (Section
+        "Implementation", "Rescaling mu_i and Lambda"): per element e_prim_i =
+        |J_i - U_i P_i|, e_dual_i = mu_i |J_i - J_i^prev| of that iteration,
+        B_i = sqrt(5 (1 + |grad f(P_i)|^2)), the floor 1/2 mu_min(w_i, F_i);
+        then L = G^T M G is assembled and factorised again."""
+        J = jacobians(self.G, self.x, self.d)
+        J_prev = jacobians(self.G, self.x_prev, self.d)
+        e_prim = np.sqrt(np.sum((J - self.U @ self.P) ** 2, axis=(1, 2)))
+        e_dual = self.mu * np.sqrt(np.sum((J - J_prev) ** 2, axis=(1, 2)))
+        p = np.linalg.eigvalsh(self.P)
+        B = np.sqrt(5.0 * (1.0 + grad_norm_sq_of_spd_eigs(p, self.energy)))
+        floor = 0.5 * mu_min(self.w, lipschitz_f(B, self.d, self.energy))
+        self.mu, s = rescale_rule(self.mu, e_prim, e_dual, floor, rho_r)
+        self.Lam = self.Lam / s[:, None, None]
+        self.L = global_matrix(self.G, self.mu, self.d)
+        self.L_FF = self.L[self.free][:, self.free].tocsc()
+        self.L_FC = self.L[self.free][:, self.pins].tocsr()
+        self._lu = None
+        if self.h_mode == 1:
+            self.h = self._prox_h(self.P)
+        return self
+
+    def run(self, max_iter: int, check_every: int = 1, eps_abs: float = 1e-6, eps_rel: float = 1e-5,
+            flip_free: bool = True, rescale: bool = True, rho_r: float = 5.0):
+        """Algorithm 2 (the paper's implementation of Algorithm 1): iterate,
+        rescale at the iterations of rescale_schedule, and stop at the first
+        check iteration (every check_every-th, not a rescaling one) whose
+        record meets eq. primaldualthresholds (and the flip-free condition).
+        Returns (iterations run, converged, rescaling events)."""
+        events = set(rescale_schedule(max_iter)) if rescale else set()
+        nres = 0
+        for k in range(1, max_iter + 1):
+            self.iterate(1)
+            if k in events:
+                self.rescale(rho_r)
+                nres += 1
+                continue
+            if k % check_every == 0:
+                pr, du = self.thresholds(eps_abs, eps_rel)
+                h = self.history.array()[-1]
+                if h[0] < pr and h[1] < du and (not flip_free or h[5] == 0):
+                    return k, True, nres
+        return max_iter, False, nres
 
     # -- sub-steps -----------------------------------------------------------
     def w_step(self, U, P, Lam):

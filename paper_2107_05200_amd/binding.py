@@ -64,6 +64,9 @@ _PROTOS = {
     "ffd_iterate_graph": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "ffd_iterate_until": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
                                     C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "ffd_rescale": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
+    "ffd_run": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_int32,
+                          C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ffd_iterate_profiled": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
     "ffd_get_state": (C.c_int, [C.c_void_p] + [C.c_void_p] * 5 + [C.c_void_p]),
     "ffd_set_state": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4 + [C.c_int64, C.c_void_p]),
@@ -220,6 +223,21 @@ class Solver:
                                           int(bool(flip_free)), int(bool(graph)), _stream(stream),
                                           C.byref(done), C.byref(conv)))
         return done.value, bool(conv.value)
+
+    def rescale(self, rho_r: float = 5.0, stream=None):
+        """One penalty rescaling event (new per-element mu, Lambda, factor)."""
+        _check(self.lib.ffd_rescale(self.h, float(rho_r), _stream(stream)))
+        return self
+
+    def run(self, max_iter: int, check_every: int = 10, eps_abs: float = 1e-6, eps_rel: float = 1e-5,
+            flip_free: bool = True, rescale_rho: float = 5.0, graph: bool = True, stream=None):
+        """Algorithm 2 (rescaling schedule and termination test); returns
+        (iterations run, converged, rescaling events)."""
+        done, conv, nres = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        _check(self.lib.ffd_run(self.h, int(max_iter), int(check_every), float(eps_abs), float(eps_rel),
+                                int(bool(flip_free)), float(rescale_rho), int(bool(graph)), _stream(stream),
+                                C.byref(done), C.byref(conv), C.byref(nres)))
+        return done.value, bool(conv.value), nres.value
 
     def iterate_profiled(self, n_iter: int, stream=None) -> dict:
         """Iterate with per-phase HIP events; returns summed milliseconds per phase."""

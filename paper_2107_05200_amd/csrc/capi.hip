@@ -108,6 +108,17 @@ struct ffd_ctx {
   double* graph_hist = nullptr;  // history buffer the graph writes to
   int64_t* k_dev = nullptr;      // device copy of the iteration counter
   void* glam = nullptr;          // corner vectors of Lambda (diagnostic iterations)
+  // penalty rescaling: per-element mu_e / w_e on the device (nullptr: rho for
+  // every element), the new mu_e of a rescaling event, and the host copy of
+  // the set-up input the factor is rebuilt from
+  void* rho_e = nullptr;
+  double* mu_dev = nullptr;
+  bool rescaled = false;
+  std::vector<double> in_V;
+  std::vector<int32_t> in_T, in_pins, enew2old_h;
+  std::vector<int8_t> in_energy;
+  int in_leaf = 0;
+  size_t n_pin_val = 0, n_lcf_val = 0;
   double* gtl_part = nullptr;    // per-block partial sums of |G^T Lambda|^2
   std::vector<LevelCfg> cfg_fwd, cfg_bwd;  // per-level launch configuration of both solve passes
   // The forest below level solve_top is split into solve_groups groups of
@@ -211,8 +222,17 @@ template <int D, typename R, int E>
 void launch_prepare(ffd_ctx* h, const ffd_ctx::Seg& g, hipStream_t s) {
   hipLaunchKernelGGL((k_prepare<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1,
                      static_cast<const R*>(h->B), static_cast<const R*>(h->w), static_cast<R>(h->rho),
-                     static_cast<const R*>(h->U), static_cast<const R*>(h->P), static_cast<const R*>(h->L),
-                     static_cast<R*>(h->gn), static_cast<R*>(h->g));
+                     static_cast<const R*>(h->rescaled ? h->rho_e : nullptr), static_cast<const R*>(h->U),
+                     static_cast<const R*>(h->P),
+                     static_cast<const R*>(h->L), static_cast<R*>(h->gn), static_cast<R*>(h->g));
+}
+
+template <int D, typename R, int E>
+void launch_rescale(ffd_ctx* h, const ffd_ctx::Seg& g, double rho_r, hipStream_t s) {
+  hipLaunchKernelGGL((k_rescale<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1, h->T,
+                     static_cast<const R*>(h->B), static_cast<const R*>(h->w), static_cast<R*>(h->rho_e),
+                     h->x[h->cur], h->x[1 - h->cur], static_cast<const R*>(h->U), static_cast<const R*>(h->P),
+                     static_cast<R*>(h->L), static_cast<const R*>(h->gn), static_cast<R*>(h->g), rho_r, h->mu_dev);
 }
 
 template <int D, typename R, int E, int BS>
@@ -220,7 +240,8 @@ void launch_local_bs(ffd_ctx* h, const ffd_ctx::Seg& g, const double* xnew, cons
                      void* glam, hipStream_t s) {
   hipLaunchKernelGGL((k_local<D, R, E, BS>), dim3(static_cast<unsigned>((g.e1 - g.e0 + BS - 1) / BS)), dim3(BS), 0, s,
                      h->m, g.e0, g.e1, h->T, static_cast<const R*>(h->B), static_cast<const R*>(h->w),
-                     static_cast<R>(h->rho), h->h_mode, store_u, xnew, xold, static_cast<R*>(h->U),
+                     static_cast<R>(h->rho), static_cast<const R*>(h->rescaled ? h->rho_e : nullptr), h->h_mode, store_u, xnew, xold,
+                     static_cast<R*>(h->U),
                      static_cast<R*>(h->P), static_cast<R*>(h->L), static_cast<R*>(h->gn), static_cast<R*>(h->g),
                      h->partials + g.pb0 * kNumPartials, static_cast<R*>(glam));
 }
@@ -729,6 +750,83 @@ ffd_status build_solve_schedule(ffd_ctx* h) {
   return FFD_OK;
 }
 
+// Rebuilds the factor of L = G^T M G for per-element penalties mu_dev_order
+// (device element order; nullptr: rho w_e) from the kept set-up input and
+// writes the new panels and pinned-coupling values into the existing buffers:
+// the ordering and the factor structure do not depend on the penalties
+// (checked).  Synchronous.
+ffd_status refactor(ffd_ctx* h, const std::vector<double>* mu_dev_order, hipStream_t s) {
+  std::vector<double> mu_in;
+  SetupInput in;
+  in.d = h->d;
+  in.din = h->din;
+  in.n = h->n;
+  in.m = h->m;
+  in.V = h->in_V.data();
+  in.T = h->in_T.data();
+  in.rho = h->rho;
+  in.n_pinned = static_cast<int64_t>(h->in_pins.size());
+  in.pinned_idx = h->in_pins.data();
+  in.leaf_size = h->in_leaf;
+  in.elem_energy = h->in_energy.empty() ? nullptr : h->in_energy.data();
+  if (mu_dev_order) {
+    mu_in.resize(h->m);
+    for (int64_t e = 0; e < h->m; ++e) mu_in[h->enew2old_h[e]] = (*mu_dev_order)[e];
+    in.mu_elem = mu_in.data();
+  }
+  Setup S;
+  std::string err;
+  const int st = build_setup(in, S, err);
+  if (st != OK) return fail(static_cast<ffd_status>(st), err);
+  bool same = S.nodes.size() == h->hnodes.size() && S.pin_val.size() == h->n_pin_val &&
+              S.lcf_val.size() == h->n_lcf_val && S.panel_entries == h->info.panel_entries;
+  for (size_t i = 0; same && i < S.nodes.size(); ++i)
+    same = S.nodes[i].first == h->hnodes[i].first && S.nodes[i].c == h->hnodes[i].c && S.nodes[i].r == h->hnodes[i].r;
+  std::vector<double> prow, pcol;
+  std::vector<int64_t> poff;
+  if (same) {
+    build_device_panels(S, prow, pcol, poff);
+    same = poff == h->hpoff;
+  }
+  if (!same) return fail(FFD_ERR_STATE, "the factor structure changed on refactorisation");
+  // on the caller's stream, after its pending work; the host vectors live
+  // until the stream has drained
+  HIP_TRY(hipMemcpyAsync(h->Prow, prow.data(), prow.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->Pcol, pcol.data(), pcol.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  if (!S.pin_val.empty())
+    HIP_TRY(hipMemcpyAsync(h->pin_val, S.pin_val.data(), S.pin_val.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  if (!S.lcf_val.empty())
+    HIP_TRY(hipMemcpyAsync(h->lcf_val, S.lcf_val.data(), S.lcf_val.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return FFD_OK;
+}
+
+// one rescaling event on the device, then the factor for the new penalties
+ffd_status do_rescale(ffd_ctx* h, double rho_r, hipStream_t s) {
+  if (!h->rho_e) {
+    HIP_TRY(h->alloc(reinterpret_cast<char**>(&h->rho_e), h->rsize() * h->m));
+    HIP_TRY(h->alloc(&h->mu_dev, static_cast<size_t>(h->m)));
+  }
+  if (!h->rescaled) {
+    if (h->prec == 32) {
+      std::vector<float> r(h->m, static_cast<float>(h->rho));
+      HIP_TRY(hipMemcpyAsync(h->rho_e, r.data(), r.size() * sizeof(float), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    } else {
+      std::vector<double> r(h->m, h->rho);
+      HIP_TRY(hipMemcpyAsync(h->rho_e, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+    h->rescaled = true;
+    h->graph_valid = false;
+  }
+  for (const auto& g : h->segs) SEG_CASES(launch_rescale, h, g, rho_r, s)
+  std::vector<double> mu(h->m);
+  HIP_TRY(hipMemcpyAsync(mu.data(), h->mu_dev, mu.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return refactor(h, &mu, s);
+}
+
 ffd_status ensure_hist(ffd_ctx* h, int64_t need, hipStream_t s) {
   if (need <= h->hist_cap) return FFD_OK;
   int64_t cap = std::max<int64_t>(kHistCap0, h->hist_cap);
@@ -894,6 +992,12 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
   h->eoff = eoff;
   h->auto_pinned = auto_pinned;
   h->vnew2old = S.vnew2old;
+  h->in_V.assign(mesh->V, mesh->V + mesh->n_vertices * mesh->dim_in);
+  h->in_T.assign(mesh->T, mesh->T + mesh->n_elements * (d + 1));
+  h->in_pins = pins;
+  h->in_energy = elem_energy;
+  h->in_leaf = opt.leaf_size;
+  h->enew2old_h = S.enew2old;
   const int64_t m = S.m, n = S.n, nc = d + 1;
   hipError_t e = hipSuccess;
 #define UP(expr)                                                     \
@@ -964,6 +1068,8 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
   UP(upload(h, &h->pin_ptr, S.pin_ptr));
   UP(upload(h, &h->pin_col, S.pin_col));
   UP(upload(h, &h->pin_val, S.pin_val));
+  h->n_pin_val = S.pin_val.size();
+  h->n_lcf_val = S.lcf_val.size();
   UP(upload(h, &h->av_ptr, S.av_ptr));
   UP(upload(h, &h->av_idx, S.av_idx));
   UP(upload(h, &h->lcf_ptr, S.lcf_ptr));
@@ -1171,6 +1277,12 @@ ffd_status ffd_init(ffd_handle h, const double* map0_dev, void* stream) {
   if (!h->pins_given && h->nC > 0)
     hipLaunchKernelGGL((h->d == 2 ? k_pins_from_map<2> : k_pins_from_map<3>), dim3(nblk(h->nC)), dim3(kBlock), 0, s,
                        h->nF, h->nC, h->x[0], h->xC);
+  if (h->rescaled) {  // back to mu_i = rho w_i and its factor
+    h->rescaled = false;
+    h->graph_valid = false;
+    const ffd_status st = refactor(h, nullptr, s);
+    if (st != FFD_OK) return st;
+  }
   do_init(h, s);
   HIP_TRY(hipGetLastError());
   h->k = 0;
@@ -1314,6 +1426,83 @@ ffd_status ffd_iterate_until(ffd_handle h, int32_t max_iter, int32_t check_every
   return FFD_OK;
 }
 
+ffd_status ffd_rescale(ffd_handle h, double rho_r, void* stream) {
+  if (!h) return fail(FFD_ERR_INVALID_ARG, "NULL handle");
+  if (!h->initialized || h->k < 1) return fail(FFD_ERR_STATE, "ffd_rescale needs an iteration after ffd_init");
+  if (!(rho_r > 2.0) || !std::isfinite(rho_r)) return fail(FFD_ERR_INVALID_ARG, "rescaling factor must exceed 2");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const ffd_status st = do_rescale(h, rho_r, s);
+  h->last_stream = s;
+  return st;
+}
+
+ffd_status ffd_run(ffd_handle h, int32_t max_iter, int32_t check_every, double eps_abs, double eps_rel,
+                   int32_t require_flip_free, double rescale_rho, int32_t use_graph, void* stream, int32_t* iters_done,
+                   int32_t* converged, int32_t* rescales_done) {
+  if (!h) return fail(FFD_ERR_INVALID_ARG, "NULL handle");
+  if (!h->initialized) return fail(FFD_ERR_STATE, "ffd_run before ffd_init / ffd_set_state");
+  if (max_iter < 0 || check_every < 1 || !(eps_abs >= 0.0) || !(eps_rel >= 0.0) ||
+      (rescale_rho != 0.0 && !(rescale_rho > 2.0)))
+    return fail(FFD_ERR_INVALID_ARG, "max_iter >= 0, check_every >= 1, tolerances >= 0, rescale_rho 0 or > 2 required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ffd_status st = ensure_hist(h, h->k + max_iter, s);
+  if (st != FFD_OK) return st;
+  if (!h->glam) HIP_TRY(h->alloc(reinterpret_cast<char**>(&h->glam), h->rsize() * h->m * (h->d + 1) * h->d));
+  if (!h->gtl_part) HIP_TRY(h->alloc(&h->gtl_part, static_cast<size_t>((4 * h->n + kBlock - 1) / kBlock)));
+  // rescaling events: after iterations 1..5 of this run, then every
+  // 5 (3/2)^p iterations (p past events, rounded half up)
+  auto next_event = [&](int32_t after) -> int64_t {
+    if (rescale_rho == 0.0) return INT64_MAX;
+    int64_t k = 0, q = 0;
+    while (true) {
+      k = q < 5 ? k + 1 : k + static_cast<int64_t>(std::floor(5.0 * std::pow(1.5, static_cast<double>(q)) + 0.5));
+      if (k > after) return k;
+      ++q;
+    }
+  };
+  const double base = eps_abs * std::sqrt(static_cast<double>(h->d) * static_cast<double>(h->m));
+  int32_t done = 0, conv = 0, nres = 0;
+  double rec[FFD_HIST_FIELDS];
+  auto plain = [&](int32_t n) -> ffd_status {
+    if (n <= 0) return FFD_OK;
+    if (use_graph) return ffd_iterate_graph(h, n, stream);
+    for (int32_t it = 0; it < n; ++it) one_iteration(h, s, nullptr, true, it == n - 1);
+    return FFD_OK;
+  };
+  while (done < max_iter) {
+    const int64_t ev = next_event(done);
+    const int64_t ck = (static_cast<int64_t>(done) / check_every + 1) * check_every;
+    const int32_t target = static_cast<int32_t>(std::min<int64_t>({ev, ck, static_cast<int64_t>(max_iter)}));
+    if (target == ev) {
+      st = plain(target - done);
+      if (st != FFD_OK) return st;
+      done = target;
+      st = do_rescale(h, rescale_rho, s);
+      if (st != FFD_OK) return st;
+      ++nres;
+      continue;
+    }
+    st = plain(target - done - 1);
+    if (st != FFD_OK) return st;
+    one_iteration(h, s, nullptr, true, true, false, target == ck);
+    done = target;
+    if (target != ck) continue;
+    HIP_TRY(hipMemcpyAsync(rec, h->hist + (h->k - 1) * FFD_HIST_FIELDS, sizeof rec, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (rec[0] < base + eps_rel * std::max(rec[7], rec[8]) && rec[1] < base + eps_rel * rec[9] &&
+        (!require_flip_free || rec[5] == 0.0)) {
+      conv = 1;
+      break;
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  if (iters_done) *iters_done = done;
+  if (converged) *converged = conv;
+  if (rescales_done) *rescales_done = nres;
+  h->last_stream = s;
+  return FFD_OK;
+}
+
 ffd_status ffd_iterate_profiled(ffd_handle h, int32_t n_iter, void* stream, double* phase_ms_host) {
   if (!h || !phase_ms_host) return fail(FFD_ERR_INVALID_ARG, "NULL argument");
   if (!h->initialized) return fail(FFD_ERR_STATE, "ffd_iterate before ffd_init / ffd_set_state");
@@ -1444,6 +1633,7 @@ ffd_status ffd_adjoint_forward(ffd_handle h, int32_t n_iter, int32_t checkpoint_
   if (!h) return fail(FFD_ERR_INVALID_ARG, "NULL handle");
   if (!h->initialized) return fail(FFD_ERR_STATE, "ffd_adjoint_forward before ffd_init / ffd_set_state");
   if (n_iter <= 0 || checkpoint_every <= 0) return fail(FFD_ERR_INVALID_ARG, "n_iter and checkpoint_every must be > 0");
+  if (h->rescaled) return fail(FFD_ERR_STATE, "the adjoint differentiates mu_i = rho w_i: not after a rescaling");
   hipStream_t s = static_cast<hipStream_t>(stream);
   ffd_status st = ensure_hist(h, h->k + n_iter, s);
   if (st != FFD_OK) return st;

@@ -226,6 +226,12 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
     err = "rho must be positive and finite";
     return ERR_INVALID_ARG;
   }
+  if (in.mu_elem)
+    for (int64_t e = 0; e < m; ++e)
+      if (!(in.mu_elem[e] > 0) || !std::isfinite(in.mu_elem[e])) {
+        err = "per-element penalties must be positive and finite";
+        return ERR_INVALID_ARG;
+      }
   for (int64_t i = 0; i < n * din; ++i)
     if (!std::isfinite(in.V[i])) {
       err = "non-finite source vertex";
@@ -306,7 +312,7 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
     for (int64_t k = inc_ptr[v]; k < inc_ptr[v + 1]; ++k) {
       const int64_t e = inc[k] / nc;
       const int cv = inc[k] % nc;
-      const double mu = in.rho * w0[e];
+      const double mu = in.mu_elem ? in.mu_elem[e] : in.rho * w0[e];
       const double* Be = B0.data() + e * d * d;
       // C[a][0] = -sum_j B[a][j], C[a][j+1] = B[a][j]
       double C[3][4];

@@ -28,6 +28,7 @@ struct SetupInput {
   const double* V = nullptr;     // n x din row-major
   const int32_t* T = nullptr;    // m x (d+1) row-major
   double rho = 10.0;             // mu_i = rho * w_i
+  const double* mu_elem = nullptr;  // optional per-element mu_i (input order, m entries; replaces rho * w_i)
   int64_t n_pinned = 0;
   const int32_t* pinned_idx = nullptr;
   int leaf_size = 0;             // 0: automatic

@@ -341,11 +341,12 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t m, int64_t e0, int64_t 
 // r = mu (U P - Lambda) -> corner vectors (after the state is set from outside)
 template <int D, typename R, int ENERGY>
 __global__ __launch_bounds__(kBlock) void k_prepare(int64_t m, int64_t e0, int64_t e1, const R* __restrict Bm_,
-                                                    const R* __restrict w, R rho, const R* __restrict U,
-                                                    const R* __restrict P, const R* __restrict Lam,
-                                                    R* __restrict gnorm2, R* __restrict g) {
+                                                    const R* __restrict w, R rho_u, const R* __restrict rho_e,
+                                                    const R* __restrict U, const R* __restrict P,
+                                                    const R* __restrict Lam, R* __restrict gnorm2, R* __restrict g) {
   const int64_t e = e0 + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (e >= e1) return;
+  const R rho = rho_e ? rho_e[e] : rho_u;  // mu_e / w_e
   R Ur[D][D], Pm[D][D], UP[D][D], Bm[D][D], r[D][D];
   load_U<D, R>(U, m, e, Ur);
   load_P<D, R>(P, m, e, Pm);
@@ -809,7 +810,8 @@ __global__ __launch_bounds__(kBlock) void k_solve_bwd_wave(const SolveTask* __re
 template <int D, typename R, int ENERGY, int BS = kBlock>
 __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1, const int32_t* __restrict T,
                                                   const R* __restrict Bm_,
-                                                  const R* __restrict w, R rho, int h_mode, int store_u,
+                                                  const R* __restrict w, R rho_u, const R* __restrict rho_e,
+                                                  int h_mode, int store_u,
                                                   const double* __restrict x, const double* __restrict xprev,
                                                   R* __restrict U, R* __restrict P, R* __restrict Lam,
                                                   R* __restrict gnorm2, R* __restrict g,
@@ -820,6 +822,7 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
   for (int f = 0; f < kNumPartials; ++f) part[f] = 0.0;
   if (e < e1) {
     const R we = w[e];
+    const R rho = rho_e ? rho_e[e] : rho_u;  // mu_e / w_e (per element after a rescaling)
     const R mu = rho * we;
     const double wd = static_cast<double>(we), mud = static_cast<double>(mu);
     R J[D][D];
@@ -1026,6 +1029,103 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict pa
     hist[9] = __longlong_as_double(0x7ff8000000000000LL);
     if (k_dev) *k_dev += 1;
   }
+}
+
+// One rescaling event (Section "Implementation", "Rescaling mu_i and
+// Lambda"), per element, from the state after an iteration: e_prim_e =
+// |J_e - U_e P_e| and e_dual_e = mu_e |J_e - J_e^prev| (both maps are still
+// in their buffers); mu_e is multiplied by rho_r / 2 if e_prim_e > rho_r
+// e_dual_e and divided by it if e_dual_e > rho_r e_prim_e, never below half
+// the bound of Prop. "Sufficient decrease" (gamma = 1, epsilon = 0) with the
+// F_e of the Lipschitz lemma for B_e = sqrt(5 (1 + |grad f(P_e)|^2)) and F_e^2
+// capped at eps_m^(-1/4); the scaled dual Lambda_e is divided by the factor
+// and the next right-hand side's corner vectors are emitted again.  Decisions
+// in float64.  mu_out: the new mu_e in float64 (for the new factor).
+template <int D, typename R, int ENERGY>
+__global__ __launch_bounds__(kBlock) void k_rescale(int64_t m, int64_t e0, int64_t e1, const int32_t* __restrict T,
+                                                    const R* __restrict Bm_, const R* __restrict w,
+                                                    R* __restrict rho_e, const double* __restrict x,
+                                                    const double* __restrict xprev, const R* __restrict U,
+                                                    const R* __restrict P, R* __restrict Lam,
+                                                    const R* __restrict gnorm2, R* __restrict g, double rho_r,
+                                                    double* __restrict mu_out) {
+  const int64_t e = e0 + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= e1) return;
+  const double wd = static_cast<double>(w[e]);
+  const double mu = static_cast<double>(rho_e[e]) * wd;
+  R Bm[D][D];
+  load_B<D, R>(Bm_, m, e, Bm);
+  double E[D][D], dE[D][D], x0[D], p0[D];
+  const int32_t v0 = T[e];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    x0[k] = x[static_cast<int64_t>(v0) * D + k];
+    p0[k] = xprev[static_cast<int64_t>(v0) * D + k];
+  }
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const int64_t vj = T[(j + 1) * m + e];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      E[j][k] = x[vj * D + k] - x0[k];
+      dE[j][k] = (x[vj * D + k] - xprev[vj * D + k]) - (x0[k] - p0[k]);
+    }
+  }
+  R Ur[D][D], Pm[D][D];
+  load_U<D, R>(U, m, e, Ur);
+  load_P<D, R>(P, m, e, Pm);
+  double ep2 = 0.0, ed2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double J = 0.0, Jd = 0.0, up = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        J += static_cast<double>(Bm[a][j]) * E[j][k];
+        Jd += static_cast<double>(Bm[a][j]) * dE[j][k];
+        up += static_cast<double>(Ur[a][j]) * static_cast<double>(Pm[j][k]);
+      }
+      ep2 += (J - up) * (J - up);
+      ed2 += Jd * Jd;
+    }
+  const double e_prim = sqrt(ep2), e_dual = mu * sqrt(ed2);
+  const double B = sqrt(5.0 * (1.0 + static_cast<double>(gnorm2[e])));
+  double F;
+  if (ENERGY == 1) {
+    const double cl = 2.0 / (B + sqrt(4.0 + B * B));  // positive root of x^2 + B x - 1
+    F = 1.0 + sqrt(static_cast<double>(D)) / (cl * cl);
+  } else {
+    double lo = 0.0, hi = 1.0;  // positive root of x^4 + B x^3 - 1 in [0, 1]
+    for (int it = 0; it < 100; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid * mid * mid * mid + B * mid * mid * mid - 1.0 < 0.0) lo = mid;
+      else hi = mid;
+    }
+    const double c = 0.5 * (lo + hi);
+    F = 1.0 + 3.0 * sqrt(static_cast<double>(D)) / (c * c * c * c);
+  }
+  F = fmin(F, 90.50966799187809);  // F^2 <= eps_m^(-1/4) = 8192
+  const double floor_mu = 0.25 * (-wd + sqrt(wd * wd + 16.0 * wd * wd * F * F));
+  double nmu = e_prim > rho_r * e_dual ? mu * (0.5 * rho_r) : e_dual > rho_r * e_prim ? mu / (0.5 * rho_r) : mu;
+  nmu = fmax(nmu, floor_mu);
+  const double sc = nmu / mu;
+  mu_out[e] = nmu;
+  rho_e[e] = static_cast<R>(nmu / wd);
+  R L[D][D], r[D][D];
+  const R nmur = static_cast<R>(nmu);
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      L[a][k] = static_cast<R>(static_cast<double>(Lam[(a * D + k) * m + e]) / sc);
+      Lam[(a * D + k) * m + e] = L[a][k];
+      R up = R(0);
+#pragma unroll
+      for (int j = 0; j < D; ++j) up += Ur[a][j] * Pm[j][k];
+      r[a][k] = nmur * (up - L[a][k]);
+    }
+  store_g<D, R>(g, e, Bm, r);
 }
 
 // |G^T Lambda|^2 over all vertex rows (the dual threshold of eq.

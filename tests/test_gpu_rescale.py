@@ -1,0 +1,195 @@
+"""Penalty rescaling (Section "Implementation", "Rescaling mu_i and Lambda")
+and Algorithm 2 on the device (ffd_rescale, ffd_run) against the oracle.
+
+Float64: the scaled dual right after an event and the state a few iterations
+later within 1e-9 relative of the oracle's; the run with the paper's
+schedule and thresholds stops at the oracle's iteration after the same number
+of events.  Float32: the run stays finite and ends flip-free, and ffd_init
+returns to the uniform penalties bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2107_05200_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _solver(w, prec, h_mode=0):
+    from paper_2107_05200_amd.binding import Solver
+    return Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=prec, h_mode=h_mode)
+
+
+def _oracle(w, h_mode=0):
+    r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, h_mode=h_mode)
+    r.init(w.x0)
+    return r
+
+
+EVENT_CASES = {
+    "height_field_sd_fp64": (lambda: mg.height_field_uv(), 0),
+    "height_field_sd_fp64_h1": (lambda: mg.height_field_uv(), 1),
+    "cube6_sd_fp64": (lambda: mg.twisted_cube(6), 0),
+    "cube5_sg_fp64": (lambda: mg.twisted_cube(5, energy=mg.SYMMETRIC_GRADIENT), 0),
+    "sphere_cap_sg_fp64": (lambda: mg.sphere_cap_uv(R=15), 0),
+}
+
+
+@pytest.mark.parametrize("name", list(EVENT_CASES))
+def test_rescale_events_match_oracle(gpu_lib, name):
+    """Two events (after iterations 4 and 7), each checked on Lambda right
+    after it (Lambda_i / s_i carries the per-element factor), and the map,
+    W_el and the records of the iterations that follow (new penalties in the
+    W-step, the local step and the dual residual)."""
+    import torch
+    mk, h_mode = EVENT_CASES[name]
+    w = mk()
+    say(f"case: rescale events {name} m={w.m}")
+    g = _solver(w, 64, h_mode)
+    g.init(w.x0)
+    r = _oracle(w, h_mode)
+    for n_before in (4, 3):
+        g.iterate(n_before)
+        r.iterate(n_before)
+        g.rescale(5.0)
+        r.rescale(5.0)
+        st = g.get_state()
+        torch.cuda.synchronize()
+        e_lam = rel(host(st["Lam"]), r.Lam)
+        say(f"  after the event at k={r.k}: Lambda rel err {e_lam:.2e}")
+        assert e_lam < 1e-9
+    g.iterate(6)
+    r.iterate(6)
+    st = g.get_state()
+    torch.cuda.synchronize()
+    ex, ew = rel(host(st["map"]), r.x), rel(host(st["Wel"]), r.wel())
+    say(f"  6 iterations later: map {ex:.2e} Wel {ew:.2e}")
+    assert ex < 1e-9 and ew < 1e-9
+    h, hr = g.history(), r.history.array()
+    assert h.shape[0] == hr.shape[0] == 13
+    assert np.allclose(h[:, 0], hr[:, 0], rtol=1e-8, atol=1e-14)
+    assert np.allclose(h[:, 1], hr[:, 1], rtol=1e-8, atol=1e-14)
+    assert np.array_equal(h[:, 5], hr[:, 5])
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_run_stops_where_the_oracle_stops(gpu_lib, graph):
+    """The height field with the paper's settings (rho_r = 5, thresholds 1e-6
+    and 1e-5, flip-free, a check every 10 iterations): the same stop
+    iteration, convergence flag and number of events as the oracle's run."""
+    import torch
+    w = mg.height_field_uv()
+    say(f"case: Algorithm 2 with rescaling, graph={graph}")
+    r = _oracle(w)
+    expect = r.run(1200, check_every=10, eps_abs=1e-6, eps_rel=1e-5, flip_free=True, rescale=True, rho_r=5.0)
+    g = _solver(w, 64)
+    g.init(w.x0)
+    got = g.run(1200, check_every=10, eps_abs=1e-6, eps_rel=1e-5, flip_free=True, rescale_rho=5.0, graph=graph)
+    say(f"  device (iterations, converged, events) {got}, oracle {expect}")
+    assert got == expect and got[1]
+    assert g.iteration() == expect[0]
+    st = g.get_state()
+    torch.cuda.synchronize()
+    ex = rel(host(st["map"]), r.x)
+    say(f"  final map rel err {ex:.2e}")
+    assert ex < 1e-7
+    h, hr = g.history(), r.history.array()
+    assert np.allclose(h[-1, :2], hr[-1, :2], rtol=1e-5)
+
+
+def test_run_without_rescaling_is_iterate_until(gpu_lib):
+    """rescale_rho = 0: ffd_run is the plain termination loop, bit for bit."""
+    import torch
+    w = mg.twisted_cube(6)
+    say("case: ffd_run without rescaling vs ffd_iterate_until (cube6 fp32)")
+    a = _solver(w, 32)
+    a.init(w.x0)
+    ra = a.iterate_until(300, check_every=7, eps_abs=1e-6, eps_rel=1e-5, flip_free=True)
+    b = _solver(w, 32)
+    b.init(w.x0)
+    rb = b.run(300, check_every=7, eps_abs=1e-6, eps_rel=1e-5, flip_free=True, rescale_rho=0.0)
+    say(f"  iterate_until {ra}, run {rb}")
+    assert rb == (ra[0], ra[1], 0)
+    sa, sb = a.get_state(), b.get_state()
+    torch.cuda.synchronize()
+    for k in ("map", "U", "P", "Lam"):
+        assert torch.equal(sa[k], sb[k]), k
+
+
+def test_fp32_cube_run_with_rescaling(gpu_lib):
+    """Float32 tet cube under Algorithm 2 with rescaling: the events follow
+    the schedule, every record is finite and the last map is flip-free."""
+    w = mg.twisted_cube(12)
+    say(f"case: fp32 cube12 run with rescaling m={w.m}")
+    g = _solver(w, 32)
+    g.init(w.x0)
+    done, conv, nres = g.run(400, check_every=10, eps_abs=1e-6, eps_rel=1e-5, flip_free=True, rescale_rho=5.0)
+    say(f"  {done} iterations, converged {conv}, {nres} events")
+    assert nres == len(O.rescale_schedule(done))
+    h = g.history()
+    assert h.shape[0] == done
+    assert np.all(np.isfinite(h[:, :3]))
+    assert h[-1, 5] == 0
+    assert h[-1, 0] < 0.1 * h[0, 0]
+
+
+def test_init_returns_to_uniform_penalties(gpu_lib):
+    """After events, ffd_init goes back to mu_i = rho w_i and its factor: the
+    next iterations equal those of a fresh handle bit for bit."""
+    import torch
+    w = mg.twisted_cube(6)
+    say("case: init after rescaling (cube6 fp32)")
+    a = _solver(w, 32)
+    a.init(w.x0)
+    a.iterate(5)
+    a.rescale(5.0)
+    a.iterate(3)
+    a.rescale(5.0)
+    a.init(w.x0)
+    a.iterate(10)
+    b = _solver(w, 32)
+    b.init(w.x0)
+    b.iterate(10)
+    sa, sb = a.get_state(), b.get_state()
+    torch.cuda.synchronize()
+    for k in ("map", "U", "P", "Lam"):
+        assert torch.equal(sa[k], sb[k]), k
+    assert np.array_equal(a.history(), b.history(), equal_nan=True)
+
+
+def test_rescale_argument_and_state_errors(gpu_lib):
+    from paper_2107_05200_amd.binding import FFDError
+    w = mg.height_field_uv()
+    g = _solver(w, 32)
+    g.init(w.x0)
+    with pytest.raises(FFDError):
+        g.rescale(5.0)  # no iteration yet
+    g.iterate(2)
+    for bad in (2.0, 1.0, float("nan")):
+        with pytest.raises(FFDError):
+            g.rescale(bad)
+    with pytest.raises(FFDError):
+        g.run(10, rescale_rho=1.5)
+    g.rescale(5.0)
+    with pytest.raises(FFDError):
+        g.adjoint_forward(5)
+    g.init(w.x0)
+    g.adjoint_forward(3)

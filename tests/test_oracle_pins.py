@@ -500,3 +500,76 @@ def test_pin13_residual_decrease_on_height_field():
     assert all(b <= a * (1 + 1e-12) for a, b in zip(win_d, win_d[1:]))
     assert s.history.col("flips")[-1] == 0
     assert math.isfinite(s.history.col("E_map")[-1])
+
+
+# ---------------------------------------------------------------------------
+# penalty rescaling (Section "Implementation", "Rescaling mu_i and Lambda")
+# ---------------------------------------------------------------------------
+
+def test_lipschitz_constants_of_the_lemma():
+    """C^L and C^LG solve their polynomials, equal 1 at B = 0, behave like 1/B
+    and B^(-1/3) for large B, and satisfy the lemma's C^L <= C^LG <= 1."""
+    B = np.concatenate([[0.0], np.logspace(-3, 3, 400)])
+    cl, clg = O.c_l(B), O.c_lg(B)
+    assert np.all(cl > 0) and np.all(clg > 0)
+    assert np.max(np.abs(cl * cl + B * cl - 1.0)) < 1e-13
+    assert np.max(np.abs(clg ** 4 + B * clg ** 3 - 1.0)) < 1e-13
+    assert cl[0] == 1.0 and abs(clg[0] - 1.0) < 1e-15
+    assert np.all(cl <= clg + 1e-15) and np.all(clg <= 1.0)
+    big = B > 500
+    assert np.allclose(cl[big] * B[big], 1.0, rtol=1e-4)
+    assert np.allclose(clg[big] * B[big] ** (1 / 3), 1.0, rtol=1e-2)
+
+
+def test_mu_min_is_the_boundary_of_the_proposition():
+    """mu_min(w, F) is the positive root of mu^2 + w mu - 4 w^2 F^2 = 0 (the
+    proposition's inequality with gamma = 1, epsilon = 0, solved for mu), and
+    F^2 is capped at eps_m^(-1/4)."""
+    rng = np.random.default_rng(4)
+    w = 10 ** rng.uniform(-6, 0, 300)
+    F = 10 ** rng.uniform(0, 1.9, 300)
+    mu = O.mu_min(w, F)
+    assert np.all(mu > 0)
+    assert np.max(np.abs(mu * mu + w * mu - 4 * w * w * F * F) / (4 * w * w * F * F)) < 1e-12
+    Fsd = O.lipschitz_f(np.array([1e6]), 3, O.SD)
+    assert abs(Fsd[0] ** 2 - O.EPS_M ** -0.25) <= 1e-9 * O.EPS_M ** -0.25
+    assert abs(O.lipschitz_f(np.array([0.0]), 2, O.SG)[0] - (1 + math.sqrt(2))) < 1e-15
+
+
+def test_rescale_rule_cases():
+    mu = np.array([1.0, 1.0, 1.0, 1.0, 1.0, 0.3])
+    ep = np.array([6.0, 1.0, 5.0, 1.0, 1.0, 1.0])
+    ed = np.array([1.0, 6.0, 1.0, 5.0, 1.0, 6.0])
+    floor = np.array([0.0, 0.0, 0.0, 0.0, 0.0, 0.2])
+    new, s = O.rescale_rule(mu, ep, ed, floor, 5.0)
+    assert np.allclose(new, [2.5, 0.4, 1.0, 1.0, 1.0, 0.2])
+    assert np.allclose(s, new / mu)
+
+
+def test_rescale_schedule_reading():
+    ks = O.rescale_schedule(400)
+    assert ks[:5] == [1, 2, 3, 4, 5]
+    assert np.diff(ks[4:]).tolist() == [38, 57, 85, 128]
+
+
+def test_rescale_keeps_the_unscaled_dual_and_refactors():
+    """A rescaling event changes mu_i by 5/2 or 2/5 (or not, or up to the
+    floor) and the scaled dual Lambda_i in the opposite direction, so the
+    unscaled dual mu_i Lambda_i is unchanged; the new L_FF factor solves the
+    new W-step exactly."""
+    w = mg.height_field_uv()
+    r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+    r.init(w.x0)
+    r.iterate(3)
+    Y0 = r.mu[:, None, None] * r.Lam
+    mu0 = r.mu.copy()
+    r.rescale(5.0)
+    ratio = r.mu / mu0
+    assert np.all(np.isclose(ratio, 2.5) | np.isclose(ratio, 0.4) | np.isclose(ratio, 1.0) | (ratio > 0.4))
+    assert np.any(ratio != 1.0)
+    assert np.allclose(r.mu[:, None, None] * r.Lam, Y0, rtol=1e-14, atol=1e-300)
+    x = r.w_step(r.U, r.P, r.Lam)
+    rr = r.mu[:, None, None] * (r.U @ r.P - r.Lam)
+    rhs = np.asarray(r.G.T @ rr.reshape(r.m * r.d, r.d))[r.free] - r.L_FC @ r.pin_pos
+    res = np.linalg.norm(r.L_FF @ x[r.free] - rhs) / np.linalg.norm(rhs)
+    assert res < 1e-12

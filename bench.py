@@ -176,6 +176,37 @@ def batched_leg(iters: int = 200):
             "autotune_s": tune, "launch": launch}
 
 
+def uv_pipeline_leg(max_iter: int = 1000):
+    """The paper's UV pipeline on the sphere cap (501,126 triangles, symmetric
+    gradient): a Tutte initial map with the boundary on a circle, then
+    Algorithm 2 with rescaling (rho_r = 5, refactorisation on the host) and
+    the termination test every 10 iterations (1e-6, 1e-5, flip-free)."""
+    import torch
+    from paper_2107_05200_amd import binding, meshgen
+    w = meshgen.sphere_cap_uv()
+    idx, pos = meshgen.circle_boundary(w.V, w.T)
+    binding.tutte_map(w.V, w.T, idx, pos)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W0 = binding.tutte_map(w.V, w.T, idx, pos)
+    torch.cuda.synchronize()
+    t_tutte = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    s = binding.Solver(w.V, w.T, w.energy, w.rho, idx[:1], pos[:1], precision=32)
+    t_setup = time.perf_counter() - t0
+    s.init(W0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, conv, nres = s.run(max_iter, check_every=10, eps_abs=1e-6, eps_rel=1e-5, flip_free=True, rescale_rho=5.0)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    h = s.history()
+    s.close()
+    return {"workload": f"sphere cap UV, {w.m:,} triangles, SG, Tutte init, rescaling, max {max_iter} iterations",
+            "tutte_s": t_tutte, "setup_s": t_setup, "run_s": t_run, "iterations": done, "converged": conv,
+            "rescales": nres, "final_flips": int(h[-1, 5]), "final_E_map": float(h[-1, 3])}
+
+
 def _cpu_name():
     try:
         for ln in open("/proc/cpuinfo"):
@@ -195,7 +226,7 @@ def main():
     ap.add_argument("--precision", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=200000)
-    ap.add_argument("--no-extra", action="store_true", help="skip the adjoint and batched legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the adjoint, batched and UV-pipeline legs")
     ap.add_argument("--tune-cache", default=None, help="launch-shape cache file (read, or written after tuning)")
     ap.add_argument("--no-graph", action="store_true", help="time direct launches instead of replayed HIP graphs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -333,6 +364,9 @@ def main():
         t0 = time.perf_counter()
         out["batched"] = batched_leg()
         log(f"batched leg: {out['batched']} ({time.perf_counter() - t0:.1f}s)")
+        t0 = time.perf_counter()
+        out["uv_pipeline"] = uv_pipeline_leg()
+        log(f"uv pipeline leg: {out['uv_pipeline']} ({time.perf_counter() - t0:.1f}s)")
     if st is not None:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(w, st, args.cpu_sample, 3)

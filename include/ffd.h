@@ -70,7 +70,7 @@ typedef struct {
 } ffd_mesh;
 
 /* Options.  mu_i = rho * w_i with w_i the element area / volume (the
- * penalties of eq. augmentedlagrangian, fixed: no rescaling).  Pins are the
+ * penalties of eq. augmentedlagrangian; per element after ffd_rescale).  Pins are the
  * linear constraints A W = b of eq. solvinginw restricted to fixed vertices;
  * with no pins and auto_pin = 1 vertex 0 is fixed at its initial position (the
  * W-step text fixes the first vertex when there are no constraints). */
@@ -109,7 +109,9 @@ typedef struct {
  *  6 nonfinite number of elements whose Lambda is not finite
  *  7 norm_GW  |G W^k|                                         (eq. primaldualthresholds)
  *  8 norm_P   |P^k|                                           (eq. primaldualthresholds)
- *  9 norm_GtLam  |G^T Lambda^k| -- not computed on the device: NaN
+ *  9 norm_GtLam  |G^T Lambda^k| over all vertex rows (eq. primaldualthresholds),
+ *             recorded at the check iterations of ffd_iterate_until / ffd_run,
+ *             NaN elsewhere
  * J_i = (G W^k)_i.  Iterations are numbered from 1 after ffd_init. */
 #define FFD_HIST_FIELDS 10
 
@@ -117,6 +119,20 @@ typedef struct {
  * dissection, FP64 multifrontal Cholesky of L_FF, then upload to the current
  * HIP device.  Synchronous.  On success *out is a new handle. */
 ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* out);
+
+/* Minimiser of Tutte's energy (supplement "Tutte's Energy", Table 1): the sum
+ * over the mesh edges (i, j) of |W_i - W_j|^2 / |V_i - V_j|, with the n_fixed
+ * vertices fixed_idx held at fixed_pos (host, n_fixed x simplex_dim
+ * row-major), e.g. the boundary on a convex curve for a flip-free 2D
+ * initial map, or on a target surface for a volume (there it may flip
+ * elements).  The edge Laplacian is factorised on the host with the same
+ * ordering and factor form as L = G^T M G and solved on the device with the
+ * W-step's solve kernels; map_dev (device, n_vertices x simplex_dim float64,
+ * input vertex order) receives the whole map.  Synchronous on `stream`.
+ * Errors: as ffd_create (a connected component without a fixed vertex:
+ * FFD_ERR_SINGULAR_SYSTEM; a zero-length edge: FFD_ERR_DEGENERATE_ELEMENT). */
+ffd_status ffd_tutte_map(const ffd_mesh* mesh, int64_t n_fixed, const int32_t* fixed_idx, const double* fixed_pos,
+                         int32_t leaf_size, double* map_dev, void* stream);
 
 /* Batched form: n_meshes independent meshes (same simplex_dim and dim_in;
  * options with the same precision, h_mode and rho; energy, pins and

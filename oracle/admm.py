@@ -7,7 +7,7 @@ ambiguous are marked "Reading:".
 Conventions (paper, Def. "Piecewise constant Jacobian" and supplement
 "Computing the Jacobian Map"): J_i = (G W)_i is d x d with column k equal to
 the gradient of output coordinate k on element i.  Element arrays are
-(m, d, d) float64.  mu_i = rho * w_i (fixed, no rescaling).
+(m, d, d) float64.  mu_i = rho * w_i until a rescaling event (OracleSolver.rescale).
 """
 from __future__ import annotations
 

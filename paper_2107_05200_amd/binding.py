@@ -65,6 +65,7 @@ _PROTOS = {
     "ffd_iterate_until": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
                                     C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ffd_rescale": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
+    "ffd_tutte_map": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "ffd_run": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_int32,
                           C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ffd_iterate_profiled": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
@@ -143,6 +144,26 @@ def analyze(V, T, energy=0, rho=10.0, pinned_idx=None, pinned_pos=None, auto_pin
     _check(lib.ffd_analyze(C.byref(ms), C.byref(op), C.byref(info), C.byref(res)))
     out = info.as_dict()
     out["selfcheck_residual"] = res.value
+    return out
+
+
+def tutte_map(V, T, fixed_idx, fixed_pos, leaf_size=0, stream=None):
+    """Minimiser of Tutte's energy with the vertices fixed_idx held at
+    fixed_pos (host factor, device solve); returns a (n, d) float64 tensor on
+    the current device in the input vertex order."""
+    import torch
+    lib = load()
+    V = np.asarray(V)
+    T = np.asarray(T)
+    d = T.shape[1] - 1
+    ms, keep1 = _mesh_struct(V, T)
+    fi = np.ascontiguousarray(fixed_idx, dtype=np.int32)
+    fp = np.ascontiguousarray(fixed_pos, dtype=np.float64).reshape(-1, d)
+    if fp.shape[0] != fi.shape[0]:
+        raise ValueError("fixed_pos needs one row per fixed vertex")
+    out = torch.empty((V.shape[0], d), dtype=torch.float64, device=torch.device("cuda", torch.cuda.current_device()))
+    _check(lib.ffd_tutte_map(C.byref(ms), fi.shape[0], fi.ctypes.data_as(C.c_void_p), fp.ctypes.data_as(C.c_void_p),
+                             int(leaf_size), C.c_void_p(out.data_ptr()), _stream(stream)))
     return out
 
 

@@ -948,7 +948,8 @@ namespace {
 // opt the common options, pins in mesh indices, pin_pos empty = taken from W^0
 ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const std::vector<int32_t>& pins,
                        const std::vector<double>& pin_pos, bool auto_pinned, const std::vector<int8_t>& elem_energy,
-                       const std::vector<int64_t>& voff, const std::vector<int64_t>& eoff, ffd_handle* out) {
+                       const std::vector<int64_t>& voff, const std::vector<int64_t>& eoff, ffd_handle* out,
+                       bool tutte = false) {
   const ffd_mesh* mesh = &mesh_in;
   const int d = mesh->simplex_dim;
   SetupInput in;
@@ -963,6 +964,7 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
   in.pinned_idx = pins.data();
   in.leaf_size = opt.leaf_size;
   in.elem_energy = elem_energy.empty() ? nullptr : elem_energy.data();
+  in.tutte = tutte;
   Setup S;
   std::string err;
   int st = build_setup(in, S, err);
@@ -1145,6 +1147,40 @@ ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* 
   std::vector<double> ppos;
   if (opt->n_pinned > 0 && opt->pinned_pos) ppos.assign(opt->pinned_pos, opt->pinned_pos + opt->n_pinned * d);
   return create_impl(*mesh, *opt, pins, ppos, auto_pinned, {}, {}, {}, out);
+}
+
+ffd_status ffd_tutte_map(const ffd_mesh* mesh, int64_t n_fixed, const int32_t* fixed_idx, const double* fixed_pos,
+                         int32_t leaf_size, double* map_dev, void* stream) {
+  if (!mesh || !map_dev || n_fixed <= 0 || !fixed_idx || !fixed_pos)
+    return fail(FFD_ERR_INVALID_ARG, "NULL argument or no fixed vertex");
+  const int d = mesh->simplex_dim;
+  if (!(d == 2 || d == 3)) return fail(FFD_ERR_INVALID_ARG, "unsupported simplex_dim");
+  for (int64_t i = 0; i < n_fixed * d; ++i)
+    if (!std::isfinite(fixed_pos[i])) return fail(FFD_ERR_NOT_FINITE, "non-finite fixed position");
+  ffd_options opt{};
+  opt.energy = 0;
+  opt.rho = 1.0;
+  opt.precision = 64;
+  opt.leaf_size = leaf_size;
+  std::vector<int32_t> pins(fixed_idx, fixed_idx + n_fixed);
+  std::vector<double> ppos(fixed_pos, fixed_pos + n_fixed * d);
+  ffd_handle h = nullptr;
+  ffd_status st = create_impl(*mesh, opt, pins, ppos, false, {}, {}, {}, &h, true);
+  if (st != FFD_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // b = -L_FC x_C (the fixed rows go straight into the map), then the two
+  // triangular solves into the free rows, then the caller's vertex order
+  double* x = h->x[0];
+  hipLaunchKernelGGL((d == 2 ? k_fixed_rhs<2> : k_fixed_rhs<3>), dim3(nblk(h->n)), dim3(kBlock), 0, s, h->nF, h->n,
+                     h->pin_ptr, h->pin_col, h->pin_val, h->xC, h->b, x);
+  do_solve(h, h->b, x, s);
+  hipLaunchKernelGGL((d == 2 ? k_map_out<2> : k_map_out<3>), dim3(nblk(h->n)), dim3(kBlock), 0, s, h->n,
+                     h->vnew2old_d, x, map_dev);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  ffd_destroy(h);
+  if (e != hipSuccess) return fail(FFD_ERR_DEVICE, hipGetErrorString(e));
+  return FFD_OK;
 }
 
 ffd_status ffd_batch_create(const ffd_mesh* meshes, const ffd_options* opts, int32_t n_meshes, ffd_handle* out) {

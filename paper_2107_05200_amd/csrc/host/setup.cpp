@@ -303,10 +303,40 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
   for (int64_t v = 0; v < n; ++v) Lptr[v + 1] = Lptr[v] + static_cast<int64_t>(rowpat[v].size());
   std::vector<int32_t> Lcol(Lptr[n]);
   std::vector<double> Lval(Lptr[n], 0.0);
+  int64_t zero_edge = -1;
 #pragma omp parallel for schedule(dynamic, 256)
   for (int64_t v = 0; v < n; ++v) {
     std::copy(rowpat[v].begin(), rowpat[v].end(), Lcol.begin() + Lptr[v]);
     std::vector<int32_t>().swap(rowpat[v]);
+    if (in.tutte) {
+      // Tutte's energy (supplement "Tutte's Energy"): every edge (v, u) of an
+      // element counted once with weight 1 / |V_v - V_u|; its Hessian is twice
+      // this graph Laplacian, whose minimiser with the fixed rows is the map
+      double diag = 0.0;
+      int64_t self = -1;
+      for (int64_t k = Lptr[v]; k < Lptr[v + 1]; ++k) {
+        const int64_t u = Lcol[k];
+        if (u == v) {
+          self = k;
+          continue;
+        }
+        double len2 = 0.0;
+        for (int a = 0; a < din; ++a) {
+          const double dv = in.V[v * din + a] - in.V[u * din + a];
+          len2 += dv * dv;
+        }
+        if (!(len2 > 0.0)) {
+#pragma omp critical
+          zero_edge = v;
+          continue;
+        }
+        const double wgt = 1.0 / std::sqrt(len2);
+        Lval[k] = -wgt;
+        diag += wgt;
+      }
+      Lval[self] = diag;
+      continue;
+    }
     const int32_t* cb = Lcol.data() + Lptr[v];
     const int64_t len = Lptr[v + 1] - Lptr[v];
     for (int64_t k = inc_ptr[v]; k < inc_ptr[v + 1]; ++k) {
@@ -334,6 +364,10 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
     }
   }
   std::vector<std::vector<int32_t>>().swap(rowpat);
+  if (zero_edge >= 0) {
+    err = "an edge at vertex " + std::to_string(zero_edge) + " has zero length (Tutte weight undefined)";
+    return ERR_DEGENERATE_ELEMENT;
+  }
   S.t_geometry = now() - t0;
 
   // every connected component needs a pinned vertex (G maps constants to 0)

@@ -29,6 +29,7 @@ struct SetupInput {
   const int32_t* T = nullptr;    // m x (d+1) row-major
   double rho = 10.0;             // mu_i = rho * w_i
   const double* mu_elem = nullptr;  // optional per-element mu_i (input order, m entries; replaces rho * w_i)
+  bool tutte = false;            // factor the edge Laplacian of Tutte's energy instead of G^T M G
   int64_t n_pinned = 0;
   const int32_t* pinned_idx = nullptr;
   int leaf_size = 0;             // 0: automatic

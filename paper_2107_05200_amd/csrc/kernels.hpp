@@ -1187,6 +1187,34 @@ __global__ void k_map_in(int64_t n, const int32_t* __restrict new2old, const dou
   for (int k = 0; k < D; ++k) xint[j * D + k] = ext[o * D + k];
 }
 
+// right-hand side of a solve whose only data are the fixed rows: b_F = -L_FC x_C
+// (the minimiser of a quadratic energy with fixed vertices); rows >= nF copy
+// the fixed positions into x
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_fixed_rhs(int64_t nF, int64_t n, const int32_t* __restrict pin_ptr,
+                                                      const int32_t* __restrict pin_col,
+                                                      const double* __restrict pin_val, const double* __restrict xC,
+                                                      double* __restrict b, double* __restrict x) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (j >= n) return;
+  if (j >= nF) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[j * D + k] = xC[(j - nF) * D + k];
+    return;
+  }
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  for (int32_t q = pin_ptr[j]; q < pin_ptr[j + 1]; ++q) {
+    const double v = pin_val[q];
+    const int64_t c = pin_col[q];
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] -= v * xC[c * D + k];
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) b[j * D + k] = acc[k];
+}
+
 template <int D>
 __global__ void k_map_out(int64_t n, const int32_t* __restrict new2old, const double* __restrict xint,
                           double* __restrict ext) {

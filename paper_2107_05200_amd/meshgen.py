@@ -320,6 +320,60 @@ def flat_grid(grid: int = 8, rho: float = 10.0, energy: int = SYMMETRIC_DIRICHLE
     return Workload(f"flat_grid_{grid}", V, T, energy, rho, pins, V[pins].copy(), V.copy(), 10)
 
 
+# ----------------------------------------------------------------------------
+# fixed boundaries for Tutte initial maps (inputs, not part of the method)
+# ----------------------------------------------------------------------------
+
+def boundary_vertices(T) -> np.ndarray:
+    """Sorted vertices of the facets that belong to exactly one element."""
+    T = np.asarray(T, dtype=np.int64)
+    nc = T.shape[1]
+    faces = np.concatenate([np.sort(np.delete(T, c, axis=1), axis=1) for c in range(nc)], axis=0)
+    uniq, cnt = np.unique(faces, axis=0, return_counts=True)
+    return np.unique(uniq[cnt == 1]).astype(np.int32)
+
+
+def boundary_loop(T) -> np.ndarray:
+    """The boundary of a triangulated disk as one closed vertex loop, walked
+    along the directed edges of the triangles (counter-clockwise for
+    counter-clockwise triangles)."""
+    T = np.asarray(T, dtype=np.int64)
+    directed = np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]], axis=0)
+    n = int(T.max()) + 1
+    key = directed[:, 0] * n + directed[:, 1]
+    rev = directed[:, 1] * n + directed[:, 0]
+    bnd = directed[~np.isin(rev, key)]
+    if np.unique(bnd[:, 0]).size != bnd.shape[0]:
+        raise ValueError("boundary is not a single simple loop")
+    nxt = dict(zip(bnd[:, 0].tolist(), bnd[:, 1].tolist()))
+    if not nxt:
+        raise ValueError("closed surface: no boundary")
+    start = min(nxt)
+    loop = [start]
+    while True:
+        v = nxt[loop[-1]]
+        if v == start:
+            break
+        loop.append(v)
+        if len(loop) > len(nxt):
+            raise ValueError("boundary is not a single simple loop")
+    if len(loop) != len(nxt):
+        raise ValueError("boundary has several loops")
+    return np.asarray(loop, dtype=np.int32)
+
+
+def circle_boundary(V, T, radius: float = 1.0):
+    """The boundary loop of a disk placed on a circle, each vertex at the
+    angle of its arc length along the loop in the source mesh.  Returns
+    (indices, positions (len, 2))."""
+    V = np.asarray(V, dtype=np.float64)
+    loop = boundary_loop(T)
+    seg = np.linalg.norm(V[np.roll(loop, -1)] - V[loop], axis=1)
+    arc = np.concatenate([[0.0], np.cumsum(seg)[:-1]])
+    ang = 2.0 * np.pi * arc / seg.sum()
+    return loop, radius * np.stack([np.cos(ang), np.sin(ang)], axis=1)
+
+
 CONFIGS = {
     "C1": lambda: height_field_uv(),
     "C2": lambda: sphere_cap_uv(),

@@ -372,7 +372,8 @@ class OracleSolver:
     gamma = 1, epsilon = 0, and the B_i of Section "Implementation").
     """
 
-    def __init__(self, V, T, energy: int, rho: float, pinned_idx, pinned_pos, h_mode: int = 0):
+    def __init__(self, V, T, energy: int, rho: float, pinned_idx, pinned_pos, h_mode: int = 0,
+                 constraints=None):
         self.V = np.asarray(V, dtype=np.float64)
         self.T = np.asarray(T, dtype=np.int64)
         self.n = self.V.shape[0]
@@ -385,15 +386,22 @@ class OracleSolver:
         self.mu = self.rho * self.w
         self.G = gradient_operator(self.B, self.T, self.n)
         self.L = global_matrix(self.G, self.mu, self.d)
-        pins = np.asarray(pinned_idx, dtype=np.int64)
-        if pins.size == 0:
-            pins = np.array([0], dtype=np.int64)  # fix the first vertex (W-step text)
+        pins = np.asarray(pinned_idx if pinned_idx is not None else [], dtype=np.int64)
+        # general linear constraints A W = c (eq. solvinginw): A is (rows, n),
+        # c is (rows, d); the pins are the constraints that fix a vertex
+        self.A = None if constraints is None else sp.csr_matrix(constraints[0], dtype=np.float64)
+        self.c = None if constraints is None else \
+            np.asarray(constraints[1], dtype=np.float64).reshape(self.A.shape[0], self.d)
+        if pins.size == 0 and self.A is None:
+            pins = np.array([0], dtype=np.int64)  # no constraints: fix the first vertex (W-step text)
             self.auto_pinned = True
         else:
             self.auto_pinned = False
         self.pins = pins
         self.pin_pos = None if (self.auto_pinned or pinned_pos is None) else \
             np.asarray(pinned_pos, dtype=np.float64).reshape(-1, self.d)
+        if pins.size == 0:
+            self.pin_pos = np.zeros((0, self.d))
         self.free = np.setdiff1d(np.arange(self.n), pins)
         self.L_FF = self.L[self.free][:, self.free].tocsc()
         self.L_FC = self.L[self.free][:, pins].tocsr()
@@ -489,16 +497,30 @@ class OracleSolver:
     # -- sub-steps -----------------------------------------------------------
     def w_step(self, U, P, Lam):
         """argmin over W with the pins of Phi (eq. solvinginw): L W = G^T r with
-        r_i = mu_i (U_i P_i - Lam_i); pinned rows eliminated."""
+        r_i = mu_i (U_i P_i - Lam_i); pinned rows eliminated.  With general
+        constraints A W = c the minimiser solves the KKT system
+        [L_FF A_F^T; A_F 0] [W_F; Y] = [b; c - A_C W_C] (sparse LU, which
+        takes the indefinite matrix as it is)."""
         r = self.mu[:, None, None] * (U @ P - Lam)
         rhs = np.asarray(self.G.T @ r.reshape(self.m * self.d, self.d))
         b = rhs[self.free] - self.L_FC @ self.pin_pos
-        if self._lu is None:
-            self._lu = spla.splu(self.L_FF)
         x = np.empty((self.n, self.d))
         x[self.pins] = self.pin_pos
-        x[self.free] = self._lu.solve(b)
+        if self.A is None:
+            if self._lu is None:
+                self._lu = spla.splu(self.L_FF)
+            x[self.free] = self._lu.solve(b)
+            return x
+        AF = self.A[:, self.free]
+        cF = self.c - self.A[:, self.pins] @ self.pin_pos
+        if self._lu is None:
+            self._lu = spla.splu(sp.bmat([[self.L_FF, AF.T], [AF, None]]).tocsc())
+        x[self.free] = self._lu.solve(np.vstack([b, cF]))[:self.free.size]
         return x
+
+    def set_constraint_rhs(self, c):
+        """New right-hand sides c of the constraints A W = c."""
+        self.c = np.asarray(c, dtype=np.float64).reshape(self.A.shape[0], self.d)
 
     def iterate(self, n_iter: int = 1):
         """Algorithm 1: W, then U (with P^{k-1}, Lam^{k-1}), then P (with U^k,

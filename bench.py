@@ -207,6 +207,43 @@ def uv_pipeline_leg(max_iter: int = 1000):
             "rescales": nres, "final_flips": int(h[-1, 5]), "final_E_map": float(h[-1, 3])}
 
 
+def constraints_leg(iters: int = 200, rows: int = 48):
+    """Disk deformation (99,846 triangles, 16 handles) with `rows` general
+    constraint rows (vertex-on-segment, fixed-difference and centroid
+    relations): seconds per replayed iteration with and without them."""
+    import numpy as np
+    import torch
+    from paper_2107_05200_amd import binding, meshgen
+    w = meshgen.disk_deformation()
+    rng = np.random.default_rng(48)
+    v = rng.choice(np.setdiff1d(np.arange(w.n), w.pinned_idx), size=7 * (rows // 3), replace=False)
+    A = np.zeros((rows, w.n))
+    c = np.zeros((rows, 2))
+    for i in range(rows // 3):
+        a, b, c_ = v[7 * i:7 * i + 3]
+        A[3 * i, [a, b, c_]] = [1.0, -0.5, -0.5]
+        A[3 * i + 1, [v[7 * i + 3], v[7 * i + 4]]] = [1.0, -1.0]
+        c[3 * i + 1] = w.V[v[7 * i + 3]] - w.V[v[7 * i + 4]]
+        A[3 * i + 2, v[7 * i + 4:7 * i + 7]] = 1.0 / 3.0
+        c[3 * i + 2] = w.V[v[7 * i + 4:7 * i + 7]].mean(axis=0)
+    out = {}
+    for name, con in (("plain", None), ("constrained", (A, c))):
+        t0 = time.perf_counter()
+        s = binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32, constraints=con)
+        setup = time.perf_counter() - t0
+        s.init(w.V).iterate(10, graph=True)
+        torch.cuda.synchronize()
+        s.init(w.V)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(iters, graph=True)
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_iter": (time.perf_counter() - t0) / iters * 1e3, "setup_s": setup}
+        s.close()
+    return {"workload": f"disk deformation, {w.m:,} triangles, 16 handles, {rows} constraint rows, {iters} iterations",
+            **out, "ratio": out["constrained"]["ms_per_iter"] / out["plain"]["ms_per_iter"]}
+
+
 def _cpu_name():
     try:
         for ln in open("/proc/cpuinfo"):
@@ -226,7 +263,7 @@ def main():
     ap.add_argument("--precision", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=200000)
-    ap.add_argument("--no-extra", action="store_true", help="skip the adjoint, batched and UV-pipeline legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the adjoint, batched, constraints and UV-pipeline legs")
     ap.add_argument("--tune-cache", default=None, help="launch-shape cache file (read, or written after tuning)")
     ap.add_argument("--no-graph", action="store_true", help="time direct launches instead of replayed HIP graphs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -364,6 +401,9 @@ def main():
         t0 = time.perf_counter()
         out["batched"] = batched_leg()
         log(f"batched leg: {out['batched']} ({time.perf_counter() - t0:.1f}s)")
+        t0 = time.perf_counter()
+        out["constraints"] = constraints_leg()
+        log(f"constraints leg: {out['constraints']} ({time.perf_counter() - t0:.1f}s)")
         t0 = time.perf_counter()
         out["uv_pipeline"] = uv_pipeline_leg()
         log(f"uv pipeline leg: {out['uv_pipeline']} ({time.perf_counter() - t0:.1f}s)")

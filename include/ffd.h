@@ -120,6 +120,38 @@ typedef struct {
  * HIP device.  Synchronous.  On success *out is a new handle. */
 ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* out);
 
+/* General linear constraints A W = c on the map (eq. solvinginw; the W-step
+ * text), beyond pins: rows of A in CSR over vertex indices (distinct columns
+ * per row, at least one free vertex per row), c = rhs (host, n_rows x
+ * simplex_dim row-major; the same row of A acts on every output
+ * coordinate).  At most 1024 rows. */
+typedef struct {
+  int64_t n_rows;
+  const int64_t* row_ptr; /* host, n_rows + 1, row_ptr[0] = 0 */
+  const int32_t* col_idx; /* host, vertex indices                 */
+  const double* val;      /* host                                 */
+  const double* rhs;      /* host, n_rows x simplex_dim           */
+} ffd_constraints;
+
+/* As ffd_create, with general constraints.  The W-step then returns the
+ * constrained minimiser of eq. solvinginw: the host factorises
+ * L_FF + gamma A_F^T A_F (gamma > 0 scales A to L's diagonal; the
+ * minimiser on the constraint set is the same for any gamma, and the matrix
+ * is definite when the constraints and pins fix every component's
+ * translation), and the device adds the KKT correction x = y - Z lambda with
+ * Z = L~^{-1} A_F^T (n_rows x n_free float64 kept on the device) and the
+ * explicit inverse of S = A_F Z.  No vertex is fixed automatically (the first
+ * vertex is fixed only when there are no constraints).  ffd_solve solves
+ * with the factorised matrix; the adjoint entry points refuse such a handle
+ * (FFD_ERR_STATE).  Errors: as ffd_create; FFD_ERR_SINGULAR_SYSTEM when the
+ * rows are dependent (with the pins) or a component's translation stays free. */
+ffd_status ffd_create_constrained(const ffd_mesh* mesh, const ffd_options* opt, const ffd_constraints* con,
+                                  ffd_handle* out);
+
+/* New right-hand sides c (device, n_rows x simplex_dim float64) for the next
+ * W-steps; stream-ordered. */
+ffd_status ffd_set_constraint_rhs(ffd_handle h, const double* rhs_dev, void* stream);
+
 /* Minimiser of Tutte's energy (supplement "Tutte's Energy", Table 1): the sum
  * over the mesh edges (i, j) of |W_i - W_j|^2 / |V_i - V_j|, with the n_fixed
  * vertices fixed_idx held at fixed_pos (host, n_fixed x simplex_dim

@@ -41,6 +41,11 @@ class Options(C.Structure):
                 ("auto_pin", C.c_int32), ("leaf_size", C.c_int32)]
 
 
+class Constraints(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
+                ("rhs", C.c_void_p)]
+
+
 class Info(C.Structure):
     _fields_ = [("n_free", C.c_int64), ("n_pinned", C.c_int64), ("factor_nnz", C.c_int64),
                 ("panel_entries", C.c_int64), ("n_nodes", C.c_int32), ("n_levels", C.c_int32),
@@ -65,6 +70,8 @@ _PROTOS = {
     "ffd_iterate_until": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
                                     C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ffd_rescale": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
+    "ffd_create_constrained": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ffd_set_constraint_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ffd_tutte_map": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "ffd_run": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_int32,
                           C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -174,7 +181,9 @@ class Solver:
     sums in float64); precision 64: everything float64."""
 
     def __init__(self, V, T, energy=0, rho=10.0, pinned_idx=None, pinned_pos=None, precision=32,
-                 h_mode=0, auto_pin=1, leaf_size=0):
+                 h_mode=0, auto_pin=1, leaf_size=0, constraints=None):
+        """constraints: optional (A, c) with A a (rows, n) matrix (dense or
+        scipy sparse) and c (rows, d): general linear constraints A W = c."""
         import torch
         self.lib = load()
         V = np.asarray(V)
@@ -189,9 +198,22 @@ class Solver:
         op, keep2 = _options_struct(self.d, energy, rho, pinned_idx, pinned_pos, precision, h_mode,
                                     auto_pin, leaf_size)
         h = C.c_void_p()
-        _check(self.lib.ffd_create(C.byref(ms), C.byref(op), C.byref(h)))
+        self.n_constraints = 0
+        if constraints is None:
+            _check(self.lib.ffd_create(C.byref(ms), C.byref(op), C.byref(h)))
+        else:
+            import scipy.sparse as sp
+            A = sp.csr_matrix(constraints[0], dtype=np.float64)
+            A.sort_indices()
+            rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
+            ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+            va = np.ascontiguousarray(A.data, dtype=np.float64)
+            rh = np.ascontiguousarray(constraints[1], dtype=np.float64).reshape(A.shape[0], self.d)
+            con = Constraints(A.shape[0], rp.ctypes.data, ci.ctypes.data, va.ctypes.data, rh.ctypes.data)
+            _check(self.lib.ffd_create_constrained(C.byref(ms), C.byref(op), C.byref(con), C.byref(h)))
+            self.n_constraints = A.shape[0]
         self.h = h
-        if self.n_pinned == 0 and auto_pin:
+        if self.n_pinned == 0 and auto_pin and constraints is None:
             self.n_pinned = 1
         self.device = torch.device("cuda", torch.cuda.current_device())
 
@@ -244,6 +266,14 @@ class Solver:
                                           int(bool(flip_free)), int(bool(graph)), _stream(stream),
                                           C.byref(done), C.byref(conv)))
         return done.value, bool(conv.value)
+
+    def set_constraint_rhs(self, c, stream=None):
+        """New right-hand sides c (rows, d) of the general constraints."""
+        import torch
+        cs = self._dev(c, torch.float64).reshape(self.n_constraints, self.d)
+        _check(self.lib.ffd_set_constraint_rhs(self.h, C.c_void_p(cs.data_ptr()), _stream(stream)))
+        self._keep_rhs = cs
+        return self
 
     def rescale(self, rho_r: float = 5.0, stream=None):
         """One penalty rescaling event (new per-element mu, Lambda, factor)."""

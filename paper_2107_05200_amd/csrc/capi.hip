@@ -120,6 +120,19 @@ struct ffd_ctx {
   int in_leaf = 0;
   size_t n_pin_val = 0, n_lcf_val = 0;
   double* gtl_part = nullptr;    // per-block partial sums of |G^T Lambda|^2
+  // general linear constraints A W = c: rows of A (device numbering; host and
+  // device copies), the transposed free part over the rows it touches, the
+  // right-hand sides c, per-iteration c', A y - c', lambda, the precomputed
+  // Z = L~^{-1} A_F^T (column-major) and S^{-1}, and a solve scratch vector
+  int64_t ncon = 0, ncon_rows = 0;
+  double con_gamma = 0;
+  std::vector<int64_t> con_ptr_h, in_con_ptr;
+  std::vector<int32_t> con_col_h, in_con_col;
+  std::vector<double> con_val_h, in_con_val;
+  int64_t* con_ptr = nullptr;
+  int32_t *con_col = nullptr, *cont_rows = nullptr, *cont_ptr = nullptr, *cont_con = nullptr;
+  double *con_val = nullptr, *cont_val = nullptr, *con_c = nullptr, *con_cp = nullptr, *con_t = nullptr;
+  double *con_lam = nullptr, *con_Z = nullptr, *con_Sinv = nullptr, *con_tmp = nullptr;
   std::vector<LevelCfg> cfg_fwd, cfg_bwd;  // per-level launch configuration of both solve passes
   // The forest below level solve_top is split into solve_groups groups of
   // whole subtrees, each solved on its own stream (group 0 on the caller's);
@@ -432,6 +445,102 @@ void do_solve(ffd_ctx* h, const double* b, double* x, hipStream_t s) {
   else launch_solve<3>(h, b, x, s);
 }
 
+// the constraint terms of the W-step: c' = c - A_C x_C and b += gamma A_F^T c'
+// before the solve, x_F -= Z S^{-1} (A x - c) after it
+template <int D>
+void con_before_solve_d(ffd_ctx* h, hipStream_t s) {
+  hipLaunchKernelGGL(k_con_shift<D>, dim3(nblk(h->ncon)), dim3(kBlock), 0, s, h->ncon, h->nF, h->con_ptr,
+                     h->con_col, h->con_val, h->con_c, h->xC, h->con_cp);
+  hipLaunchKernelGGL(k_con_addq<D>, dim3(nblk(h->ncon_rows)), dim3(kBlock), 0, s, h->ncon_rows, h->cont_rows,
+                     h->cont_ptr, h->cont_con, h->cont_val, h->con_gamma, h->con_cp, h->b);
+}
+template <int D>
+void con_after_solve_d(ffd_ctx* h, double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_con_resid<D>, dim3(nblk(h->ncon)), dim3(kBlock), 0, s, h->ncon, h->con_ptr, h->con_col,
+                     h->con_val, h->con_c, x, h->con_t);
+  hipLaunchKernelGGL(k_con_lambda<D>, dim3(nblk(h->ncon)), dim3(kBlock), 0, s, h->ncon, h->con_Sinv, h->con_t,
+                     h->con_lam);
+  if (h->nF > 0)
+    hipLaunchKernelGGL(k_con_correct<D>, dim3(nblk(h->nF)), dim3(kBlock), 0, s, h->nF, h->ncon, h->con_Z,
+                       h->con_lam, x);
+}
+void con_before_solve(ffd_ctx* h, hipStream_t s) {
+  if (h->d == 2) con_before_solve_d<2>(h, s);
+  else con_before_solve_d<3>(h, s);
+}
+void con_after_solve(ffd_ctx* h, double* x, hipStream_t s) {
+  if (h->d == 2) con_after_solve_d<2>(h, x, s);
+  else con_after_solve_d<3>(h, x, s);
+}
+
+// Z = L~^{-1} A_F^T by solves of D columns at a time, S = A_F Z on the device,
+// S^{-1} on the host (Cholesky with a relative pivot floor: dependent rows
+// are an error).  Synchronous; uses b and con_tmp as scratch.
+ffd_status prepare_constraints(ffd_ctx* h, hipStream_t s) {
+  const int d = h->d;
+  const int64_t nF = h->nF, nc = h->ncon;
+  std::vector<double> rhs(static_cast<size_t>(nF) * d, 0.0);
+  for (int64_t a0 = 0; a0 < nc; a0 += d) {
+    for (int k = 0; k < d && a0 + k < nc; ++k)
+      for (int64_t q = h->con_ptr_h[a0 + k]; q < h->con_ptr_h[a0 + k + 1]; ++q)
+        if (h->con_col_h[q] < nF) rhs[static_cast<size_t>(h->con_col_h[q]) * d + k] = h->con_val_h[q];
+    HIP_TRY(hipMemcpyAsync(h->b, rhs.data(), rhs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    do_solve(h, h->b, h->con_tmp, s);
+    hipLaunchKernelGGL((d == 2 ? k_con_zcols<2> : k_con_zcols<3>), dim3(nblk(nF)), dim3(kBlock), 0, s, nF, nc, a0,
+                       h->con_tmp, h->con_Z);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < d && a0 + k < nc; ++k)
+      for (int64_t q = h->con_ptr_h[a0 + k]; q < h->con_ptr_h[a0 + k + 1]; ++q)
+        if (h->con_col_h[q] < nF) rhs[static_cast<size_t>(h->con_col_h[q]) * d + k] = 0.0;
+  }
+  hipLaunchKernelGGL(k_con_gram, dim3(nblk(nc * nc)), dim3(kBlock), 0, s, nF, nc, h->con_ptr, h->con_col, h->con_val,
+                     h->con_Z, h->con_Sinv);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> S(static_cast<size_t>(nc) * nc), X(static_cast<size_t>(nc) * nc, 0.0);
+  HIP_TRY(hipMemcpyAsync(S.data(), h->con_Sinv, S.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  // symmetrise, then S = C C^T (C lower, row-major in place)
+  double dmax = 0.0;
+  for (int64_t i = 0; i < nc; ++i) {
+    for (int64_t j = 0; j < i; ++j) S[i * nc + j] = S[j * nc + i] = 0.5 * (S[i * nc + j] + S[j * nc + i]);
+    dmax = std::max(dmax, S[i * nc + i]);
+  }
+  for (int64_t j = 0; j < nc; ++j) {
+    double dj = S[j * nc + j];
+    for (int64_t l = 0; l < j; ++l) dj -= S[j * nc + l] * S[j * nc + l];
+    if (!(dj > 1e-12 * dmax) || !std::isfinite(dj))
+      return fail(FFD_ERR_SINGULAR_SYSTEM, "constraint row " + std::to_string(j) +
+                                               " depends on the others (with the pins): the constraint system is singular");
+    dj = std::sqrt(dj);
+    S[j * nc + j] = dj;
+    for (int64_t i = j + 1; i < nc; ++i) {
+      double t = S[i * nc + j];
+      for (int64_t l = 0; l < j; ++l) t -= S[i * nc + l] * S[j * nc + l];
+      S[i * nc + j] = t / dj;
+    }
+  }
+  // X = C^{-1} (lower), then S^{-1} = X^T X
+  for (int64_t j = 0; j < nc; ++j) {
+    X[j * nc + j] = 1.0 / S[j * nc + j];
+    for (int64_t i = j + 1; i < nc; ++i) {
+      double t = 0.0;
+      for (int64_t l = j; l < i; ++l) t += S[i * nc + l] * X[l * nc + j];
+      X[i * nc + j] = -t / S[i * nc + i];
+    }
+  }
+  std::vector<double> Si(static_cast<size_t>(nc) * nc);
+  for (int64_t i = 0; i < nc; ++i)
+    for (int64_t j = 0; j <= i; ++j) {
+      double t = 0.0;
+      for (int64_t l = i; l < nc; ++l) t += X[l * nc + i] * X[l * nc + j];
+      Si[i * nc + j] = Si[j * nc + i] = t;
+    }
+  HIP_TRY(hipMemcpyAsync(h->con_Sinv, Si.data(), Si.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return FFD_OK;
+}
+
 // one iteration of Algorithm 1; with ev != nullptr an event is recorded after
 // each of the five phases
 // store_u: write the rotation and |grad f|^2 of this iteration even where the
@@ -445,6 +554,7 @@ void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true
   double* xold = h->x[h->cur];
   double* xnew = h->x[1 - h->cur];
   do_wrhs(h, xnew, s);
+  if (h->ncon > 0) con_before_solve(h, s);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (h->nF > 0) {
     if (h->d == 2) launch_solve_fwd<2>(h, h->b, s);
@@ -455,6 +565,7 @@ void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true
     if (h->d == 2) launch_solve_bwd<2>(h, xnew, s);
     else launch_solve_bwd<3>(h, xnew, s);
   }
+  if (h->ncon > 0) con_after_solve(h, xnew, s);
   if (ev) (void)hipEventRecord(ev[2], s);
   do_local(h, xnew, xold, store_u ? 1 : 0, s, diag ? h->glam : nullptr);
   if (ev) (void)hipEventRecord(ev[3], s);
@@ -769,6 +880,12 @@ ffd_status refactor(ffd_ctx* h, const std::vector<double>* mu_dev_order, hipStre
   in.pinned_idx = h->in_pins.data();
   in.leaf_size = h->in_leaf;
   in.elem_energy = h->in_energy.empty() ? nullptr : h->in_energy.data();
+  if (h->ncon > 0) {
+    in.n_con = h->ncon;
+    in.con_ptr = h->in_con_ptr.data();
+    in.con_col = h->in_con_col.data();
+    in.con_val = h->in_con_val.data();
+  }
   if (mu_dev_order) {
     mu_in.resize(h->m);
     for (int64_t e = 0; e < h->m; ++e) mu_in[h->enew2old_h[e]] = (*mu_dev_order)[e];
@@ -798,6 +915,11 @@ ffd_status refactor(ffd_ctx* h, const std::vector<double>* mu_dev_order, hipStre
   if (!S.lcf_val.empty())
     HIP_TRY(hipMemcpyAsync(h->lcf_val, S.lcf_val.data(), S.lcf_val.size() * sizeof(double), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (h->ncon > 0) {
+    h->con_gamma = S.con_gamma;
+    h->graph_valid = false;  // gamma is a kernel argument
+    return prepare_constraints(h, s);
+  }
   return FFD_OK;
 }
 
@@ -949,7 +1071,7 @@ namespace {
 ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const std::vector<int32_t>& pins,
                        const std::vector<double>& pin_pos, bool auto_pinned, const std::vector<int8_t>& elem_energy,
                        const std::vector<int64_t>& voff, const std::vector<int64_t>& eoff, ffd_handle* out,
-                       bool tutte = false) {
+                       bool tutte = false, const ffd_constraints* con = nullptr) {
   const ffd_mesh* mesh = &mesh_in;
   const int d = mesh->simplex_dim;
   SetupInput in;
@@ -965,6 +1087,12 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
   in.leaf_size = opt.leaf_size;
   in.elem_energy = elem_energy.empty() ? nullptr : elem_energy.data();
   in.tutte = tutte;
+  if (con && con->n_rows > 0) {
+    in.n_con = con->n_rows;
+    in.con_ptr = con->row_ptr;
+    in.con_col = con->col_idx;
+    in.con_val = con->val;
+  }
   Setup S;
   std::string err;
   int st = build_setup(in, S, err);
@@ -1000,6 +1128,17 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
   h->in_energy = elem_energy;
   h->in_leaf = opt.leaf_size;
   h->enew2old_h = S.enew2old;
+  if (in.n_con > 0) {
+    h->ncon = in.n_con;
+    h->in_con_ptr.assign(in.con_ptr, in.con_ptr + in.n_con + 1);
+    h->in_con_col.assign(in.con_col, in.con_col + in.con_ptr[in.n_con]);
+    h->in_con_val.assign(in.con_val, in.con_val + in.con_ptr[in.n_con]);
+    h->con_ptr_h = S.con_ptr;
+    h->con_col_h = S.con_col;
+    h->con_val_h = S.con_val;
+    h->con_gamma = S.con_gamma;
+    h->ncon_rows = static_cast<int64_t>(S.cont_rows.size());
+  }
   const int64_t m = S.m, n = S.n, nc = d + 1;
   hipError_t e = hipSuccess;
 #define UP(expr)                                                     \
@@ -1100,8 +1239,29 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
   UP(upload(h, &h->pull_ptr, S.pull_ptr));
   UP(upload(h, &h->pull_idx, S.pull_idx));
   if (h->pins_given) UP(hipMemcpy(h->xC, pin_pos.data(), pin_pos.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (h->ncon > 0) {
+    const std::vector<double> crhs(con->rhs, con->rhs + h->ncon * d);
+    UP(upload(h, &h->con_ptr, S.con_ptr));
+    UP(upload(h, &h->con_col, S.con_col));
+    UP(upload(h, &h->con_val, S.con_val));
+    UP(upload(h, &h->cont_rows, S.cont_rows));
+    UP(upload(h, &h->cont_ptr, S.cont_ptr));
+    UP(upload(h, &h->cont_con, S.cont_con));
+    UP(upload(h, &h->cont_val, S.cont_val));
+    UP(upload(h, &h->con_c, crhs));
+    UP(h->alloc(&h->con_cp, static_cast<size_t>(h->ncon) * d));
+    UP(h->alloc(&h->con_t, static_cast<size_t>(h->ncon) * d));
+    UP(h->alloc(&h->con_lam, static_cast<size_t>(h->ncon) * d));
+    UP(h->alloc(&h->con_Z, static_cast<size_t>(h->ncon) * static_cast<size_t>(std::max<int64_t>(S.nF, 1))));
+    UP(h->alloc(&h->con_Sinv, static_cast<size_t>(h->ncon) * h->ncon));
+    UP(h->alloc(&h->con_tmp, static_cast<size_t>(n) * d));
+  }
   UP(hipDeviceSynchronize());
 #undef UP
+  if (h->ncon > 0) {
+    const ffd_status cst = prepare_constraints(h, nullptr);
+    if (cst != FFD_OK) return cleanup(cst);
+  }
   const auto t1 = std::chrono::steady_clock::now();
   ffd_info& I = h->info;
   I.n_free = S.nF;
@@ -1147,6 +1307,46 @@ ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* 
   std::vector<double> ppos;
   if (opt->n_pinned > 0 && opt->pinned_pos) ppos.assign(opt->pinned_pos, opt->pinned_pos + opt->n_pinned * d);
   return create_impl(*mesh, *opt, pins, ppos, auto_pinned, {}, {}, {}, out);
+}
+
+ffd_status ffd_create_constrained(const ffd_mesh* mesh, const ffd_options* opt, const ffd_constraints* con,
+                                  ffd_handle* out) {
+  if (!mesh || !opt || !con || !out) return fail(FFD_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (con->n_rows <= 0 || con->n_rows > kMaxConstraints || !con->row_ptr || !con->col_idx || !con->val || !con->rhs)
+    return fail(FFD_ERR_INVALID_ARG, "constraints: 1 to 1024 rows with row_ptr, col_idx, val and rhs required");
+  if (!(opt->energy == 0 || opt->energy == 1)) return fail(FFD_ERR_INVALID_ARG, "energy must be 0 or 1");
+  if (!(opt->precision == 32 || opt->precision == 64)) return fail(FFD_ERR_INVALID_ARG, "precision must be 32 or 64");
+  if (!(opt->h_mode == 0 || opt->h_mode == 1)) return fail(FFD_ERR_INVALID_ARG, "h_mode must be 0 or 1");
+  if (opt->n_pinned < 0 || (opt->n_pinned > 0 && !opt->pinned_idx))
+    return fail(FFD_ERR_INVALID_ARG, "bad pinned vertex list");
+  const int d = mesh->simplex_dim;
+  if (!(d == 2 || d == 3)) return fail(FFD_ERR_INVALID_ARG, "unsupported simplex_dim");
+  for (int64_t i = 0; i < con->n_rows * d; ++i)
+    if (!std::isfinite(con->rhs[i])) return fail(FFD_ERR_NOT_FINITE, "non-finite constraint right-hand side");
+  std::vector<int32_t> pins;
+  std::vector<double> ppos;
+  if (opt->n_pinned > 0) {
+    pins.assign(opt->pinned_idx, opt->pinned_idx + opt->n_pinned);
+    if (opt->pinned_pos) {
+      for (int64_t i = 0; i < opt->n_pinned * d; ++i)
+        if (!std::isfinite(opt->pinned_pos[i])) return fail(FFD_ERR_NOT_FINITE, "non-finite pinned position");
+      ppos.assign(opt->pinned_pos, opt->pinned_pos + opt->n_pinned * d);
+    }
+  }
+  // with constraints no vertex is fixed automatically (the W-step text fixes
+  // the first vertex only when there are no constraints)
+  return create_impl(*mesh, *opt, pins, ppos, false, {}, {}, {}, out, false, con);
+}
+
+ffd_status ffd_set_constraint_rhs(ffd_handle h, const double* rhs_dev, void* stream) {
+  if (!h || !rhs_dev) return fail(FFD_ERR_INVALID_ARG, "NULL argument");
+  if (h->ncon == 0) return fail(FFD_ERR_STATE, "the handle has no general constraints");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(h->con_c, rhs_dev, static_cast<size_t>(h->ncon) * h->d * sizeof(double),
+                         hipMemcpyDeviceToDevice, s));
+  h->last_stream = s;
+  return FFD_OK;
 }
 
 ffd_status ffd_tutte_map(const ffd_mesh* mesh, int64_t n_fixed, const int32_t* fixed_idx, const double* fixed_pos,
@@ -1670,6 +1870,7 @@ ffd_status ffd_adjoint_forward(ffd_handle h, int32_t n_iter, int32_t checkpoint_
   if (!h->initialized) return fail(FFD_ERR_STATE, "ffd_adjoint_forward before ffd_init / ffd_set_state");
   if (n_iter <= 0 || checkpoint_every <= 0) return fail(FFD_ERR_INVALID_ARG, "n_iter and checkpoint_every must be > 0");
   if (h->rescaled) return fail(FFD_ERR_STATE, "the adjoint differentiates mu_i = rho w_i: not after a rescaling");
+  if (h->ncon > 0) return fail(FFD_ERR_STATE, "the adjoint is not built for general constraints");
   hipStream_t s = static_cast<hipStream_t>(stream);
   ffd_status st = ensure_hist(h, h->k + n_iter, s);
   if (st != FFD_OK) return st;

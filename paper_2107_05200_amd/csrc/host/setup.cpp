@@ -17,6 +17,7 @@
 #include "setup.hpp"
 
 #include <omp.h>
+#include <tuple>
 
 #include <algorithm>
 #include <chrono>
@@ -249,6 +250,37 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
           err = "element " + std::to_string(e) + " repeats a vertex";
           return ERR_DEGENERATE_ELEMENT;
         }
+  if (in.n_con < 0 || (in.n_con > 0 && (!in.con_ptr || !in.con_col || !in.con_val || in.tutte))) {
+    err = "bad constraint arrays";
+    return ERR_INVALID_ARG;
+  }
+  if (in.n_con > 0) {
+    if (in.con_ptr[0] != 0) {
+      err = "constraint row_ptr must start at 0";
+      return ERR_INVALID_ARG;
+    }
+    for (int64_t a = 0; a < in.n_con; ++a) {
+      if (in.con_ptr[a + 1] <= in.con_ptr[a]) {
+        err = "constraint row " + std::to_string(a) + " is empty or row_ptr decreases";
+        return ERR_INVALID_ARG;
+      }
+      for (int64_t q = in.con_ptr[a]; q < in.con_ptr[a + 1]; ++q) {
+        if (in.con_col[q] < 0 || in.con_col[q] >= n) {
+          err = "constraint column out of range";
+          return ERR_INVALID_ARG;
+        }
+        if (!std::isfinite(in.con_val[q])) {
+          err = "non-finite constraint coefficient";
+          return ERR_NOT_FINITE;
+        }
+        for (int64_t q2 = in.con_ptr[a]; q2 < q; ++q2)
+          if (in.con_col[q2] == in.con_col[q]) {
+            err = "constraint row " + std::to_string(a) + " repeats a vertex";
+            return ERR_INVALID_ARG;
+          }
+      }
+    }
+  }
   std::vector<uint8_t> pinned(n, 0);
   for (int64_t i = 0; i < in.n_pinned; ++i) {
     const int32_t v = in.pinned_idx[i];
@@ -370,30 +402,155 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
   }
   S.t_geometry = now() - t0;
 
-  // every connected component needs a pinned vertex (G maps constants to 0)
+  // every connected component needs a pinned vertex (G maps constants to 0),
+  // or, with general constraints, the constraints must fix the translations
+  // of the components without one: A times their indicator vectors has full
+  // column rank
   {
     std::vector<int32_t> comp(n, -1), stack;
+    std::vector<int64_t> unpinned;  // one vertex of each component without a pin
+    int32_t nco = 0;
     for (int64_t s0 = 0; s0 < n; ++s0) {
       if (comp[s0] >= 0) continue;
       bool has_pin = false;
       stack.push_back(static_cast<int32_t>(s0));
-      comp[s0] = 1;
+      comp[s0] = nco;
       while (!stack.empty()) {
         const int32_t v = stack.back();
         stack.pop_back();
         has_pin |= pinned[v] != 0;
         for (int64_t k = Lptr[v]; k < Lptr[v + 1]; ++k)
           if (comp[Lcol[k]] < 0) {
-            comp[Lcol[k]] = 1;
+            comp[Lcol[k]] = nco;
             stack.push_back(Lcol[k]);
           }
       }
-      if (!has_pin) {
-        err = "a connected component (containing vertex " + std::to_string(s0) +
-              ") has no pinned vertex: the W-step system is singular";
+      if (!has_pin) unpinned.push_back(s0);
+      ++nco;
+    }
+    if (!unpinned.empty() && in.n_con == 0) {
+      err = "a connected component (containing vertex " + std::to_string(unpinned[0]) +
+            ") has no pinned vertex: the W-step system is singular";
+      return ERR_SINGULAR_SYSTEM;
+    }
+    if (!unpinned.empty()) {
+      const int64_t nu = static_cast<int64_t>(unpinned.size());
+      if (nu > 4096) {
+        err = "more than 4096 connected components without a pinned vertex";
+        return ERR_INVALID_ARG;
+      }
+      std::vector<int32_t> slot(nco, -1);
+      for (int64_t i = 0; i < nu; ++i) slot[comp[unpinned[i]]] = static_cast<int32_t>(i);
+      // Gram matrix of the columns A 1_c, then a Cholesky with a relative pivot floor
+      std::vector<double> Mrow(nu), Gm(nu * nu, 0.0);
+      for (int64_t a = 0; a < in.n_con; ++a) {
+        std::fill(Mrow.begin(), Mrow.end(), 0.0);
+        for (int64_t q = in.con_ptr[a]; q < in.con_ptr[a + 1]; ++q) {
+          const int32_t c = slot[comp[in.con_col[q]]];
+          if (c >= 0 && !pinned[in.con_col[q]]) Mrow[c] += in.con_val[q];
+        }
+        for (int64_t i = 0; i < nu; ++i)
+          if (Mrow[i] != 0.0)
+            for (int64_t j = 0; j < nu; ++j) Gm[i * nu + j] += Mrow[i] * Mrow[j];
+      }
+      double dmax = 0.0;
+      for (int64_t i = 0; i < nu; ++i) dmax = std::max(dmax, Gm[i * nu + i]);
+      bool ok = dmax > 0.0;
+      for (int64_t j = 0; ok && j < nu; ++j) {
+        double dj = Gm[j * nu + j];
+        for (int64_t l = 0; l < j; ++l) dj -= Gm[j * nu + l] * Gm[j * nu + l];
+        if (!(dj > 1e-12 * dmax)) {
+          ok = false;
+          break;
+        }
+        dj = std::sqrt(dj);
+        Gm[j * nu + j] = dj;
+        for (int64_t i = j + 1; i < nu; ++i) {
+          double t = Gm[i * nu + j];
+          for (int64_t l = 0; l < j; ++l) t -= Gm[i * nu + l] * Gm[j * nu + l];
+          Gm[i * nu + j] = t / dj;
+        }
+      }
+      if (!ok) {
+        err = "the constraints leave the translation of a component without pinned vertex free "
+              "(containing vertex " + std::to_string(unpinned[0]) + "): the W-step system is singular";
         return ERR_SINGULAR_SYSTEM;
       }
     }
+  }
+  // constraint rows must involve a free vertex
+  for (int64_t a = 0; a < in.n_con; ++a) {
+    bool any_free = false;
+    for (int64_t q = in.con_ptr[a]; q < in.con_ptr[a + 1]; ++q) any_free |= !pinned[in.con_col[q]];
+    if (!any_free) {
+      err = "constraint row " + std::to_string(a) + " involves pinned vertices only";
+      return ERR_INVALID_ARG;
+    }
+  }
+  // gamma A_F^T A_F: gamma scales the rows of A to the mean diagonal of L_FF
+  // (any gamma > 0 gives the same constrained minimiser); its pattern joins L's
+  if (in.n_con > 0) {
+    double dsum = 0.0, asum = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+      if (pinned[v]) continue;
+      const int64_t pos = std::lower_bound(Lcol.begin() + Lptr[v], Lcol.begin() + Lptr[v + 1], static_cast<int32_t>(v)) -
+                          Lcol.begin();
+      dsum += Lval[pos];
+    }
+    for (int64_t a = 0; a < in.n_con; ++a)
+      for (int64_t q = in.con_ptr[a]; q < in.con_ptr[a + 1]; ++q)
+        if (!pinned[in.con_col[q]]) asum += in.con_val[q] * in.con_val[q];
+    const double gamma = (dsum / static_cast<double>(n - in.n_pinned)) / (asum / static_cast<double>(in.n_con));
+    S.con_gamma = gamma;
+    // vertex -> constraint rows
+    std::vector<int64_t> vc_ptr(n + 1, 0);
+    for (int64_t q = 0; q < in.con_ptr[in.n_con]; ++q) vc_ptr[in.con_col[q] + 1]++;
+    for (int64_t v = 0; v < n; ++v) vc_ptr[v + 1] += vc_ptr[v];
+    std::vector<int64_t> vc_q(in.con_ptr[in.n_con]);
+    {
+      std::vector<int64_t> fill(vc_ptr.begin(), vc_ptr.end() - 1);
+      for (int64_t a = 0; a < in.n_con; ++a)
+        for (int64_t q = in.con_ptr[a]; q < in.con_ptr[a + 1]; ++q) vc_q[fill[in.con_col[q]]++] = q;
+    }
+    std::vector<int64_t> qrow(in.con_ptr[in.n_con]);
+    for (int64_t a = 0; a < in.n_con; ++a)
+      for (int64_t q = in.con_ptr[a]; q < in.con_ptr[a + 1]; ++q) qrow[q] = a;
+    // merge the pattern and the values row by row
+    std::vector<int64_t> Nptr(n + 1, 0);
+    std::vector<std::vector<std::pair<int32_t, double>>> extra(n);
+    for (int64_t v = 0; v < n; ++v) {
+      if (pinned[v]) continue;
+      for (int64_t k = vc_ptr[v]; k < vc_ptr[v + 1]; ++k) {
+        const int64_t q = vc_q[k], a = qrow[q];
+        for (int64_t q2 = in.con_ptr[a]; q2 < in.con_ptr[a + 1]; ++q2)
+          if (!pinned[in.con_col[q2]]) extra[v].push_back({in.con_col[q2], gamma * in.con_val[q] * in.con_val[q2]});
+      }
+      std::sort(extra[v].begin(), extra[v].end(),
+                [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) { return x.first < y.first; });
+    }
+    std::vector<int32_t> Ncol;
+    std::vector<double> Nval;
+    Ncol.reserve(Lcol.size());
+    Nval.reserve(Lcol.size());
+    for (int64_t v = 0; v < n; ++v) {
+      int64_t k = Lptr[v];
+      size_t e = 0;
+      const auto& ex = extra[v];
+      while (k < Lptr[v + 1] || e < ex.size()) {
+        int32_t col;
+        if (e >= ex.size() || (k < Lptr[v + 1] && Lcol[k] <= ex[e].first)) col = Lcol[k];
+        else col = ex[e].first;
+        double val = 0.0;
+        while (k < Lptr[v + 1] && Lcol[k] == col) val += Lval[k++];
+        while (e < ex.size() && ex[e].first == col) val += ex[e++].second;
+        Ncol.push_back(col);
+        Nval.push_back(val);
+      }
+      Nptr[v + 1] = static_cast<int64_t>(Ncol.size());
+    }
+    Lptr.swap(Nptr);
+    Lcol.swap(Ncol);
+    Lval.swap(Nval);
   }
 
   // ---- ordering -------------------------------------------------------------
@@ -732,6 +889,32 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
         const int32_t v = S.T[e * nc + c];
         if (v < S.nF) S.dt_idx[fill[v]++] = static_cast<int32_t>(e * nc + c);
       }
+  }
+  // constraint rows in the device numbering, and their transpose over the
+  // free rows they touch
+  if (in.n_con > 0) {
+    const int64_t nnz = in.con_ptr[in.n_con];
+    S.con_ptr.assign(in.con_ptr, in.con_ptr + in.n_con + 1);
+    S.con_val.assign(in.con_val, in.con_val + nnz);
+    S.con_col.resize(nnz);
+    std::vector<std::tuple<int32_t, int32_t, double>> ent;
+    for (int64_t a = 0; a < in.n_con; ++a)
+      for (int64_t q = in.con_ptr[a]; q < in.con_ptr[a + 1]; ++q) {
+        const int32_t j = S.vold2new[in.con_col[q]];
+        S.con_col[q] = j;
+        if (j < S.nF) ent.emplace_back(j, static_cast<int32_t>(a), in.con_val[q]);
+      }
+    std::sort(ent.begin(), ent.end());
+    S.cont_ptr.push_back(0);
+    for (size_t i = 0; i < ent.size(); ++i) {
+      if (i == 0 || std::get<0>(ent[i]) != std::get<0>(ent[i - 1])) {
+        if (i > 0) S.cont_ptr.push_back(static_cast<int32_t>(i));
+        S.cont_rows.push_back(std::get<0>(ent[i]));
+      }
+      S.cont_con.push_back(std::get<1>(ent[i]));
+      S.cont_val.push_back(std::get<2>(ent[i]));
+    }
+    S.cont_ptr.push_back(static_cast<int32_t>(ent.size()));
   }
   if (in.selfcheck && S.nF > 0) {
     // solve L_FF x = b with the panels exactly as the device does (forward

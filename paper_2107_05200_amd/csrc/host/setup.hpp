@@ -30,6 +30,13 @@ struct SetupInput {
   double rho = 10.0;             // mu_i = rho * w_i
   const double* mu_elem = nullptr;  // optional per-element mu_i (input order, m entries; replaces rho * w_i)
   bool tutte = false;            // factor the edge Laplacian of Tutte's energy instead of G^T M G
+  // general linear constraints A W = c beyond the pins (eq. solvinginw): the
+  // rows of A in CSR over input vertex indices; the factorised matrix becomes
+  // L_FF + gamma A_F^T A_F, which has the same minimiser on the constraint set
+  int64_t n_con = 0;
+  const int64_t* con_ptr = nullptr;  // n_con + 1
+  const int32_t* con_col = nullptr;
+  const double* con_val = nullptr;
   int64_t n_pinned = 0;
   const int32_t* pinned_idx = nullptr;
   int leaf_size = 0;             // 0: automatic
@@ -68,7 +75,15 @@ struct Setup {
   // L_CF over pinned rows: free column and value
   std::vector<int32_t> lcf_ptr, lcf_col;
   std::vector<double> lcf_val;
-  // factor of L_FF
+  // constraints: rows of A with columns in the device numbering (>= nF:
+  // pinned), gamma, and the transposed free part over the free rows it touches
+  double con_gamma = 0;
+  std::vector<int64_t> con_ptr;
+  std::vector<int32_t> con_col;
+  std::vector<double> con_val;
+  std::vector<int32_t> cont_rows, cont_ptr, cont_con;
+  std::vector<double> cont_val;
+  // factor of L_FF (+ gamma A_F^T A_F)
   std::vector<SolveNode> nodes;
   std::vector<std::vector<int32_t>> children;
   std::vector<double> panel_f;  // [Linv; -M] per node; the backward pass reads it transposed

@@ -1187,6 +1187,146 @@ __global__ void k_map_in(int64_t n, const int32_t* __restrict new2old, const dou
   for (int k = 0; k < D; ++k) xint[j * D + k] = ext[o * D + k];
 }
 
+// ---------------------------------------------------------------------------
+// General linear constraints A W = c in the W-step (eq. solvinginw).  The
+// factor is of L~ = L_FF + gamma A_F^T A_F; with c' = c - A_C x_C the
+// constrained minimiser is x = y - Z lambda with y = L~^{-1} (b + gamma A_F^T c'),
+// Z = L~^{-1} A_F^T (precomputed, column-major ncon x nF) and lambda =
+// S^{-1} (A_F y - c'), S = A_F Z (block elimination of the KKT system; the
+// explicit S^{-1} is precomputed on the host).
+// ---------------------------------------------------------------------------
+constexpr int kMaxConstraints = 1024;
+
+// c' = c - A_C x_C, one thread per constraint row
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_con_shift(int64_t ncon, int64_t nF, const int64_t* __restrict con_ptr,
+                                                      const int32_t* __restrict con_col,
+                                                      const double* __restrict con_val, const double* __restrict c,
+                                                      const double* __restrict xC, double* __restrict cp) {
+  const int64_t a = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (a >= ncon) return;
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = c[a * D + k];
+  for (int64_t q = con_ptr[a]; q < con_ptr[a + 1]; ++q) {
+    const int64_t j = con_col[q];
+    if (j < nF) continue;
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] -= con_val[q] * xC[(j - nF) * D + k];
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) cp[a * D + k] = acc[k];
+}
+
+// b_j += gamma (A_F^T c')_j on the free rows the constraints touch
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_con_addq(int64_t nrows, const int32_t* __restrict rows,
+                                                     const int32_t* __restrict cont_ptr,
+                                                     const int32_t* __restrict cont_con,
+                                                     const double* __restrict cont_val, double gamma,
+                                                     const double* __restrict cp, double* __restrict b) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= nrows) return;
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  for (int32_t q = cont_ptr[i]; q < cont_ptr[i + 1]; ++q) {
+    const int64_t a = cont_con[q];
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] += cont_val[q] * cp[a * D + k];
+  }
+  const int64_t j = rows[i];
+#pragma unroll
+  for (int k = 0; k < D; ++k) b[j * D + k] += gamma * acc[k];
+}
+
+// t = A x - c over all columns (the pinned rows of x hold x_C), i.e. A_F y - c'
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_con_resid(int64_t ncon, const int64_t* __restrict con_ptr,
+                                                      const int32_t* __restrict con_col,
+                                                      const double* __restrict con_val, const double* __restrict c,
+                                                      const double* __restrict x, double* __restrict t) {
+  const int64_t a = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (a >= ncon) return;
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = -c[a * D + k];
+  for (int64_t q = con_ptr[a]; q < con_ptr[a + 1]; ++q) {
+    const int64_t j = con_col[q];
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] += con_val[q] * x[j * D + k];
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) t[a * D + k] = acc[k];
+}
+
+// lambda = S^{-1} t (S^{-1} symmetric, read by columns so lanes load
+// consecutive entries)
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_con_lambda(int64_t ncon, const double* __restrict Sinv,
+                                                       const double* __restrict t, double* __restrict lam) {
+  const int64_t a = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (a >= ncon) return;
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  for (int64_t b2 = 0; b2 < ncon; ++b2) {
+    const double sv = Sinv[b2 * ncon + a];
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] += sv * t[b2 * D + k];
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) lam[a * D + k] = acc[k];
+}
+
+// x_F -= Z lambda, one thread per free row; lambda staged in LDS
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_con_correct(int64_t nF, int64_t ncon, const double* __restrict Z,
+                                                        const double* __restrict lam, double* __restrict x) {
+  __shared__ double sl[kMaxConstraints * D];
+  for (int64_t i = threadIdx.x; i < ncon * D; i += kBlock) sl[i] = lam[i];
+  __syncthreads();
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (j >= nF) return;
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  for (int64_t a = 0; a < ncon; ++a) {
+    const double z = Z[a * nF + j];
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] += z * sl[a * D + k];
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k) x[j * D + k] -= acc[k];
+}
+
+// set-up: the solution columns of one group of D constraint rows into Z
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_con_zcols(int64_t nF, int64_t ncon, int64_t a0,
+                                                      const double* __restrict xs, double* __restrict Z) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (j >= nF) return;
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+    if (a0 + k < ncon) Z[(a0 + k) * nF + j] = xs[j * D + k];
+}
+
+// set-up: S = A_F Z, one thread per entry
+__global__ __launch_bounds__(kBlock) void k_con_gram(int64_t nF, int64_t ncon, const int64_t* __restrict con_ptr,
+                                                     const int32_t* __restrict con_col,
+                                                     const double* __restrict con_val, const double* __restrict Z,
+                                                     double* __restrict S) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= ncon * ncon) return;
+  const int64_t a = t / ncon, b2 = t % ncon;
+  double acc = 0.0;
+  for (int64_t q = con_ptr[a]; q < con_ptr[a + 1]; ++q) {
+    const int64_t j = con_col[q];
+    if (j < nF) acc += con_val[q] * Z[b2 * nF + j];
+  }
+  S[t] = acc;
+}
+
 // right-hand side of a solve whose only data are the fixed rows: b_F = -L_FC x_C
 // (the minimiser of a quadratic energy with fixed vertices); rows >= nF copy
 // the fixed positions into x

@@ -2163,8 +2163,10 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
     }
     cf = h->cfg_fwd;
     cb = h->cfg_bwd;
-    // then the forest below a top level split over 2..4 streams
-    double tbest = time_solve_pass(h, s, true, 3) + time_solve_pass(h, s, false, 3);
+    // then the forest below a top level split over 2..4 streams, kept only
+    // when it beats one stream by more than 3% (run-to-run noise is ~2%)
+    const double t_one = time_solve_pass(h, s, true, 3) + time_solve_pass(h, s, false, 3);
+    double tbest = 0.97 * t_one;
     groups = 1;
     topl = static_cast<int>(nlev);
     HIP_TRY(ensure_workers(h, 4));

@@ -29,8 +29,8 @@ FP32_PEAK_TFLOPS = 78.6  # no packed FP32: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 # hash of the kernel sources they were measured on: a changed kernel reports
 # no traffic until it is measured again.
 MEASURED_TRAFFIC = {
-    "531e7f655fc59e42": {"solve": 3804.7e6, "local": 513.8e6,
-                         "local_flop_per_elem": 2266.1, "local_valu_per_wave": 2635.2},
+    "9ea00a43f2211886": {"solve": 3218.9e6, "local": 527.1e6,
+                         "local_flop_per_elem": 2266.1, "local_valu_per_wave": 2635.3},
 }
 
 

@@ -11,6 +11,7 @@
 #include <sstream>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/ffd.h"
@@ -138,6 +139,7 @@ struct ffd_ctx {
   // whole subtrees, each solved on its own stream (group 0 on the caller's);
   // levels >= solve_top run on the caller's stream after the join.
   int solve_groups = 1, solve_top = 0;
+  bool xcd_lanes = true;  // level tasks grouped per node onto one XCD (see xcd_order)
   std::vector<int32_t> hparent;                  // parent node (-1: root)
   std::vector<std::vector<LevelRun>> grun_fwd, grun_bwd;  // [group][level]; group solve_groups = top levels
   std::vector<hipStream_t> wstreams;             // worker streams of groups 1..
@@ -689,6 +691,52 @@ hipError_t ensure_workers(ffd_ctx* h, int g) {
   return hipSuccess;
 }
 
+// Reorders the main tasks of one level run (from t0 on) so that the tasks of
+// a node run on one XCD, whose L2 then serves the inner vector they all
+// stage: blocks go to the 8 XCDs round-robin by index, so lane x of 8 takes
+// block indices x, x + 8, ...  A node's tasks go to one lane in pieces of at
+// most a lane's share (a level of one node still spreads over all eight),
+// pieces onto the lane with the fewest tasks; each lane keeps the
+// longest-first order; g tasks form a block (one wave each in wave mode);
+// lanes are padded with empty tasks (no outputs).
+void xcd_order(std::vector<SolveTask>& tasks, size_t t0, int g) {
+  constexpr int X = 8;
+  const size_t nt = tasks.size() - t0;
+  if (nt < static_cast<size_t>(2 * X * g)) return;
+  std::vector<std::vector<SolveTask>> byn;
+  std::unordered_map<int64_t, size_t> slot_of;  // node (panel offset) -> its list
+  for (size_t t = t0; t < tasks.size(); ++t) {
+    const auto it = slot_of.emplace(tasks[t].pf, byn.size());
+    if (it.second) byn.emplace_back();
+    byn[it.first->second].push_back(tasks[t]);
+  }
+  std::stable_sort(byn.begin(), byn.end(),
+                   [](const std::vector<SolveTask>& a, const std::vector<SolveTask>& b) { return a.size() > b.size(); });
+  const size_t cap = std::max<size_t>(g, (nt + X - 1) / X);
+  std::vector<std::vector<SolveTask>> lane(X);
+  for (const auto& nd : byn)
+    for (size_t o = 0; o < nd.size(); o += cap) {
+      size_t x = 0;
+      for (size_t y2 = 1; y2 < X; ++y2)
+        if (lane[y2].size() < lane[x].size()) x = y2;
+      lane[x].insert(lane[x].end(), nd.begin() + o, nd.begin() + std::min(nd.size(), o + cap));
+    }
+  size_t groups = 0;
+  for (auto& l : lane) {
+    std::stable_sort(l.begin(), l.end(), [](const SolveTask& a, const SolveTask& b) { return a.hi - a.lo > b.hi - b.lo; });
+    groups = std::max(groups, (l.size() + g - 1) / g);
+  }
+  SolveTask empty{};
+  empty.slot = -1;
+  tasks.resize(t0);
+  for (size_t k = 0; k < groups; ++k)
+    for (int x = 0; x < X; ++x)
+      for (int u = 0; u < g; ++u) {
+        const size_t i = k * g + u;
+        tasks.push_back(i < lane[x].size() ? lane[x][i] : empty);
+      }
+}
+
 // Builds the task lists of both passes from cfg_fwd / cfg_bwd (defaults for
 // levels without one) and uploads them.  Waits for the device first: the
 // task buffers may be in use by earlier launches.
@@ -796,6 +844,7 @@ ffd_status build_solve_schedule(ffd_ctx* h) {
                                     b0 + q, nk));
           red.push_back(task_of(o, fwd, 0, cfg.opt, b0, nk));  // hi: outputs of the block
         }
+        if (h->xcd_lanes) xcd_order(tasks, static_cast<size_t>(run.t0), cfg.mode == 1 ? 4 : 1);
         run.nt = static_cast<int32_t>(tasks.size()) - run.t0;
         run.nr = static_cast<int32_t>(red.size()) - run.r0;
         run.reduce_now = !fwd || !cfg.defer || l + 1 == nlev;

@@ -376,13 +376,22 @@ __global__ __launch_bounds__(kBlock) void k_prepare(int64_t m, int64_t e0, int64
 // combined by a fixed shuffle tree.  Rows >= nF copy the pinned positions into
 // the new map.
 // ---------------------------------------------------------------------------
+// Block index that gives each of the 8 XCDs (blocks are dispatched to them
+// round-robin by index) a contiguous eighth of the blocks, so that rows
+// sharing data share an L2; a bijection on [0, gridDim.x) (the blocks past
+// the largest multiple of 8 keep their index).
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t per = gridDim.x / 8, b = blockIdx.x;
+  return b < 8 * per ? (b % 8) * per + b / 8 : b;
+}
+
 template <int D, typename R, int LPR = 4>
 __global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const int32_t* __restrict dt_ptr,
                                                  const int32_t* __restrict dt_idx, const R* __restrict g,
                                                  const int32_t* __restrict pin_ptr, const int32_t* __restrict pin_col,
                                                  const double* __restrict pin_val, const double* __restrict xC,
                                                  double* __restrict b, double* __restrict xnew) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t t = xcd_block() * kBlock + threadIdx.x;
   const int64_t j = t / LPR;
   const int sub = static_cast<int>(t % LPR);
   if (j >= n) return;

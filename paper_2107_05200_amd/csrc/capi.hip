@@ -2,1110 +2,12 @@
 // and the launch sequence of one iteration of Algorithm 1:
 //   K2 W-step right-hand side -> K4 forward solve levels -> K5 backward solve
 //   levels -> K3 fused U/P/Lambda step -> finalize (history record).
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <chrono>
-#include <cmath>
-#include <cstdio>
-#include <sstream>
-#include <cstring>
-#include <string>
-#include <unordered_map>
-#include <vector>
-
-#include "../../include/ffd.h"
-#include "host/setup.hpp"
-#include "adjoint.hpp"
-#include "kernels.hpp"
-
-using namespace ffd;
-
-namespace {
-
-thread_local std::string g_last_error;
-
-ffd_status fail(ffd_status st, const std::string& msg) {
-  g_last_error = msg;
-  return st;
-}
-
-#define HIP_TRY(expr)                                                                     \
-  do {                                                                                    \
-    hipError_t e_ = (expr);                                                               \
-    if (e_ != hipSuccess)                                                                 \
-      return fail(e_ == hipErrorOutOfMemory ? FFD_ERR_OUT_OF_MEMORY : FFD_ERR_DEVICE,     \
-                  std::string(#expr) + ": " + hipGetErrorString(e_));                     \
-  } while (0)
-
-constexpr int64_t kHistCap0 = 1 << 14;
-
-inline unsigned nblk(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
-
-
-}  // namespace
-
-// Launch configuration of one solve level of one pass: mode 0 = blocks of nw
-// waves per task, 1 = one wave per task; opt = outputs per task (64, 32, 16);
-// chunk > 0 splits inner ranges longer than chunk (block mode only); the
-// partials are added right after the level, or (forward, defer) only for
-// blocks of y rows, by the backward pass.
-struct LevelCfg {
-  int32_t mode = 0, opt = 64, chunk = 0, nw = 4;  // nw: waves per block (block mode: 4, 8, 16)
-  int32_t defer = 0;  // forward only: split y-row blocks only and add their partials in the backward pass
-  bool operator==(const LevelCfg& o) const {
-    return mode == o.mode && opt == o.opt && chunk == o.chunk && nw == o.nw && defer == o.defer;
-  }
-};
-struct LevelRun {
-  int32_t mode = 0, opt = 64, nw = 4, t0 = 0, nt = 0, r0 = 0, nr = 0;  // tasks [t0, t0+nt), reductions [r0, r0+nr)
-  int32_t y0 = 0, ny = 0;  // backward runs: pending forward y-row reductions [y0, y0+ny) of yred
-  bool reduce_now = true;  // forward runs: add the split partials right after the level
-};
-
-struct ffd_ctx {
-  int d = 0, din = 0, prec = 32, energy = 0, h_mode = 0;
-  double rho = 0;
-  int64_t n = 0, m = 0, nF = 0, nC = 0;
-  bool pins_given = false, auto_pinned = false, initialized = false;
-  int64_t k = 0;          // completed iterations
-  struct Seg {
-    int64_t e0, e1;   // element range of one energy (elements are grouped by energy)
-    int energy;
-    int64_t pb0;      // first partial-sum block of the range
-  };
-  std::vector<Seg> segs;
-  std::vector<int64_t> voff, eoff;  // batch layout: vertex / element offsets per mesh (empty: one mesh)
-  // launch shapes (chosen by ffd_autotune)
-  int local_bs = 256;              // threads per block of the local step
-  int wrhs_lpr = 4;                // lanes per vertex row of the right-hand side
-  std::vector<SolveNode> hnodes;   // host copies for rebuilding the solve schedule
-  std::vector<std::vector<int32_t>> hlevels;
-  int64_t nparts = 0;     // partial-sum blocks of one local step
-  int cur = 0;            // index of the buffer holding W^k
-  int dev = 0;
-  hipStream_t last_stream = nullptr;
-  ffd_info info{};
-  // host copies
-  std::vector<int32_t> vnew2old;
-  // device buffers
-  int32_t *T = nullptr, *vnew2old_d = nullptr, *enew2old_d = nullptr;
-  double* B64 = nullptr;
-  void *B = nullptr, *w = nullptr;
-  double *x[2] = {nullptr, nullptr}, *xC = nullptr;
-  void *U = nullptr, *P = nullptr, *L = nullptr, *gn = nullptr, *g = nullptr;
-  double *b = nullptr, *y = nullptr, *ub = nullptr, *partials = nullptr, *hist = nullptr;
-  double* partials2 = nullptr;  // first-stage sums of the partials (many local-step blocks)
-  int64_t hist_cap = 0;
-  int32_t *dt_ptr = nullptr, *dt_idx = nullptr, *pin_ptr = nullptr, *pin_col = nullptr;
-  double* pin_val = nullptr;
-  std::vector<int64_t> hpoff;  // device panel offset of every node
-  // two captured iterations replayed by ffd_iterate_graph
-  hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
-  bool graph_valid = false;      // captured with the current launch shapes and buffers
-  int graph_cur = 0;             // map buffer holding W^k when the graph starts
-  double* graph_hist = nullptr;  // history buffer the graph writes to
-  int64_t* k_dev = nullptr;      // device copy of the iteration counter
-  void* glam = nullptr;          // corner vectors of Lambda (diagnostic iterations)
-  // penalty rescaling: per-element mu_e / w_e on the device (nullptr: rho for
-  // every element), the new mu_e of a rescaling event, and the host copy of
-  // the set-up input the factor is rebuilt from
-  void* rho_e = nullptr;
-  double* mu_dev = nullptr;
-  bool rescaled = false;
-  std::vector<double> in_V;
-  std::vector<int32_t> in_T, in_pins, enew2old_h;
-  std::vector<int8_t> in_energy;
-  int in_leaf = 0;
-  size_t n_pin_val = 0, n_lcf_val = 0;
-  double* gtl_part = nullptr;    // per-block partial sums of |G^T Lambda|^2
-  // general linear constraints A W = c: rows of A (device numbering; host and
-  // device copies), the transposed free part over the rows it touches, the
-  // right-hand sides c, per-iteration c', A y - c', lambda, the precomputed
-  // Z = L~^{-1} A_F^T (column-major) and S^{-1}, and a solve scratch vector
-  int64_t ncon = 0, ncon_rows = 0;
-  double con_gamma = 0;
-  std::vector<int64_t> con_ptr_h, in_con_ptr;
-  std::vector<int32_t> con_col_h, in_con_col;
-  std::vector<double> con_val_h, in_con_val;
-  int64_t* con_ptr = nullptr;
-  int32_t *con_col = nullptr, *cont_rows = nullptr, *cont_ptr = nullptr, *cont_con = nullptr;
-  double *con_val = nullptr, *cont_val = nullptr, *con_c = nullptr, *con_cp = nullptr, *con_t = nullptr;
-  double *con_lam = nullptr, *con_Z = nullptr, *con_Sinv = nullptr, *con_tmp = nullptr;
-  std::vector<LevelCfg> cfg_fwd, cfg_bwd;  // per-level launch configuration of both solve passes
-  // The forest below level solve_top is split into solve_groups groups of
-  // whole subtrees, each solved on its own stream (group 0 on the caller's);
-  // levels >= solve_top run on the caller's stream after the join.
-  int solve_groups = 1, solve_top = 0;
-  bool xcd_lanes = true;  // level tasks grouped per node onto one XCD (see xcd_order)
-  std::vector<int32_t> hparent;                  // parent node (-1: root)
-  std::vector<std::vector<LevelRun>> grun_fwd, grun_bwd;  // [group][level]; group solve_groups = top levels
-  std::vector<hipStream_t> wstreams;             // worker streams of groups 1..
-  hipEvent_t fork_ev[2] = {nullptr, nullptr}, join_ev[2][8] = {};
-  double *Prow = nullptr, *Pcol = nullptr;  // factor panels, row- and column-major copies
-  int32_t *sidx = nullptr, *pull_ptr = nullptr, *pull_idx = nullptr;
-  SolveTask *tasks_fwd = nullptr, *tasks_bwd = nullptr, *red_fwd = nullptr, *red_bwd = nullptr;
-  size_t cap_tf = 0, cap_tb = 0, cap_rf = 0, cap_rb = 0, cap_slots = 0;  // capacities (entries)
-  SolveTask* yred = nullptr;  // forward y-row reductions, in the order the backward launches run them
-  double* fpart = nullptr;    // forward split partials (kept until the backward pass adds them)
-  size_t cap_yr = 0, cap_fslots = 0;
-  double* solve_part = nullptr;                   // split-K partials (reused level by level)
-  int64_t device_bytes = 0;
-  std::vector<void*> allocs;
-  std::vector<hipEvent_t> events;
-  double* hist_scratch = nullptr;  // history record target of recomputed iterations
-  // adjoint: incidence of all vertex rows, L_CF, checkpoints and adjoint state
-  int32_t *av_ptr = nullptr, *av_idx = nullptr, *lcf_ptr = nullptr, *lcf_col = nullptr;
-  double* lcf_val = nullptr;
-  int64_t adj_k0 = -1, adj_K = 0, adj_every = 0, adj_nslots = 0;
-  char* adj_ck = nullptr;    // checkpoint slots
-  char* adj_seg = nullptr;   // per-iteration states of one segment (every + 1 slots)
-  char* adj_fin = nullptr;   // the state after the K iterations
-  double *Ubar = nullptr, *Pbar = nullptr, *Lbar = nullptr, *Bbar = nullptr, *wbar = nullptr;
-  double *gadj = nullptr, *lam = nullptr, *xbar = nullptr, *pinsbar = nullptr, *vbar = nullptr;
-  // one saved state: U, P, Lambda, |grad f(P)|^2, the next right-hand side's
-  // corner vectors (so a restored state continues bit for bit), and the map
-  size_t slot_elem_entries() const {
-    const size_t nU = d == 2 ? 2 : 9, nP = d == 2 ? 3 : 6;
-    return nU + nP + static_cast<size_t>(d) * d + 1 + static_cast<size_t>(d + 1) * d;
-  }
-  size_t slot_bytes() const {
-    const size_t el = rsize() * m * slot_elem_entries();
-    return ((el + 255) / 256) * 256 + static_cast<size_t>(n) * d * sizeof(double);
-  }
-
-  template <typename T_>
-  hipError_t alloc(T_** p, size_t count) {
-    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T_);
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
-    if (e == hipSuccess) {
-      allocs.push_back(*p);
-      device_bytes += bytes;
-    }
-    return e;
-  }
-  size_t rsize() const { return prec == 32 ? 4 : 8; }
-  ~ffd_ctx() {
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    for (hipStream_t w : wstreams) (void)hipStreamDestroy(w);
-    for (int p = 0; p < 2; ++p) {
-      if (fork_ev[p]) (void)hipEventDestroy(fork_ev[p]);
-      for (hipEvent_t e : join_ev[p])
-        if (e) (void)hipEventDestroy(e);
-    }
-    for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
-    for (void* p : allocs) (void)hipFree(p);
-  }
-};
-
-namespace {
-
-template <typename T_>
-hipError_t upload(ffd_ctx* h, T_** dst, const std::vector<T_>& src) {
-  hipError_t e = h->alloc(dst, src.size());
-  if (e != hipSuccess) return e;
-  if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T_), hipMemcpyHostToDevice);
-  return e;
-}
-
-// element arrays as SoA [entry][m] in the arithmetic type
-template <typename R>
-std::vector<R> soa(const std::vector<double>& aos, int64_t m, int per) {
-  std::vector<R> out(static_cast<size_t>(m) * per);
-  for (int64_t e = 0; e < m; ++e)
-    for (int i = 0; i < per; ++i) out[static_cast<size_t>(i) * m + e] = static_cast<R>(aos[e * per + i]);
-  return out;
-}
-
-// --------------------------------------------------------------------------
-// launch helpers (dispatch on d, precision, energy)
-// --------------------------------------------------------------------------
-
-template <int D, typename R, int E>
-void launch_init(ffd_ctx* h, const ffd_ctx::Seg& g, hipStream_t s) {
-  hipLaunchKernelGGL((k_init<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1, h->T, h->B64,
-                     static_cast<const R*>(h->B), static_cast<const R*>(h->w), static_cast<R>(h->rho), h->x[h->cur],
-                     static_cast<R*>(h->U), static_cast<R*>(h->P), static_cast<R*>(h->L), static_cast<R*>(h->gn),
-                     static_cast<R*>(h->g));
-}
-
-template <int D, typename R, int E>
-void launch_prepare(ffd_ctx* h, const ffd_ctx::Seg& g, hipStream_t s) {
-  hipLaunchKernelGGL((k_prepare<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1,
-                     static_cast<const R*>(h->B), static_cast<const R*>(h->w), static_cast<R>(h->rho),
-                     static_cast<const R*>(h->rescaled ? h->rho_e : nullptr), static_cast<const R*>(h->U),
-                     static_cast<const R*>(h->P),
-                     static_cast<const R*>(h->L), static_cast<R*>(h->gn), static_cast<R*>(h->g));
-}
-
-template <int D, typename R, int E>
-void launch_rescale(ffd_ctx* h, const ffd_ctx::Seg& g, double rho_r, hipStream_t s) {
-  hipLaunchKernelGGL((k_rescale<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1, h->T,
-                     static_cast<const R*>(h->B), static_cast<const R*>(h->w), static_cast<R*>(h->rho_e),
-                     h->x[h->cur], h->x[1 - h->cur], static_cast<const R*>(h->U), static_cast<const R*>(h->P),
-                     static_cast<R*>(h->L), static_cast<const R*>(h->gn), static_cast<R*>(h->g), rho_r, h->mu_dev);
-}
-
-template <int D, typename R, int E, int BS>
-void launch_local_bs(ffd_ctx* h, const ffd_ctx::Seg& g, const double* xnew, const double* xold, int store_u,
-                     void* glam, hipStream_t s) {
-  hipLaunchKernelGGL((k_local<D, R, E, BS>), dim3(static_cast<unsigned>((g.e1 - g.e0 + BS - 1) / BS)), dim3(BS), 0, s,
-                     h->m, g.e0, g.e1, h->T, static_cast<const R*>(h->B), static_cast<const R*>(h->w),
-                     static_cast<R>(h->rho), static_cast<const R*>(h->rescaled ? h->rho_e : nullptr), h->h_mode, store_u, xnew, xold,
-                     static_cast<R*>(h->U),
-                     static_cast<R*>(h->P), static_cast<R*>(h->L), static_cast<R*>(h->gn), static_cast<R*>(h->g),
-                     h->partials + g.pb0 * kNumPartials, static_cast<R*>(glam));
-}
-
-template <int D, typename R, int E>
-void launch_local(ffd_ctx* h, const ffd_ctx::Seg& g, const double* xnew, const double* xold, int store_u,
-                  void* glam, hipStream_t s) {
-  if (h->local_bs == 64) launch_local_bs<D, R, E, 64>(h, g, xnew, xold, store_u, glam, s);
-  else if (h->local_bs == 128) launch_local_bs<D, R, E, 128>(h, g, xnew, xold, store_u, glam, s);
-  else launch_local_bs<D, R, E, 256>(h, g, xnew, xold, store_u, glam, s);
-}
-
-// partial-sum block offsets of the energy ranges for the local-step block size
-void set_local_block(ffd_ctx* h, int bs) {
-  h->graph_valid = false;
-  h->local_bs = bs;
-  int64_t pb = 0;
-  for (auto& g : h->segs) {
-    g.pb0 = pb;
-    pb += (g.e1 - g.e0 + bs - 1) / bs;
-  }
-  h->nparts = pb;
-}
-
-template <int D, typename R, int LPR>
-void launch_wrhs_l(ffd_ctx* h, double* xnew, hipStream_t s) {
-  hipLaunchKernelGGL((k_wrhs<D, R, LPR>), dim3(nblk(LPR * h->n)), dim3(kBlock), 0, s, h->nF, h->n, h->dt_ptr,
-                     h->dt_idx, static_cast<const R*>(h->g), h->pin_ptr, h->pin_col, h->pin_val, h->xC, h->b, xnew);
-}
-
-template <int D, typename R>
-void launch_wrhs(ffd_ctx* h, double* xnew, hipStream_t s) {
-  if (h->wrhs_lpr == 2) launch_wrhs_l<D, R, 2>(h, xnew, s);
-  else if (h->wrhs_lpr == 8) launch_wrhs_l<D, R, 8>(h, xnew, s);
-  else launch_wrhs_l<D, R, 4>(h, xnew, s);
-}
-
-template <int D, int OPT, int NW>
-void launch_fwd_block(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, const double* b, hipStream_t s) {
-  hipLaunchKernelGGL((k_solve_fwd<D, OPT, NW>), dim3(r.nt), dim3(NW * 64), 0, s, tasks, h->Pcol, h->pull_ptr,
-                     h->pull_idx, b, h->y, h->ub, h->fpart);
-}
-
-template <int D, int OPT, int NW>
-void launch_bwd_block(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, double* x, hipStream_t s) {
-  const int grid = r.nt + (r.ny + NW - 1) / NW;
-  hipLaunchKernelGGL((k_solve_bwd<D, OPT, NW>), dim3(grid), dim3(NW * 64), 0, s, tasks, r.nt, h->Prow, h->sidx, h->y,
-                     x, h->solve_part, h->yred + r.y0, r.ny, h->fpart);
-}
-
-template <int D, int OPT>
-void launch_fwd_opt(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, const double* b, hipStream_t s) {
-  if (r.mode == 1)
-    hipLaunchKernelGGL((k_solve_fwd_wave<D, OPT>), dim3((r.nt + 3) / 4), dim3(kBlock), 0, s, tasks, r.nt, h->Pcol,
-                       h->pull_ptr, h->pull_idx, b, h->y, h->ub);
-  else if (r.nw == 16)
-    launch_fwd_block<D, OPT, 16>(h, r, tasks, b, s);
-  else if (r.nw == 8)
-    launch_fwd_block<D, OPT, 8>(h, r, tasks, b, s);
-  else
-    launch_fwd_block<D, OPT, 4>(h, r, tasks, b, s);
-}
-
-template <int D, int OPT>
-void launch_bwd_opt(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, double* x, hipStream_t s) {
-  if (r.mode == 1)
-    hipLaunchKernelGGL((k_solve_bwd_wave<D, OPT>), dim3((r.nt + r.ny + 3) / 4), dim3(kBlock), 0, s, tasks, r.nt,
-                       h->Prow, h->sidx, h->y, x, h->yred + r.y0, r.ny, h->fpart);
-  else if (r.nw == 16)
-    launch_bwd_block<D, OPT, 16>(h, r, tasks, x, s);
-  else if (r.nw == 8)
-    launch_bwd_block<D, OPT, 8>(h, r, tasks, x, s);
-  else
-    launch_bwd_block<D, OPT, 4>(h, r, tasks, x, s);
-}
-
-// reduce: add the split partials now (otherwise a backward launch adds them)
-template <int D>
-void launch_fwd_level(ffd_ctx* h, const LevelRun& r, const double* b, hipStream_t s, bool reduce) {
-  const SolveTask* tasks = h->tasks_fwd + r.t0;
-  if (r.nt > 0) {
-    if (r.opt == 16) launch_fwd_opt<D, 16>(h, r, tasks, b, s);
-    else if (r.opt == 32) launch_fwd_opt<D, 32>(h, r, tasks, b, s);
-    else launch_fwd_opt<D, 64>(h, r, tasks, b, s);
-  }
-  if (reduce && r.nr > 0)
-    hipLaunchKernelGGL((k_solve_fwd_reduce<D>), dim3((r.nr + 3) / 4), dim3(kBlock), 0, s, h->red_fwd + r.r0, r.nr,
-                       h->pull_ptr, h->pull_idx, h->y, h->ub, h->fpart);
-}
-
-template <int D>
-void launch_bwd_level(ffd_ctx* h, const LevelRun& r, double* x, hipStream_t s) {
-  const SolveTask* tasks = h->tasks_bwd + r.t0;
-  if (r.nt > 0 || r.ny > 0) {
-    if (r.opt == 16) launch_bwd_opt<D, 16>(h, r, tasks, x, s);
-    else if (r.opt == 32) launch_bwd_opt<D, 32>(h, r, tasks, x, s);
-    else launch_bwd_opt<D, 64>(h, r, tasks, x, s);
-  }
-  if (r.nr > 0)
-    hipLaunchKernelGGL((k_solve_bwd_reduce<D>), dim3((r.nr + 3) / 4), dim3(kBlock), 0, s, h->red_bwd + r.r0, r.nr, x,
-                       h->solve_part);
-}
-
-// stream of group g (group 0 and the top levels run on the caller's stream)
-inline hipStream_t group_stream(ffd_ctx* h, int g, hipStream_t s) { return g == 0 ? s : h->wstreams[g - 1]; }
-
-template <int D>
-void launch_solve_fwd(ffd_ctx* h, const double* b, hipStream_t s) {
-  const int G = h->solve_groups, top = h->solve_top;
-  if (G > 1) {
-    (void)hipEventRecord(h->fork_ev[0], s);
-    for (int g = 1; g < G; ++g) (void)hipStreamWaitEvent(h->wstreams[g - 1], h->fork_ev[0], 0);
-  }
-  const int nlev = static_cast<int>(h->hlevels.size());
-  for (int l = 0; l < top; ++l)
-    for (int g = 0; g < G; ++g)
-      launch_fwd_level<D>(h, h->grun_fwd[g][l], b, group_stream(h, g, s), h->grun_fwd[g][l].reduce_now);
-  if (G > 1)
-    for (int g = 1; g < G; ++g) {
-      (void)hipEventRecord(h->join_ev[0][g], h->wstreams[g - 1]);
-      (void)hipStreamWaitEvent(s, h->join_ev[0][g], 0);
-    }
-  for (int l = top; l < nlev; ++l) launch_fwd_level<D>(h, h->grun_fwd[G][l], b, s, h->grun_fwd[G][l].reduce_now);
-}
-
-template <int D>
-void launch_solve_bwd(ffd_ctx* h, double* x, hipStream_t s) {
-  const int G = h->solve_groups, top = h->solve_top;
-  const int nlev = static_cast<int>(h->hlevels.size());
-  for (int l = nlev - 1; l >= top; --l) launch_bwd_level<D>(h, h->grun_bwd[G][l], x, s);
-  if (G > 1) {
-    (void)hipEventRecord(h->fork_ev[1], s);
-    for (int g = 1; g < G; ++g) (void)hipStreamWaitEvent(h->wstreams[g - 1], h->fork_ev[1], 0);
-  }
-  for (int l = top - 1; l >= 0; --l)
-    for (int g = 0; g < G; ++g) launch_bwd_level<D>(h, h->grun_bwd[g][l], x, group_stream(h, g, s));
-  if (G > 1)
-    for (int g = 1; g < G; ++g) {
-      (void)hipEventRecord(h->join_ev[1][g], h->wstreams[g - 1]);
-      (void)hipStreamWaitEvent(s, h->join_ev[1][g], 0);
-    }
-}
-
-template <int D>
-void launch_solve(ffd_ctx* h, const double* b, double* x, hipStream_t s) {
-  launch_solve_fwd<D>(h, b, s);
-  launch_solve_bwd<D>(h, x, s);
-}
-
-#define SEG_CASES(FN, ...)                                                  \
-  switch (h->d * 100 + h->prec + g.energy) {                                \
-    case 232: FN<2, float, 0>(__VA_ARGS__); break;                          \
-    case 233: FN<2, float, 1>(__VA_ARGS__); break;                          \
-    case 264: FN<2, double, 0>(__VA_ARGS__); break;                         \
-    case 265: FN<2, double, 1>(__VA_ARGS__); break;                         \
-    case 332: FN<3, float, 0>(__VA_ARGS__); break;                          \
-    case 333: FN<3, float, 1>(__VA_ARGS__); break;                          \
-    case 364: FN<3, double, 0>(__VA_ARGS__); break;                         \
-    case 365: FN<3, double, 1>(__VA_ARGS__); break;                         \
-  }
-
-void do_init(ffd_ctx* h, hipStream_t s) {
-  for (const auto& g : h->segs) SEG_CASES(launch_init, h, g, s)
-}
-
-void do_prepare(ffd_ctx* h, hipStream_t s) {
-  for (const auto& g : h->segs) SEG_CASES(launch_prepare, h, g, s)
-}
-
-void do_local(ffd_ctx* h, const double* xnew, const double* xold, int store_u, hipStream_t s,
-              void* glam = nullptr) {
-  for (const auto& g : h->segs) SEG_CASES(launch_local, h, g, xnew, xold, store_u, glam, s)
-}
-
-void do_wrhs(ffd_ctx* h, double* xnew, hipStream_t s) {
-  if (h->d == 2) {
-    if (h->prec == 32) launch_wrhs<2, float>(h, xnew, s);
-    else launch_wrhs<2, double>(h, xnew, s);
-  } else {
-    if (h->prec == 32) launch_wrhs<3, float>(h, xnew, s);
-    else launch_wrhs<3, double>(h, xnew, s);
-  }
-}
-
-void do_solve(ffd_ctx* h, const double* b, double* x, hipStream_t s) {
-  if (h->nF == 0) return;
-  if (h->d == 2) launch_solve<2>(h, b, x, s);
-  else launch_solve<3>(h, b, x, s);
-}
-
-// the constraint terms of the W-step: c' = c - A_C x_C and b += gamma A_F^T c'
-// before the solve, x_F -= Z S^{-1} (A x - c) after it
-template <int D>
-void con_before_solve_d(ffd_ctx* h, hipStream_t s) {
-  hipLaunchKernelGGL(k_con_shift<D>, dim3(nblk(h->ncon)), dim3(kBlock), 0, s, h->ncon, h->nF, h->con_ptr,
-                     h->con_col, h->con_val, h->con_c, h->xC, h->con_cp);
-  hipLaunchKernelGGL(k_con_addq<D>, dim3(nblk(h->ncon_rows)), dim3(kBlock), 0, s, h->ncon_rows, h->cont_rows,
-                     h->cont_ptr, h->cont_con, h->cont_val, h->con_gamma, h->con_cp, h->b);
-}
-template <int D>
-void con_after_solve_d(ffd_ctx* h, double* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_con_resid<D>, dim3(nblk(h->ncon)), dim3(kBlock), 0, s, h->ncon, h->con_ptr, h->con_col,
-                     h->con_val, h->con_c, x, h->con_t);
-  hipLaunchKernelGGL(k_con_lambda<D>, dim3(nblk(h->ncon)), dim3(kBlock), 0, s, h->ncon, h->con_Sinv, h->con_t,
-                     h->con_lam);
-  if (h->nF > 0)
-    hipLaunchKernelGGL(k_con_correct<D>, dim3(nblk(h->nF)), dim3(kBlock), 0, s, h->nF, h->ncon, h->con_Z,
-                       h->con_lam, x);
-}
-void con_before_solve(ffd_ctx* h, hipStream_t s) {
-  if (h->d == 2) con_before_solve_d<2>(h, s);
-  else con_before_solve_d<3>(h, s);
-}
-void con_after_solve(ffd_ctx* h, double* x, hipStream_t s) {
-  if (h->d == 2) con_after_solve_d<2>(h, x, s);
-  else con_after_solve_d<3>(h, x, s);
-}
-
-// Z = L~^{-1} A_F^T by solves of D columns at a time, S = A_F Z on the device,
-// S^{-1} on the host (Cholesky with a relative pivot floor: dependent rows
-// are an error).  Synchronous; uses b and con_tmp as scratch.
-ffd_status prepare_constraints(ffd_ctx* h, hipStream_t s) {
-  const int d = h->d;
-  const int64_t nF = h->nF, nc = h->ncon;
-  std::vector<double> rhs(static_cast<size_t>(nF) * d, 0.0);
-  for (int64_t a0 = 0; a0 < nc; a0 += d) {
-    for (int k = 0; k < d && a0 + k < nc; ++k)
-      for (int64_t q = h->con_ptr_h[a0 + k]; q < h->con_ptr_h[a0 + k + 1]; ++q)
-        if (h->con_col_h[q] < nF) rhs[static_cast<size_t>(h->con_col_h[q]) * d + k] = h->con_val_h[q];
-    HIP_TRY(hipMemcpyAsync(h->b, rhs.data(), rhs.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    do_solve(h, h->b, h->con_tmp, s);
-    hipLaunchKernelGGL((d == 2 ? k_con_zcols<2> : k_con_zcols<3>), dim3(nblk(nF)), dim3(kBlock), 0, s, nF, nc, a0,
-                       h->con_tmp, h->con_Z);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(s));
-    for (int k = 0; k < d && a0 + k < nc; ++k)
-      for (int64_t q = h->con_ptr_h[a0 + k]; q < h->con_ptr_h[a0 + k + 1]; ++q)
-        if (h->con_col_h[q] < nF) rhs[static_cast<size_t>(h->con_col_h[q]) * d + k] = 0.0;
-  }
-  hipLaunchKernelGGL(k_con_gram, dim3(nblk(nc * nc)), dim3(kBlock), 0, s, nF, nc, h->con_ptr, h->con_col, h->con_val,
-                     h->con_Z, h->con_Sinv);
-  HIP_TRY(hipGetLastError());
-  std::vector<double> S(static_cast<size_t>(nc) * nc), X(static_cast<size_t>(nc) * nc, 0.0);
-  HIP_TRY(hipMemcpyAsync(S.data(), h->con_Sinv, S.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  // symmetrise, then S = C C^T (C lower, row-major in place)
-  double dmax = 0.0;
-  for (int64_t i = 0; i < nc; ++i) {
-    for (int64_t j = 0; j < i; ++j) S[i * nc + j] = S[j * nc + i] = 0.5 * (S[i * nc + j] + S[j * nc + i]);
-    dmax = std::max(dmax, S[i * nc + i]);
-  }
-  for (int64_t j = 0; j < nc; ++j) {
-    double dj = S[j * nc + j];
-    for (int64_t l = 0; l < j; ++l) dj -= S[j * nc + l] * S[j * nc + l];
-    if (!(dj > 1e-12 * dmax) || !std::isfinite(dj))
-      return fail(FFD_ERR_SINGULAR_SYSTEM, "constraint row " + std::to_string(j) +
-                                               " depends on the others (with the pins): the constraint system is singular");
-    dj = std::sqrt(dj);
-    S[j * nc + j] = dj;
-    for (int64_t i = j + 1; i < nc; ++i) {
-      double t = S[i * nc + j];
-      for (int64_t l = 0; l < j; ++l) t -= S[i * nc + l] * S[j * nc + l];
-      S[i * nc + j] = t / dj;
-    }
-  }
-  // X = C^{-1} (lower), then S^{-1} = X^T X
-  for (int64_t j = 0; j < nc; ++j) {
-    X[j * nc + j] = 1.0 / S[j * nc + j];
-    for (int64_t i = j + 1; i < nc; ++i) {
-      double t = 0.0;
-      for (int64_t l = j; l < i; ++l) t += S[i * nc + l] * X[l * nc + j];
-      X[i * nc + j] = -t / S[i * nc + i];
-    }
-  }
-  std::vector<double> Si(static_cast<size_t>(nc) * nc);
-  for (int64_t i = 0; i < nc; ++i)
-    for (int64_t j = 0; j <= i; ++j) {
-      double t = 0.0;
-      for (int64_t l = i; l < nc; ++l) t += X[l * nc + i] * X[l * nc + j];
-      Si[i * nc + j] = Si[j * nc + i] = t;
-    }
-  HIP_TRY(hipMemcpyAsync(h->con_Sinv, Si.data(), Si.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  return FFD_OK;
-}
-
-// one iteration of Algorithm 1; with ev != nullptr an event is recorded after
-// each of the five phases
-// store_u: write the rotation and |grad f|^2 of this iteration even where the
-// next iteration does not read them (3D with h = 0); they are state outputs, so
-// the last iteration of a call and every iteration whose state is saved store
-// them (2D and h_mode 1 always store them)
-// dev_k: the history record index comes from the device counter (graph capture)
-// diag: also record |G^T Lambda| (history field 9; needs h->glam and h->gtl_part)
-void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true, bool store_u = true,
-                   bool dev_k = false, bool diag = false) {
-  double* xold = h->x[h->cur];
-  double* xnew = h->x[1 - h->cur];
-  do_wrhs(h, xnew, s);
-  if (h->ncon > 0) con_before_solve(h, s);
-  if (ev) (void)hipEventRecord(ev[0], s);
-  if (h->nF > 0) {
-    if (h->d == 2) launch_solve_fwd<2>(h, h->b, s);
-    else launch_solve_fwd<3>(h, h->b, s);
-  }
-  if (ev) (void)hipEventRecord(ev[1], s);
-  if (h->nF > 0) {
-    if (h->d == 2) launch_solve_bwd<2>(h, xnew, s);
-    else launch_solve_bwd<3>(h, xnew, s);
-  }
-  if (h->ncon > 0) con_after_solve(h, xnew, s);
-  if (ev) (void)hipEventRecord(ev[2], s);
-  do_local(h, xnew, xold, store_u ? 1 : 0, s, diag ? h->glam : nullptr);
-  if (ev) (void)hipEventRecord(ev[3], s);
-  double* rec = dev_k ? h->hist : record ? h->hist + h->k * FFD_HIST_FIELDS : h->hist_scratch;
-  int64_t* kd = dev_k ? h->k_dev : nullptr;
-  if (h->nparts > 2 * kFinalizeRows) {
-    const int64_t nb2 = (h->nparts + kFinalizeRows - 1) / kFinalizeRows;
-    hipLaunchKernelGGL(k_partials_reduce, dim3(static_cast<unsigned>(nb2)), dim3(kBlock), 0, s, h->partials,
-                       h->nparts, h->partials2);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials2, nb2, rec, kd, FFD_HIST_FIELDS);
-  } else {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials, h->nparts, rec, kd, FFD_HIST_FIELDS);
-  }
-  if (diag && !dev_k) {
-    const int64_t nb = (4 * h->n + kBlock - 1) / kBlock;
-    if (h->d == 2) {
-      if (h->prec == 32)
-        hipLaunchKernelGGL((k_gtlam<2, float>), dim3(nb), dim3(kBlock), 0, s, h->n, h->av_ptr, h->av_idx,
-                           static_cast<const float*>(h->glam), h->gtl_part);
-      else
-        hipLaunchKernelGGL((k_gtlam<2, double>), dim3(nb), dim3(kBlock), 0, s, h->n, h->av_ptr, h->av_idx,
-                           static_cast<const double*>(h->glam), h->gtl_part);
-    } else {
-      if (h->prec == 32)
-        hipLaunchKernelGGL((k_gtlam<3, float>), dim3(nb), dim3(kBlock), 0, s, h->n, h->av_ptr, h->av_idx,
-                           static_cast<const float*>(h->glam), h->gtl_part);
-      else
-        hipLaunchKernelGGL((k_gtlam<3, double>), dim3(nb), dim3(kBlock), 0, s, h->n, h->av_ptr, h->av_idx,
-                           static_cast<const double*>(h->glam), h->gtl_part);
-    }
-    hipLaunchKernelGGL(k_gtlam_finalize, dim3(1), dim3(kBlock), 0, s, h->gtl_part, nb, rec);
-  }
-  if (ev) (void)hipEventRecord(ev[4], s);
-  h->cur = 1 - h->cur;
-  if (record) h->k += 1;
-}
-
-// Output blocks of one level of one pass: (node, first output, inner range).
-struct OutBlock {
-  int32_t node, out0, lo, hi;
-};
-
-std::vector<OutBlock> level_blocks(const ffd_ctx* h, const std::vector<int32_t>& lvl, bool fwd, int opt) {
-  std::vector<OutBlock> obs;
-  for (int32_t i : lvl) {
-    const SolveNode& N = h->hnodes[i];
-    const int nf = N.c + N.r;
-    if (fwd) {
-      for (int o0 = 0; o0 < nf; o0 += opt) obs.push_back(OutBlock{i, o0, 0, std::min(N.c, o0 + opt)});
-    } else {
-      for (int o0 = 0; o0 < N.c; o0 += opt) obs.push_back(OutBlock{i, o0, o0, nf});
-    }
-  }
-  // longest inner ranges first: the blocks that take longest start first
-  std::stable_sort(obs.begin(), obs.end(),
-                   [](const OutBlock& a, const OutBlock& b) { return a.hi - a.lo > b.hi - b.lo; });
-  return obs;
-}
-
-// Default configuration of a level: four-wave blocks of 64 outputs; a level
-// with fewer than 512 blocks splits inner ranges into the largest chunks
-// (4096 .. 256) that give it 512 tasks.
-LevelCfg default_level_cfg(const ffd_ctx* h, const std::vector<int32_t>& lvl, bool fwd) {
-  constexpr int64_t kMinTasks = 512;
-  LevelCfg c;
-  const std::vector<OutBlock> obs = level_blocks(h, lvl, fwd, 64);
-  if (static_cast<int64_t>(obs.size()) >= kMinTasks) return c;
-  c.chunk = 256;
-  for (int64_t kc = 4096; kc >= 256; kc /= 2) {
-    int64_t nt = 0;
-    for (const OutBlock& o : obs) nt += (o.hi - o.lo + kc - 1) / kc;
-    if (nt >= kMinTasks) {
-      c.chunk = static_cast<int32_t>(kc);
-      break;
-    }
-  }
-  return c;
-}
-
-template <typename T_>
-hipError_t upload_cap(ffd_ctx* h, T_** dst, size_t* cap, const std::vector<T_>& src) {
-  if (src.size() > *cap) {
-    if (*dst) {
-      for (auto& a : h->allocs)
-        if (a == *dst) a = nullptr;
-      (void)hipFree(*dst);
-      *dst = nullptr;
-    }
-    const size_t n = src.size() + src.size() / 4 + 16;
-    hipError_t e = h->alloc(dst, n);
-    if (e != hipSuccess) {
-      *cap = 0;
-      return e;
-    }
-    *cap = n;
-  }
-  if (src.empty()) return hipSuccess;
-  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T_), hipMemcpyHostToDevice);
-}
-
-// worker streams (default priority) and fork / join events for g groups
-hipError_t ensure_workers(ffd_ctx* h, int g) {
-  g = std::min(g, 8);
-  while (static_cast<int>(h->wstreams.size()) < g - 1) {
-    hipStream_t w = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&w, hipStreamNonBlocking);
-    if (e != hipSuccess) return e;
-    h->wstreams.push_back(w);
-  }
-  for (int p = 0; p < 2; ++p) {
-    if (!h->fork_ev[p]) {
-      hipError_t e = hipEventCreateWithFlags(&h->fork_ev[p], hipEventDisableTiming);
-      if (e != hipSuccess) return e;
-    }
-    for (int i = 1; i < g; ++i)
-      if (!h->join_ev[p][i]) {
-        hipError_t e = hipEventCreateWithFlags(&h->join_ev[p][i], hipEventDisableTiming);
-        if (e != hipSuccess) return e;
-      }
-  }
-  return hipSuccess;
-}
-
-// Reorders the main tasks of one level run (from t0 on) so that the tasks of
-// a node run on one XCD, whose L2 then serves the inner vector they all
-// stage: blocks go to the 8 XCDs round-robin by index, so lane x of 8 takes
-// block indices x, x + 8, ...  A node's tasks go to one lane in pieces of at
-// most a lane's share (a level of one node still spreads over all eight),
-// pieces onto the lane with the fewest tasks; each lane keeps the
-// longest-first order; g tasks form a block (one wave each in wave mode);
-// lanes are padded with empty tasks (no outputs).
-void xcd_order(std::vector<SolveTask>& tasks, size_t t0, int g) {
-  constexpr int X = 8;
-  const size_t nt = tasks.size() - t0;
-  if (nt < static_cast<size_t>(2 * X * g)) return;
-  std::vector<std::vector<SolveTask>> byn;
-  std::unordered_map<int64_t, size_t> slot_of;  // node (panel offset) -> its list
-  for (size_t t = t0; t < tasks.size(); ++t) {
-    const auto it = slot_of.emplace(tasks[t].pf, byn.size());
-    if (it.second) byn.emplace_back();
-    byn[it.first->second].push_back(tasks[t]);
-  }
-  std::stable_sort(byn.begin(), byn.end(),
-                   [](const std::vector<SolveTask>& a, const std::vector<SolveTask>& b) { return a.size() > b.size(); });
-  const size_t cap = std::max<size_t>(g, (nt + X - 1) / X);
-  std::vector<std::vector<SolveTask>> lane(X);
-  for (const auto& nd : byn)
-    for (size_t o = 0; o < nd.size(); o += cap) {
-      size_t x = 0;
-      for (size_t y2 = 1; y2 < X; ++y2)
-        if (lane[y2].size() < lane[x].size()) x = y2;
-      lane[x].insert(lane[x].end(), nd.begin() + o, nd.begin() + std::min(nd.size(), o + cap));
-    }
-  size_t groups = 0;
-  for (auto& l : lane) {
-    std::stable_sort(l.begin(), l.end(), [](const SolveTask& a, const SolveTask& b) { return a.hi - a.lo > b.hi - b.lo; });
-    groups = std::max(groups, (l.size() + g - 1) / g);
-  }
-  SolveTask empty{};
-  empty.slot = -1;
-  tasks.resize(t0);
-  for (size_t k = 0; k < groups; ++k)
-    for (int x = 0; x < X; ++x)
-      for (int u = 0; u < g; ++u) {
-        const size_t i = k * g + u;
-        tasks.push_back(i < lane[x].size() ? lane[x][i] : empty);
-      }
-}
-
-// Builds the task lists of both passes from cfg_fwd / cfg_bwd (defaults for
-// levels without one) and uploads them.  Waits for the device first: the
-// task buffers may be in use by earlier launches.
-ffd_status build_solve_schedule(ffd_ctx* h) {
-  h->graph_valid = false;
-  const size_t nlev = h->hlevels.size();
-  if (h->cfg_fwd.size() != nlev || h->cfg_bwd.size() != nlev) {
-    h->cfg_fwd.resize(nlev);
-    h->cfg_bwd.resize(nlev);
-    for (size_t l = 0; l < nlev; ++l) {
-      h->cfg_fwd[l] = default_level_cfg(h, h->hlevels[l], true);
-      h->cfg_bwd[l] = default_level_cfg(h, h->hlevels[l], false);
-    }
-  }
-  auto task_of = [&](const OutBlock& o, bool fwd, int32_t lo, int32_t hi, int32_t slot, int32_t nk) {
-    const SolveNode& N = h->hnodes[o.node];
-    const int32_t nf = N.c + N.r;
-    SolveTask t{};
-    t.pf = h->hpoff[o.node];
-    t.poff = N.poff;
-    t.uoff = N.uoff;
-    t.soff = N.soff;
-    t.ld = fwd ? ((nf + 1) & ~1) : ((N.c + 1) & ~1);
-    t.first = N.first;
-    t.c = N.c;
-    t.nf = nf;
-    t.out0 = o.out0;
-    t.lo = lo;
-    t.hi = hi;
-    t.slot = slot;
-    t.nk = nk;
-    return t;
-  };
-  // groups of the forest below solve_top: whole subtrees, balanced greedily
-  // by panel bytes (largest subtree first onto the lightest group)
-  const int G = std::max(1, std::min(h->solve_groups, 1 + static_cast<int>(h->wstreams.size())));
-  const int top = G > 1 ? std::max(0, std::min(h->solve_top, static_cast<int>(nlev))) : static_cast<int>(nlev);
-  const int nn = static_cast<int>(h->hnodes.size());
-  std::vector<int32_t> group(nn, G);
-  if (G == 1) {
-    std::fill(group.begin(), group.end(), 0);
-  } else {
-    std::vector<double> sub(nn, 0.0);
-    for (int i = 0; i < nn; ++i) {  // postorder: children before parents
-      const SolveNode& N = h->hnodes[i];
-      sub[i] += static_cast<double>(N.c + N.r) * N.c;
-      if (h->hparent[i] >= 0) sub[h->hparent[i]] += sub[i];
-    }
-    std::vector<int32_t> roots;
-    for (int i = 0; i < nn; ++i)
-      if (h->hnodes[i].level < top && (h->hparent[i] < 0 || h->hnodes[h->hparent[i]].level >= top)) roots.push_back(i);
-    std::stable_sort(roots.begin(), roots.end(), [&](int32_t a, int32_t b) { return sub[a] > sub[b]; });
-    std::vector<double> load(G, 0.0);
-    for (int32_t r : roots) {
-      const int g = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
-      group[r] = g;
-      load[g] += sub[r];
-    }
-    for (int i = nn - 1; i >= 0; --i)  // parents before children
-      if (h->hnodes[i].level < top && group[i] == G) group[i] = group[h->hparent[i]];
-  }
-  std::vector<SolveTask> tf, tb, rf, rb;
-  int64_t total_slots = 1;  // backward split partials: per group, reused level by level
-  int64_t fslots = 1;       // forward split partials: kept until the backward pass
-  h->grun_fwd.assign(G + 1, std::vector<LevelRun>(nlev));
-  h->grun_bwd.assign(G + 1, std::vector<LevelRun>(nlev));
-  for (int g = 0; g <= G; ++g) {
-    int64_t gmax = 0;  // slots of this group: reused level by level, disjoint from other groups
-    for (size_t l = 0; l < nlev; ++l) {
-      if ((g < G) != (static_cast<int>(l) < top)) continue;
-      std::vector<int32_t> nodes;
-      for (int32_t i : h->hlevels[l])
-        if (group[i] == g) nodes.push_back(i);
-      if (nodes.empty()) continue;
-      for (int pass = 0; pass < 2; ++pass) {
-        const bool fwd = pass == 0;
-        const LevelCfg& cfg = fwd ? h->cfg_fwd[l] : h->cfg_bwd[l];
-        std::vector<SolveTask>& tasks = fwd ? tf : tb;
-        std::vector<SolveTask>& red = fwd ? rf : rb;
-        LevelRun& run = fwd ? h->grun_fwd[g][l] : h->grun_bwd[g][l];
-        const std::vector<OutBlock> obs = level_blocks(h, nodes, fwd, cfg.opt);
-        run.mode = cfg.mode;
-        run.opt = cfg.opt;
-        run.nw = cfg.nw;
-        run.t0 = static_cast<int32_t>(tasks.size());
-        run.r0 = static_cast<int32_t>(red.size());
-        int32_t slots = 0;
-        const int32_t base = static_cast<int32_t>(fwd ? fslots : total_slots);
-        for (const OutBlock& o : obs) {
-          const int64_t len = o.hi - o.lo;
-          // forward: only blocks of y rows split (update rows feed the parents
-          // within the pass and stay whole)
-          const bool may_split =
-              cfg.mode == 0 && cfg.chunk > 0 && (!fwd || !cfg.defer || o.out0 + cfg.opt <= h->hnodes[o.node].c);
-          const int32_t nk = may_split ? static_cast<int32_t>((len + cfg.chunk - 1) / cfg.chunk) : 1;
-          if (nk <= 1) {
-            tasks.push_back(task_of(o, fwd, o.lo, o.hi, -1, 1));
-            continue;
-          }
-          const int32_t b0 = base + slots;
-          slots += nk;
-          for (int32_t q = 0; q < nk; ++q)
-            tasks.push_back(task_of(o, fwd, static_cast<int32_t>(o.lo + q * cfg.chunk),
-                                    static_cast<int32_t>(std::min<int64_t>(o.hi, o.lo + static_cast<int64_t>(q + 1) * cfg.chunk)),
-                                    b0 + q, nk));
-          red.push_back(task_of(o, fwd, 0, cfg.opt, b0, nk));  // hi: outputs of the block
-        }
-        if (h->xcd_lanes) xcd_order(tasks, static_cast<size_t>(run.t0), cfg.mode == 1 ? 4 : 1);
-        run.nt = static_cast<int32_t>(tasks.size()) - run.t0;
-        run.nr = static_cast<int32_t>(red.size()) - run.r0;
-        run.reduce_now = !fwd || !cfg.defer || l + 1 == nlev;
-        if (fwd) fslots += slots;
-        else gmax = std::max<int64_t>(gmax, slots);
-      }
-    }
-    total_slots += gmax;
-  }
-  const int64_t max_slots = total_slots;
-  // forward y-row reductions of level l run in the backward launch of level
-  // l + 1 of the same stream group; those of the forest groups' level top - 1
-  // in the top group's launch of level top (before the fork); the highest
-  // level's in a launch of their own at the end of the forward pass
-  std::vector<SolveTask> yr;
-  auto attach = [&](LevelRun& br, int gsrc, size_t lsrc) {
-    const LevelRun& fr = h->grun_fwd[gsrc][lsrc];
-    if (fr.reduce_now) return;
-    for (int32_t q = 0; q < fr.nr; ++q) yr.push_back(rf[fr.r0 + q]);
-    br.ny += fr.nr;
-  };
-  for (int g = 0; g <= G; ++g)
-    for (size_t l = 1; l < nlev; ++l) {
-      if ((g < G) != (static_cast<int>(l) < top)) continue;
-      LevelRun& br = h->grun_bwd[g][l];
-      br.y0 = static_cast<int32_t>(yr.size());
-      br.ny = 0;
-      if (g == G && static_cast<int>(l) == top) {
-        for (int gf = 0; gf < G; ++gf) attach(br, gf, l - 1);
-      } else {
-        attach(br, g, l - 1);
-      }
-    }
-  h->solve_groups = G;
-  h->solve_top = top;
-  if (hipDeviceSynchronize() != hipSuccess) return fail(FFD_ERR_DEVICE, "device error before a schedule upload");
-  bool ok = upload_cap(h, &h->tasks_fwd, &h->cap_tf, tf) == hipSuccess &&
-            upload_cap(h, &h->tasks_bwd, &h->cap_tb, tb) == hipSuccess &&
-            upload_cap(h, &h->red_fwd, &h->cap_rf, rf) == hipSuccess &&
-            upload_cap(h, &h->red_bwd, &h->cap_rb, rb) == hipSuccess &&
-            upload_cap(h, &h->yred, &h->cap_yr, yr) == hipSuccess;
-  if (ok && static_cast<size_t>(fslots) > h->cap_fslots) {
-    if (h->fpart) {
-      for (auto& a : h->allocs)
-        if (a == h->fpart) a = nullptr;
-      (void)hipFree(h->fpart);
-      h->fpart = nullptr;
-    }
-    ok = h->alloc(&h->fpart, static_cast<size_t>(fslots) * kSolveOutMax * h->d) == hipSuccess;
-    h->cap_fslots = ok ? static_cast<size_t>(fslots) : 0;
-  }
-  if (ok && static_cast<size_t>(max_slots) > h->cap_slots) {
-    if (h->solve_part) {
-      for (auto& a : h->allocs)
-        if (a == h->solve_part) a = nullptr;
-      (void)hipFree(h->solve_part);
-      h->solve_part = nullptr;
-    }
-    ok = h->alloc(&h->solve_part, static_cast<size_t>(max_slots) * kSolveOutMax * h->d) == hipSuccess;
-    h->cap_slots = ok ? static_cast<size_t>(max_slots) : 0;
-  }
-  if (!ok) return fail(FFD_ERR_OUT_OF_MEMORY, "solve schedule upload failed");
-  return FFD_OK;
-}
-
-// Rebuilds the factor of L = G^T M G for per-element penalties mu_dev_order
-// (device element order; nullptr: rho w_e) from the kept set-up input and
-// writes the new panels and pinned-coupling values into the existing buffers:
-// the ordering and the factor structure do not depend on the penalties
-// (checked).  Synchronous.
-ffd_status refactor(ffd_ctx* h, const std::vector<double>* mu_dev_order, hipStream_t s) {
-  std::vector<double> mu_in;
-  SetupInput in;
-  in.d = h->d;
-  in.din = h->din;
-  in.n = h->n;
-  in.m = h->m;
-  in.V = h->in_V.data();
-  in.T = h->in_T.data();
-  in.rho = h->rho;
-  in.n_pinned = static_cast<int64_t>(h->in_pins.size());
-  in.pinned_idx = h->in_pins.data();
-  in.leaf_size = h->in_leaf;
-  in.elem_energy = h->in_energy.empty() ? nullptr : h->in_energy.data();
-  if (h->ncon > 0) {
-    in.n_con = h->ncon;
-    in.con_ptr = h->in_con_ptr.data();
-    in.con_col = h->in_con_col.data();
-    in.con_val = h->in_con_val.data();
-  }
-  if (mu_dev_order) {
-    mu_in.resize(h->m);
-    for (int64_t e = 0; e < h->m; ++e) mu_in[h->enew2old_h[e]] = (*mu_dev_order)[e];
-    in.mu_elem = mu_in.data();
-  }
-  Setup S;
-  std::string err;
-  const int st = build_setup(in, S, err);
-  if (st != OK) return fail(static_cast<ffd_status>(st), err);
-  bool same = S.nodes.size() == h->hnodes.size() && S.pin_val.size() == h->n_pin_val &&
-              S.lcf_val.size() == h->n_lcf_val && S.panel_entries == h->info.panel_entries;
-  for (size_t i = 0; same && i < S.nodes.size(); ++i)
-    same = S.nodes[i].first == h->hnodes[i].first && S.nodes[i].c == h->hnodes[i].c && S.nodes[i].r == h->hnodes[i].r;
-  std::vector<double> prow, pcol;
-  std::vector<int64_t> poff;
-  if (same) {
-    build_device_panels(S, prow, pcol, poff);
-    same = poff == h->hpoff;
-  }
-  if (!same) return fail(FFD_ERR_STATE, "the factor structure changed on refactorisation");
-  // on the caller's stream, after its pending work; the host vectors live
-  // until the stream has drained
-  HIP_TRY(hipMemcpyAsync(h->Prow, prow.data(), prow.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(h->Pcol, pcol.data(), pcol.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  if (!S.pin_val.empty())
-    HIP_TRY(hipMemcpyAsync(h->pin_val, S.pin_val.data(), S.pin_val.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  if (!S.lcf_val.empty())
-    HIP_TRY(hipMemcpyAsync(h->lcf_val, S.lcf_val.data(), S.lcf_val.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (h->ncon > 0) {
-    h->con_gamma = S.con_gamma;
-    h->graph_valid = false;  // gamma is a kernel argument
-    return prepare_constraints(h, s);
-  }
-  return FFD_OK;
-}
-
-// one rescaling event on the device, then the factor for the new penalties
-ffd_status do_rescale(ffd_ctx* h, double rho_r, hipStream_t s) {
-  if (!h->rho_e) {
-    HIP_TRY(h->alloc(reinterpret_cast<char**>(&h->rho_e), h->rsize() * h->m));
-    HIP_TRY(h->alloc(&h->mu_dev, static_cast<size_t>(h->m)));
-  }
-  if (!h->rescaled) {
-    if (h->prec == 32) {
-      std::vector<float> r(h->m, static_cast<float>(h->rho));
-      HIP_TRY(hipMemcpyAsync(h->rho_e, r.data(), r.size() * sizeof(float), hipMemcpyHostToDevice, s));
-      HIP_TRY(hipStreamSynchronize(s));
-    } else {
-      std::vector<double> r(h->m, h->rho);
-      HIP_TRY(hipMemcpyAsync(h->rho_e, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice, s));
-      HIP_TRY(hipStreamSynchronize(s));
-    }
-    h->rescaled = true;
-    h->graph_valid = false;
-  }
-  for (const auto& g : h->segs) SEG_CASES(launch_rescale, h, g, rho_r, s)
-  std::vector<double> mu(h->m);
-  HIP_TRY(hipMemcpyAsync(mu.data(), h->mu_dev, mu.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  return refactor(h, &mu, s);
-}
-
-ffd_status ensure_hist(ffd_ctx* h, int64_t need, hipStream_t s) {
-  if (need <= h->hist_cap) return FFD_OK;
-  int64_t cap = std::max<int64_t>(kHistCap0, h->hist_cap);
-  while (cap < need) cap *= 2;
-  double* nh = nullptr;
-  HIP_TRY(hipMalloc(&nh, cap * FFD_HIST_FIELDS * sizeof(double)));
-  if (h->hist) {
-    HIP_TRY(hipMemcpyAsync(nh, h->hist, h->hist_cap * FFD_HIST_FIELDS * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    for (auto& p : h->allocs)
-      if (p == h->hist) p = nh;
-    (void)hipFree(h->hist);
-    h->device_bytes += (cap - h->hist_cap) * FFD_HIST_FIELDS * sizeof(double);
-  } else {
-    h->allocs.push_back(nh);
-    h->device_bytes += cap * FFD_HIST_FIELDS * sizeof(double);
-  }
-  h->hist = nh;
-  h->hist_cap = cap;
-  return FFD_OK;
-}
-
-
-// ---------------------------------------------------------------------------
-// adjoint helpers
-// ---------------------------------------------------------------------------
-struct SlotView {
-  void *U, *P, *L, *gn, *g;
-  double* x;
-};
-
-SlotView slot_view(ffd_ctx* h, char* base) {
-  const size_t nU = h->d == 2 ? 2 : 9, nP = h->d == 2 ? 3 : 6, rs = h->rsize(), m = h->m, d = h->d;
-  SlotView v;
-  v.U = base;
-  v.P = base + rs * m * nU;
-  v.L = base + rs * m * (nU + nP);
-  v.gn = base + rs * m * (nU + nP + d * d);
-  v.g = base + rs * m * (nU + nP + d * d + 1);
-  const size_t el = rs * m * h->slot_elem_entries();
-  v.x = reinterpret_cast<double*>(base + ((el + 255) / 256) * 256);
-  return v;
-}
-
-// element state and map, copied in both directions
-hipError_t copy_state(ffd_ctx* h, char* slot, bool save, hipStream_t s) {
-  const size_t nU = h->d == 2 ? 2 : 9, nP = h->d == 2 ? 3 : 6, rs = h->rsize(), m = h->m, d = h->d;
-  SlotView v = slot_view(h, slot);
-  void* live[6] = {h->U, h->P, h->L, h->gn, h->g, h->x[h->cur]};
-  void* saved[6] = {v.U, v.P, v.L, v.gn, v.g, v.x};
-  const size_t bytes[6] = {rs * m * nU, rs * m * nP, rs * m * d * d, rs * m, rs * m * (d + 1) * d,
-                           sizeof(double) * h->n * d};
-  for (int i = 0; i < 6; ++i) {
-    hipError_t e = save ? hipMemcpyAsync(saved[i], live[i], bytes[i], hipMemcpyDeviceToDevice, s)
-                        : hipMemcpyAsync(live[i], saved[i], bytes[i], hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-hipError_t save_state(ffd_ctx* h, char* slot, hipStream_t s) { return copy_state(h, slot, true, s); }
-hipError_t load_state(ffd_ctx* h, char* slot, hipStream_t s) { return copy_state(h, slot, false, s); }
-
-template <int D, typename R, int E>
-void launch_adj_seed(ffd_ctx* h, const ffd_ctx::Seg& g, const void* Pbar_ext, int energy_loss, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_seed<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1,
-                     static_cast<const R*>(h->P),
-                     static_cast<const R*>(h->w), energy_loss, static_cast<const R*>(Pbar_ext), h->enew2old_d,
-                     h->Ubar, h->Pbar, h->Lbar, h->Bbar, h->wbar);
-}
-
-template <int D, typename R, int E>
-void launch_adj_local(ffd_ctx* h, const ffd_ctx::Seg& g, const SlotView& prev, const double* x, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_local<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1, h->T,
-                     static_cast<const R*>(h->B), h->B64, static_cast<R>(h->rho), x, static_cast<const R*>(prev.U),
-                     static_cast<const R*>(prev.P), static_cast<const R*>(prev.L), h->Ubar, h->Pbar, h->Lbar, h->Bbar,
-                     h->gadj);
-}
-
-template <int D, typename R, int E>
-void launch_adj_wstep(ffd_ctx* h, const SlotView& prev, const double* x, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_wstep<D, R>), dim3(nblk(h->m)), dim3(kBlock), 0, s, h->m, h->T, h->B64,
-                     static_cast<const R*>(h->w), static_cast<R>(h->rho), x, h->lam, static_cast<const R*>(prev.U),
-                     static_cast<const R*>(prev.P), static_cast<const R*>(prev.L), h->Ubar, h->Pbar, h->Lbar, h->Bbar,
-                     h->wbar);
-}
-
-template <int D, typename R, int E>
-void launch_adj_vbar(ffd_ctx* h, hipStream_t s) {
-  hipLaunchKernelGGL((k_adj_vbar<D, R>), dim3(nblk(h->m)), dim3(kBlock), 0, s, h->m, h->B64,
-                     static_cast<const R*>(h->w), h->Bbar, h->wbar, h->gadj);
-}
-
-#define ADJ_DISPATCH(FN, ...)                                                        \
-  do {                                                                               \
-    switch (h->d * 100 + h->prec + h->energy) {                                      \
-      case 232: FN<2, float, 0>(__VA_ARGS__); break;                                 \
-      case 233: FN<2, float, 1>(__VA_ARGS__); break;                                 \
-      case 264: FN<2, double, 0>(__VA_ARGS__); break;                                \
-      case 265: FN<2, double, 1>(__VA_ARGS__); break;                                \
-      case 332: FN<3, float, 0>(__VA_ARGS__); break;                                 \
-      case 333: FN<3, float, 1>(__VA_ARGS__); break;                                 \
-      case 364: FN<3, double, 0>(__VA_ARGS__); break;                                \
-      case 365: FN<3, double, 1>(__VA_ARGS__); break;                                \
-    }                                                                                \
-  } while (0)
-
-}  // namespace
+// This file holds the extern "C" entry points; the runtime they use is one
+// translation unit with it, in runtime/ (each header includes the previous):
+// context (handle state) -> launch (one iteration) -> schedule (solve task
+// lists) -> state (refactorisation, checkpoints, adjoint launches) -> create
+// (handle set-up) -> graph (captured iterations) -> tune (autotuner timing).
+#include "runtime/tune.hpp"
 
 extern "C" {
 
@@ -1113,223 +15,6 @@ const char* ffd_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
 
-namespace {
-
-// shared by ffd_create and ffd_batch_create: mesh is the (concatenated) mesh,
-// opt the common options, pins in mesh indices, pin_pos empty = taken from W^0
-ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const std::vector<int32_t>& pins,
-                       const std::vector<double>& pin_pos, bool auto_pinned, const std::vector<int8_t>& elem_energy,
-                       const std::vector<int64_t>& voff, const std::vector<int64_t>& eoff, ffd_handle* out,
-                       bool tutte = false, const ffd_constraints* con = nullptr) {
-  const ffd_mesh* mesh = &mesh_in;
-  const int d = mesh->simplex_dim;
-  SetupInput in;
-  in.d = d;
-  in.din = mesh->dim_in;
-  in.n = mesh->n_vertices;
-  in.m = mesh->n_elements;
-  in.V = mesh->V;
-  in.T = mesh->T;
-  in.rho = opt.rho;
-  in.n_pinned = static_cast<int64_t>(pins.size());
-  in.pinned_idx = pins.data();
-  in.leaf_size = opt.leaf_size;
-  in.elem_energy = elem_energy.empty() ? nullptr : elem_energy.data();
-  in.tutte = tutte;
-  if (con && con->n_rows > 0) {
-    in.n_con = con->n_rows;
-    in.con_ptr = con->row_ptr;
-    in.con_col = con->col_idx;
-    in.con_val = con->val;
-  }
-  Setup S;
-  std::string err;
-  int st = build_setup(in, S, err);
-  if (st != OK) return fail(static_cast<ffd_status>(st), err);
-
-  auto h = new ffd_ctx();
-  auto cleanup = [&](ffd_status s2) {
-    std::string msg = g_last_error;
-    delete h;
-    g_last_error = msg;
-    return s2;
-  };
-  (void)hipGetDevice(&h->dev);
-  const auto t0 = std::chrono::steady_clock::now();
-  h->d = d;
-  h->din = S.din;
-  h->prec = opt.precision;
-  h->energy = opt.energy;
-  h->h_mode = opt.h_mode;
-  h->rho = opt.rho;
-  h->n = S.n;
-  h->m = S.m;
-  h->nF = S.nF;
-  h->nC = S.nC;
-  h->pins_given = !pin_pos.empty();
-  h->voff = voff;
-  h->eoff = eoff;
-  h->auto_pinned = auto_pinned;
-  h->vnew2old = S.vnew2old;
-  h->in_V.assign(mesh->V, mesh->V + mesh->n_vertices * mesh->dim_in);
-  h->in_T.assign(mesh->T, mesh->T + mesh->n_elements * (d + 1));
-  h->in_pins = pins;
-  h->in_energy = elem_energy;
-  h->in_leaf = opt.leaf_size;
-  h->enew2old_h = S.enew2old;
-  if (in.n_con > 0) {
-    h->ncon = in.n_con;
-    h->in_con_ptr.assign(in.con_ptr, in.con_ptr + in.n_con + 1);
-    h->in_con_col.assign(in.con_col, in.con_col + in.con_ptr[in.n_con]);
-    h->in_con_val.assign(in.con_val, in.con_val + in.con_ptr[in.n_con]);
-    h->con_ptr_h = S.con_ptr;
-    h->con_col_h = S.con_col;
-    h->con_val_h = S.con_val;
-    h->con_gamma = S.con_gamma;
-    h->ncon_rows = static_cast<int64_t>(S.cont_rows.size());
-  }
-  const int64_t m = S.m, n = S.n, nc = d + 1;
-  hipError_t e = hipSuccess;
-#define UP(expr)                                                     \
-  do {                                                               \
-    e = (expr);                                                      \
-    if (e != hipSuccess) {                                           \
-      fail(e == hipErrorOutOfMemory ? FFD_ERR_OUT_OF_MEMORY : FFD_ERR_DEVICE, \
-           std::string(#expr) + ": " + hipGetErrorString(e));        \
-      return cleanup(e == hipErrorOutOfMemory ? FFD_ERR_OUT_OF_MEMORY : FFD_ERR_DEVICE); \
-    }                                                                \
-  } while (0)
-  {
-    std::vector<int32_t> Tsoa(static_cast<size_t>(m) * nc);
-    for (int64_t el = 0; el < m; ++el)
-      for (int c = 0; c < nc; ++c) Tsoa[static_cast<size_t>(c) * m + el] = S.T[el * nc + c];
-    UP(upload(h, &h->T, Tsoa));
-  }
-  UP(upload(h, &h->vnew2old_d, S.vnew2old));
-  UP(upload(h, &h->enew2old_d, S.enew2old));
-  UP(upload(h, &h->B64, soa<double>(S.B, m, d * d)));
-  if (h->prec == 32) {
-    float *Bf = nullptr, *wf = nullptr;
-    UP(upload(h, &Bf, soa<float>(S.B, m, d * d)));
-    UP(upload(h, &wf, soa<float>(S.w, m, 1)));
-    h->B = Bf;
-    h->w = wf;
-  } else {
-    double *Bd = nullptr, *wd = nullptr;
-    UP(upload(h, &Bd, soa<double>(S.B, m, d * d)));
-    UP(upload(h, &wd, S.w));
-    h->B = Bd;
-    h->w = wd;
-  }
-  UP(h->alloc(&h->x[0], n * d));
-  UP(h->alloc(&h->x[1], n * d));
-  UP(h->alloc(&h->xC, std::max<int64_t>(h->nC, 1) * d));
-  const size_t rs = h->rsize();
-  const int nU = d == 2 ? 2 : 9, nP = d == 2 ? 3 : 6;
-  char* tmp = nullptr;
-  UP(h->alloc(&tmp, rs * m * nU));
-  h->U = tmp;
-  UP(h->alloc(&tmp, rs * m * nP));
-  h->P = tmp;
-  UP(h->alloc(&tmp, rs * m * d * d));
-  h->L = tmp;
-  UP(h->alloc(&tmp, rs * m));
-  h->gn = tmp;
-  UP(h->alloc(&tmp, rs * m * nc * d));
-  h->g = tmp;
-  UP(h->alloc(&h->b, std::max<int64_t>(h->nF, 1) * d));
-  UP(h->alloc(&h->y, std::max<int64_t>(h->nF, 1) * d));
-  UP(h->alloc(&h->ub, std::max<int64_t>(S.ubuf_rows, 1) * d));
-  {
-    if (elem_energy.empty()) {
-      h->segs.push_back(ffd_ctx::Seg{0, m, opt.energy, 0});
-    } else {
-      if (S.m_energy0 > 0) h->segs.push_back(ffd_ctx::Seg{0, S.m_energy0, 0, 0});
-      if (S.m_energy0 < m) h->segs.push_back(ffd_ctx::Seg{S.m_energy0, m, 1, 0});
-    }
-    int64_t pmax = 0;
-    for (auto& g : h->segs) pmax += (g.e1 - g.e0 + 63) / 64;
-    set_local_block(h, 256);
-    UP(h->alloc(&h->partials, static_cast<size_t>(std::max<int64_t>(pmax, 1)) * kNumPartials));
-    UP(h->alloc(&h->partials2, static_cast<size_t>((pmax + kFinalizeRows - 1) / kFinalizeRows + 1) * kNumPartials));
-  }
-  UP(upload(h, &h->dt_ptr, S.dt_ptr));
-  UP(upload(h, &h->dt_idx, S.dt_idx));
-  UP(upload(h, &h->pin_ptr, S.pin_ptr));
-  UP(upload(h, &h->pin_col, S.pin_col));
-  UP(upload(h, &h->pin_val, S.pin_val));
-  h->n_pin_val = S.pin_val.size();
-  h->n_lcf_val = S.lcf_val.size();
-  UP(upload(h, &h->av_ptr, S.av_ptr));
-  UP(upload(h, &h->av_idx, S.av_idx));
-  UP(upload(h, &h->lcf_ptr, S.lcf_ptr));
-  UP(upload(h, &h->lcf_col, S.lcf_col));
-  UP(upload(h, &h->lcf_val, S.lcf_val));
-  UP(h->alloc(&h->hist_scratch, FFD_HIST_FIELDS));
-  {
-    std::vector<double> prow, pcol;
-    std::vector<int64_t> poff;
-    build_device_panels(S, prow, pcol, poff);
-    std::vector<double>().swap(S.panel_f);
-    UP(upload(h, &h->Prow, prow));
-    std::vector<double>().swap(prow);
-    UP(upload(h, &h->Pcol, pcol));
-    std::vector<double>().swap(pcol);
-    h->hpoff = poff;
-    h->hnodes = S.nodes;
-    h->hlevels = S.level_nodes;
-    h->hparent.assign(S.nodes.size(), -1);
-    for (size_t i = 0; i < S.children.size(); ++i)
-      for (int32_t ch : S.children[i]) h->hparent[ch] = static_cast<int32_t>(i);
-    h->solve_top = static_cast<int>(S.level_nodes.size());
-    if (build_solve_schedule(h) != FFD_OK) return cleanup(FFD_ERR_OUT_OF_MEMORY);
-  }
-  UP(upload(h, &h->sidx, S.struct_idx));
-  UP(upload(h, &h->pull_ptr, S.pull_ptr));
-  UP(upload(h, &h->pull_idx, S.pull_idx));
-  if (h->pins_given) UP(hipMemcpy(h->xC, pin_pos.data(), pin_pos.size() * sizeof(double), hipMemcpyHostToDevice));
-  if (h->ncon > 0) {
-    const std::vector<double> crhs(con->rhs, con->rhs + h->ncon * d);
-    UP(upload(h, &h->con_ptr, S.con_ptr));
-    UP(upload(h, &h->con_col, S.con_col));
-    UP(upload(h, &h->con_val, S.con_val));
-    UP(upload(h, &h->cont_rows, S.cont_rows));
-    UP(upload(h, &h->cont_ptr, S.cont_ptr));
-    UP(upload(h, &h->cont_con, S.cont_con));
-    UP(upload(h, &h->cont_val, S.cont_val));
-    UP(upload(h, &h->con_c, crhs));
-    UP(h->alloc(&h->con_cp, static_cast<size_t>(h->ncon) * d));
-    UP(h->alloc(&h->con_t, static_cast<size_t>(h->ncon) * d));
-    UP(h->alloc(&h->con_lam, static_cast<size_t>(h->ncon) * d));
-    UP(h->alloc(&h->con_Z, static_cast<size_t>(h->ncon) * static_cast<size_t>(std::max<int64_t>(S.nF, 1))));
-    UP(h->alloc(&h->con_Sinv, static_cast<size_t>(h->ncon) * h->ncon));
-    UP(h->alloc(&h->con_tmp, static_cast<size_t>(n) * d));
-  }
-  UP(hipDeviceSynchronize());
-#undef UP
-  if (h->ncon > 0) {
-    const ffd_status cst = prepare_constraints(h, nullptr);
-    if (cst != FFD_OK) return cleanup(cst);
-  }
-  const auto t1 = std::chrono::steady_clock::now();
-  ffd_info& I = h->info;
-  I.n_free = S.nF;
-  I.n_pinned = S.nC;
-  I.factor_nnz = S.factor_nnz;
-  I.panel_entries = S.panel_entries;
-  I.n_nodes = static_cast<int32_t>(S.nodes.size());
-  I.n_levels = static_cast<int32_t>(S.level_nodes.size());
-  I.t_geometry = S.t_geometry;
-  I.t_order = S.t_order;
-  I.t_symbolic = S.t_symbolic;
-  I.t_numeric = S.t_numeric;
-  I.t_upload = std::chrono::duration<double>(t1 - t0).count();
-  I.factor_flops = S.factor_flops;
-  *out = h;
-  return FFD_OK;
-}
-
-}  // namespace
 extern "C" {
 
 ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* out) {
@@ -1600,39 +285,6 @@ ffd_status ffd_iterate(ffd_handle h, int32_t n_iter, void* stream) {
 }
 
 }  // extern "C"
-
-namespace {
-
-// Captures two iterations (so the two map buffers return to their roles) on
-// the handle's own stream; history records are addressed through the device
-// counter.  Host bookkeeping changed by the capture is restored.
-ffd_status capture_graph(ffd_ctx* h) {
-  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
-  if (h->graph) (void)hipGraphDestroy(h->graph);
-  h->graph_exec = nullptr;
-  h->graph = nullptr;
-  h->graph_valid = false;
-  if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-  if (!h->k_dev) HIP_TRY(h->alloc(&h->k_dev, 1));
-  const int cur0 = h->cur;
-  const int64_t k0 = h->k;
-  HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-  one_iteration(h, h->cap_stream, nullptr, true, true, true);
-  one_iteration(h, h->cap_stream, nullptr, true, true, true);
-  hipGraph_t g = nullptr;
-  const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
-  h->cur = cur0;
-  h->k = k0;
-  if (e != hipSuccess || !g) return fail(FFD_ERR_DEVICE, "graph capture failed");
-  h->graph = g;
-  HIP_TRY(hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0));
-  h->graph_cur = cur0;
-  h->graph_hist = h->hist;
-  h->graph_valid = true;
-  return FFD_OK;
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -2019,77 +671,6 @@ ffd_status ffd_adjoint_backward(ffd_handle h, const void* Pbar_dev, int32_t ener
 
 }  // extern "C"
 
-namespace {
-
-// time `iters` iterations (not recorded) and return the summed milliseconds of
-// phase `phase` (0 right-hand side, 1+2 solve, 3 local step)
-double time_phase(ffd_ctx* h, hipStream_t s, int phase, int iters) {
-  const size_t need = static_cast<size_t>(iters) * 5 + 1;
-  while (h->events.size() < need) {
-    hipEvent_t ev;
-    if (hipEventCreate(&ev) != hipSuccess) return 1e30;
-    h->events.push_back(ev);
-  }
-  for (int it = 0; it < 2; ++it) one_iteration(h, s, nullptr, false, true);
-  (void)hipEventRecord(h->events[0], s);
-  for (int it = 0; it < iters; ++it) one_iteration(h, s, h->events.data() + 1 + static_cast<size_t>(it) * 5, false, true);
-  if (hipEventSynchronize(h->events[need - 1]) != hipSuccess) return 1e30;
-  double tot = 0.0;
-  for (int it = 0; it < iters; ++it)
-    for (int p = 0; p < 5; ++p) {
-      const bool want = phase == 1 ? (p == 1 || p == 2) : p == phase;
-      if (!want) continue;
-      float ms = 0.f;
-      const size_t i = 1 + static_cast<size_t>(it) * 5 + p;
-      (void)hipEventElapsedTime(&ms, h->events[i - 1], h->events[i]);
-      tot += ms;
-    }
-  return tot;
-}
-
-// milliseconds of one forward (or backward) solve pass on the current
-// right-hand side, the smallest of `reps` timed passes after one untimed one
-double time_solve_pass(ffd_ctx* h, hipStream_t s, bool fwd, int reps) {
-  while (h->events.size() < 2) {
-    hipEvent_t ev;
-    if (hipEventCreate(&ev) != hipSuccess) return 1e30;
-    h->events.push_back(ev);
-  }
-  double* xs = h->x[1 - h->cur];
-  double best = 1e30;
-  for (int r = 0; r <= reps; ++r) {
-    (void)hipEventRecord(h->events[0], s);
-    if (fwd) {
-      if (h->d == 2) launch_solve_fwd<2>(h, h->b, s);
-      else launch_solve_fwd<3>(h, h->b, s);
-    } else {
-      if (h->d == 2) launch_solve_bwd<2>(h, xs, s);
-      else launch_solve_bwd<3>(h, xs, s);
-    }
-    (void)hipEventRecord(h->events[1], s);
-    if (hipEventSynchronize(h->events[1]) != hipSuccess) return 1e30;
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, h->events[0], h->events[1]);
-    if (r > 0) best = std::min(best, static_cast<double>(ms));
-  }
-  return best;
-}
-
-std::string tune_key(ffd_ctx* h) {
-  hipDeviceProp_t prop;
-  std::string arch = hipGetDeviceProperties(&prop, h->dev) == hipSuccess ? prop.gcnArchName : "unknown";
-  const size_t colon = arch.find(':');
-  if (colon != std::string::npos) arch = arch.substr(0, colon);
-  int64_t mb = 1, nb = 1;
-  while (mb < h->m) mb *= 2;
-  while (nb < h->info.factor_nnz) nb *= 2;
-  std::string energy = h->segs.size() > 1 ? "mixed" : std::to_string(h->segs.empty() ? 0 : h->segs[0].energy);
-  return arch + "|d" + std::to_string(h->d) + "|e" + energy + "|p" + std::to_string(h->prec) + "|m" +
-         std::to_string(mb) + "|nnz" + std::to_string(nb) + "|lv" + std::to_string(h->hlevels.size()) + "|h" +
-         std::to_string(h->h_mode);
-}
-
-}  // namespace
 extern "C" {
 
 ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int32_t* choice_out) {

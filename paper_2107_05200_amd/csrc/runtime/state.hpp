@@ -1,0 +1,205 @@
+// Refactorisation after a penalty rescaling event, the history buffer, state
+// slots (checkpoints) and the adjoint launch helpers.  Part of the single
+// translation unit capi.hip.
+#pragma once
+
+#include "schedule.hpp"
+
+namespace {
+
+// Rebuilds the factor of L = G^T M G for per-element penalties mu_dev_order
+// (device element order; nullptr: rho w_e) from the kept set-up input and
+// writes the new panels and pinned-coupling values into the existing buffers:
+// the ordering and the factor structure do not depend on the penalties
+// (checked).  Synchronous.
+ffd_status refactor(ffd_ctx* h, const std::vector<double>* mu_dev_order, hipStream_t s) {
+  std::vector<double> mu_in;
+  SetupInput in;
+  in.d = h->d;
+  in.din = h->din;
+  in.n = h->n;
+  in.m = h->m;
+  in.V = h->in_V.data();
+  in.T = h->in_T.data();
+  in.rho = h->rho;
+  in.n_pinned = static_cast<int64_t>(h->in_pins.size());
+  in.pinned_idx = h->in_pins.data();
+  in.leaf_size = h->in_leaf;
+  in.elem_energy = h->in_energy.empty() ? nullptr : h->in_energy.data();
+  if (h->ncon > 0) {
+    in.n_con = h->ncon;
+    in.con_ptr = h->in_con_ptr.data();
+    in.con_col = h->in_con_col.data();
+    in.con_val = h->in_con_val.data();
+  }
+  if (mu_dev_order) {
+    mu_in.resize(h->m);
+    for (int64_t e = 0; e < h->m; ++e) mu_in[h->enew2old_h[e]] = (*mu_dev_order)[e];
+    in.mu_elem = mu_in.data();
+  }
+  Setup S;
+  std::string err;
+  const int st = build_setup(in, S, err);
+  if (st != OK) return fail(static_cast<ffd_status>(st), err);
+  bool same = S.nodes.size() == h->hnodes.size() && S.pin_val.size() == h->n_pin_val &&
+              S.lcf_val.size() == h->n_lcf_val && S.panel_entries == h->info.panel_entries;
+  for (size_t i = 0; same && i < S.nodes.size(); ++i)
+    same = S.nodes[i].first == h->hnodes[i].first && S.nodes[i].c == h->hnodes[i].c && S.nodes[i].r == h->hnodes[i].r;
+  std::vector<double> prow, pcol;
+  std::vector<int64_t> poff;
+  if (same) {
+    build_device_panels(S, prow, pcol, poff);
+    same = poff == h->hpoff;
+  }
+  if (!same) return fail(FFD_ERR_STATE, "the factor structure changed on refactorisation");
+  // on the caller's stream, after its pending work; the host vectors live
+  // until the stream has drained
+  HIP_TRY(hipMemcpyAsync(h->Prow, prow.data(), prow.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->Pcol, pcol.data(), pcol.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  if (!S.pin_val.empty())
+    HIP_TRY(hipMemcpyAsync(h->pin_val, S.pin_val.data(), S.pin_val.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  if (!S.lcf_val.empty())
+    HIP_TRY(hipMemcpyAsync(h->lcf_val, S.lcf_val.data(), S.lcf_val.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h->ncon > 0) {
+    h->con_gamma = S.con_gamma;
+    h->graph_valid = false;  // gamma is a kernel argument
+    return prepare_constraints(h, s);
+  }
+  return FFD_OK;
+}
+
+// one rescaling event on the device, then the factor for the new penalties
+ffd_status do_rescale(ffd_ctx* h, double rho_r, hipStream_t s) {
+  if (!h->rho_e) {
+    HIP_TRY(h->alloc(reinterpret_cast<char**>(&h->rho_e), h->rsize() * h->m));
+    HIP_TRY(h->alloc(&h->mu_dev, static_cast<size_t>(h->m)));
+  }
+  if (!h->rescaled) {
+    if (h->prec == 32) {
+      std::vector<float> r(h->m, static_cast<float>(h->rho));
+      HIP_TRY(hipMemcpyAsync(h->rho_e, r.data(), r.size() * sizeof(float), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    } else {
+      std::vector<double> r(h->m, h->rho);
+      HIP_TRY(hipMemcpyAsync(h->rho_e, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+    h->rescaled = true;
+    h->graph_valid = false;
+  }
+  for (const auto& g : h->segs) SEG_CASES(launch_rescale, h, g, rho_r, s)
+  std::vector<double> mu(h->m);
+  HIP_TRY(hipMemcpyAsync(mu.data(), h->mu_dev, mu.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return refactor(h, &mu, s);
+}
+
+ffd_status ensure_hist(ffd_ctx* h, int64_t need, hipStream_t s) {
+  if (need <= h->hist_cap) return FFD_OK;
+  int64_t cap = std::max<int64_t>(kHistCap0, h->hist_cap);
+  while (cap < need) cap *= 2;
+  double* nh = nullptr;
+  HIP_TRY(hipMalloc(&nh, cap * FFD_HIST_FIELDS * sizeof(double)));
+  if (h->hist) {
+    HIP_TRY(hipMemcpyAsync(nh, h->hist, h->hist_cap * FFD_HIST_FIELDS * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (auto& p : h->allocs)
+      if (p == h->hist) p = nh;
+    (void)hipFree(h->hist);
+    h->device_bytes += (cap - h->hist_cap) * FFD_HIST_FIELDS * sizeof(double);
+  } else {
+    h->allocs.push_back(nh);
+    h->device_bytes += cap * FFD_HIST_FIELDS * sizeof(double);
+  }
+  h->hist = nh;
+  h->hist_cap = cap;
+  return FFD_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// adjoint helpers
+// ---------------------------------------------------------------------------
+struct SlotView {
+  void *U, *P, *L, *gn, *g;
+  double* x;
+};
+
+SlotView slot_view(ffd_ctx* h, char* base) {
+  const size_t nU = h->d == 2 ? 2 : 9, nP = h->d == 2 ? 3 : 6, rs = h->rsize(), m = h->m, d = h->d;
+  SlotView v;
+  v.U = base;
+  v.P = base + rs * m * nU;
+  v.L = base + rs * m * (nU + nP);
+  v.gn = base + rs * m * (nU + nP + d * d);
+  v.g = base + rs * m * (nU + nP + d * d + 1);
+  const size_t el = rs * m * h->slot_elem_entries();
+  v.x = reinterpret_cast<double*>(base + ((el + 255) / 256) * 256);
+  return v;
+}
+
+// element state and map, copied in both directions
+hipError_t copy_state(ffd_ctx* h, char* slot, bool save, hipStream_t s) {
+  const size_t nU = h->d == 2 ? 2 : 9, nP = h->d == 2 ? 3 : 6, rs = h->rsize(), m = h->m, d = h->d;
+  SlotView v = slot_view(h, slot);
+  void* live[6] = {h->U, h->P, h->L, h->gn, h->g, h->x[h->cur]};
+  void* saved[6] = {v.U, v.P, v.L, v.gn, v.g, v.x};
+  const size_t bytes[6] = {rs * m * nU, rs * m * nP, rs * m * d * d, rs * m, rs * m * (d + 1) * d,
+                           sizeof(double) * h->n * d};
+  for (int i = 0; i < 6; ++i) {
+    hipError_t e = save ? hipMemcpyAsync(saved[i], live[i], bytes[i], hipMemcpyDeviceToDevice, s)
+                        : hipMemcpyAsync(live[i], saved[i], bytes[i], hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t save_state(ffd_ctx* h, char* slot, hipStream_t s) { return copy_state(h, slot, true, s); }
+hipError_t load_state(ffd_ctx* h, char* slot, hipStream_t s) { return copy_state(h, slot, false, s); }
+
+template <int D, typename R, int E>
+void launch_adj_seed(ffd_ctx* h, const ffd_ctx::Seg& g, const void* Pbar_ext, int energy_loss, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_seed<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1,
+                     static_cast<const R*>(h->P),
+                     static_cast<const R*>(h->w), energy_loss, static_cast<const R*>(Pbar_ext), h->enew2old_d,
+                     h->Ubar, h->Pbar, h->Lbar, h->Bbar, h->wbar);
+}
+
+template <int D, typename R, int E>
+void launch_adj_local(ffd_ctx* h, const ffd_ctx::Seg& g, const SlotView& prev, const double* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_local<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1, h->T,
+                     static_cast<const R*>(h->B), h->B64, static_cast<R>(h->rho), x, static_cast<const R*>(prev.U),
+                     static_cast<const R*>(prev.P), static_cast<const R*>(prev.L), h->Ubar, h->Pbar, h->Lbar, h->Bbar,
+                     h->gadj);
+}
+
+template <int D, typename R, int E>
+void launch_adj_wstep(ffd_ctx* h, const SlotView& prev, const double* x, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_wstep<D, R>), dim3(nblk(h->m)), dim3(kBlock), 0, s, h->m, h->T, h->B64,
+                     static_cast<const R*>(h->w), static_cast<R>(h->rho), x, h->lam, static_cast<const R*>(prev.U),
+                     static_cast<const R*>(prev.P), static_cast<const R*>(prev.L), h->Ubar, h->Pbar, h->Lbar, h->Bbar,
+                     h->wbar);
+}
+
+template <int D, typename R, int E>
+void launch_adj_vbar(ffd_ctx* h, hipStream_t s) {
+  hipLaunchKernelGGL((k_adj_vbar<D, R>), dim3(nblk(h->m)), dim3(kBlock), 0, s, h->m, h->B64,
+                     static_cast<const R*>(h->w), h->Bbar, h->wbar, h->gadj);
+}
+
+#define ADJ_DISPATCH(FN, ...)                                                        \
+  do {                                                                               \
+    switch (h->d * 100 + h->prec + h->energy) {                                      \
+      case 232: FN<2, float, 0>(__VA_ARGS__); break;                                 \
+      case 233: FN<2, float, 1>(__VA_ARGS__); break;                                 \
+      case 264: FN<2, double, 0>(__VA_ARGS__); break;                                \
+      case 265: FN<2, double, 1>(__VA_ARGS__); break;                                \
+      case 332: FN<3, float, 0>(__VA_ARGS__); break;                                 \
+      case 333: FN<3, float, 1>(__VA_ARGS__); break;                                 \
+      case 364: FN<3, double, 0>(__VA_ARGS__); break;                                \
+      case 365: FN<3, double, 1>(__VA_ARGS__); break;                                \
+    }                                                                                \
+  } while (0)
+
+}  // namespace

@@ -193,3 +193,36 @@ def test_rescale_argument_and_state_errors(gpu_lib):
         g.adjoint_forward(5)
     g.init(w.x0)
     g.adjoint_forward(3)
+
+
+def test_rescaling_a_batch_matches_each_chart(gpu_lib):
+    """A batched handle of charts of both energies: rescaling events act per
+    element, so each chart of the batch follows its own oracle through two
+    events (float64, 1e-9)."""
+    import torch
+    from paper_2107_05200_amd.binding import BatchSolver
+    ws = mg.batched_charts(n_charts=5, seed_c=8, m_lo=200.0, m_hi=2000.0)
+    say(f"case: batch rescaling, m = {[w.m for w in ws]}, energies {[w.energy for w in ws]}")
+    bs = BatchSolver(ws, precision=64)
+    vo, eo = bs.layout()
+    bs.init(np.concatenate([w.x0 for w in ws]))
+    rs = []
+    for w in ws:
+        r = _oracle(w)
+        rs.append(r)
+    for n_before in (3, 4):
+        bs.iterate(n_before)
+        bs.rescale(5.0)
+        for r in rs:
+            r.iterate(n_before)
+            r.rescale(5.0)
+    bs.iterate(5)
+    st = bs.get_state()
+    torch.cuda.synchronize()
+    x, wel = host(st["map"]), host(st["Wel"])
+    worst = 0.0
+    for i, r in enumerate(rs):
+        r.iterate(5)
+        worst = max(worst, rel(x[vo[i]:vo[i + 1]], r.x), rel(wel[eo[i]:eo[i + 1]], r.wel()))
+    say(f"  worst rel err over the charts {worst:.2e}")
+    assert worst < 1e-9

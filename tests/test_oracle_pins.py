@@ -573,3 +573,34 @@ def test_rescale_keeps_the_unscaled_dual_and_refactors():
     rhs = np.asarray(r.G.T @ rr.reshape(r.m * r.d, r.d))[r.free] - r.L_FC @ r.pin_pos
     res = np.linalg.norm(r.L_FF @ x[r.free] - rhs) / np.linalg.norm(rhs)
     assert res < 1e-12
+
+
+def test_constants_the_paper_prints():
+    """tests/golden/paper_constants.txt transcribes the method's constants as
+    the paper prints them (each with its passage); the oracle uses exactly
+    these: machine epsilon of float64, the termination pair, the rescaling
+    factor and F^2 cap, the initialisation epsilons and the eigenvalue floor."""
+    import inspect
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.txt")
+    vals = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            name, expr, _ = [f.strip() for f in line.split("|")]
+            vals[name] = float(eval(expr, {"__builtins__": {}}, {"eps_m": np.finfo(np.float64).eps}))
+    assert O.EPS_M == np.finfo(np.float64).eps
+    run = inspect.signature(O.OracleSolver.run).parameters
+    assert run["eps_abs"].default == vals["eps_abs"] and run["eps_rel"].default == vals["eps_rel"]
+    assert run["rho_r"].default == vals["rescale_rho"]
+    assert inspect.signature(O.OracleSolver.rescale).parameters["rho_r"].default == vals["rescale_rho"]
+    # F^2 cap: a huge B saturates F at the cap
+    F = O.lipschitz_f(np.array([1e30]), 3, O.SD)[0]
+    assert F * F == pytest.approx(vals["lipschitz_F2_cap"], rel=1e-15)
+    F = O.lipschitz_f(np.array([1e30]), 2, O.SG)[0]
+    assert F * F == pytest.approx(vals["lipschitz_F2_cap"], rel=1e-15)
+    assert O.init_epsilon(O.SG) == pytest.approx(vals["init_eps_sg"], rel=1e-15)
+    assert O.init_epsilon(O.SD) == pytest.approx(vals["init_eps_sd"], rel=1e-15)
+    # the P-step floor: a nearly singular S gives eigenvalues raised to sqrt(eps_m)
+    S = np.diag([-1e3, -1e3, -1e3])[None]
+    P, p = O.p_step(S, np.array([1.0]), np.array([1e6]), O.SG)
+    assert np.min(p) >= vals["p_eig_floor"] * (1 - 1e-15)

@@ -23,7 +23,7 @@ __all__ = [
     "jacobians", "energy_density", "energy_of_spd_eigs", "grad_norm_sq_of_spd_eigs",
     "root_sg", "root_sd", "rot2", "rot3", "rotation_step", "p_step", "polar_init",
     "init_epsilon", "OracleSolver", "History", "HIST_FIELDS",
-    "c_l", "c_lg", "lipschitz_f", "mu_min", "rescale_rule", "rescale_schedule",
+    "c_l", "c_lg", "lipschitz_f", "mu_min", "rescale_rule", "rescale_schedule", "lambda_ratio",
 ]
 
 # Reading: the machine epsilon of the supplement is taken as the float64 one
@@ -282,7 +282,24 @@ def polar_init(J0: np.ndarray, energy: int):
 # ----------------------------------------------------------------------------
 
 HIST_FIELDS = ("e_prim", "e_dual", "E_P", "E_map", "Phi", "flips", "nonfinite",
-               "norm_GW", "norm_P", "norm_GtLam")
+               "norm_GW", "norm_P", "norm_GtLam", "max_grad_f", "max_lambda_ratio")
+
+
+def lambda_ratio(U0, L0, U1, L1):
+    """Per element, the ratio the paper plots as a proxy for gamma^(1/2) of
+    Condition "lambdabound" (caption of the figure with the UV-mapping
+    bounds): |L1 - L0| / |1/2 (L1 - L0 + U1 L1^T U1 - U0 L0^T U0)| for
+    consecutive iterates.  Reading: the figure scales Lambda by mu_i so that
+    iterates compare across rescalings; within one iteration mu_i is the same
+    on both sides and cancels, and after a rescaling event the stored scaled
+    dual is already divided by the event's factor.  A zero denominator gives
+    +inf when the numerator is positive and 0 when it is zero."""
+    tr = lambda X: np.transpose(X, (0, 2, 1))
+    num = np.sqrt(np.sum((L1 - L0) ** 2, axis=(1, 2)))
+    den = 0.5 * np.sqrt(np.sum((L1 - L0 + U1 @ tr(L1) @ U1 - U0 @ tr(L0) @ U0) ** 2, axis=(1, 2)))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = num / den
+    return np.where(den > 0, r, np.where(num > 0, np.inf, 0.0))
 
 
 @dataclass
@@ -542,10 +559,11 @@ class OracleSolver:
         P, p = p_step(S, self.w, self.mu, self.energy)
         UP = U @ P
         Lam = self.Lam + J - UP
+        ratio = float(np.max(lambda_ratio(self.U, self.Lam, U, Lam)))
         self.x_prev, self.x = self.x, x_new
         self.U, self.P, self.Lam = U, P, Lam
         self.k += 1
-        self.history.rows.append(self._diagnostics(J, J_prev, UP, p))
+        self.history.rows.append(self._diagnostics(J, J_prev, UP, p) + [ratio])
         if self.h_mode == 1:
             self.h = self._prox_h(self.P)
         return self
@@ -553,8 +571,10 @@ class OracleSolver:
     def _diagnostics(self, J, J_prev, UP, p):
         """e_prim, e_dual (eq. primaldualerror), E_P = sum w f(P), E_map = sum w f(J)
         (+inf with any det J <= 0), Phi (eq. augmentedlagrangian at the new
-        iterate), flip count, non-finite count, and the norms used by the
-        thresholds of eq. primaldualthresholds."""
+        iterate), flip count, non-finite count, the norms used by the
+        thresholds of eq. primaldualthresholds, and max_i |grad f(P_i)| (the
+        proxy for the B_i of Condition "gradf" in the figure with the UV-mapping
+        bounds)."""
         mu, w = self.mu, self.w
         e_prim = math.sqrt(np.sum((J - UP) ** 2))
         e_dual = math.sqrt(np.sum(mu[:, None, None] ** 2 * (J - J_prev) ** 2))
@@ -568,9 +588,10 @@ class OracleSolver:
                                                   - np.sum(self.Lam ** 2, axis=(1, 2)))))
         nonfinite = int(np.sum(~np.isfinite(self.Lam).all(axis=(1, 2))))
         GtLam = np.asarray(self.G.T @ self.Lam.reshape(self.m * self.d, self.d))
+        gmax = math.sqrt(float(np.max(grad_norm_sq_of_spd_eigs(p, self.energy))))
         return [e_prim, e_dual, E_P, E_map, Phi, flips, nonfinite,
                 math.sqrt(np.sum(J * J)), math.sqrt(np.sum(self.P ** 2)),
-                math.sqrt(np.sum(GtLam ** 2))]
+                math.sqrt(np.sum(GtLam ** 2)), gmax]
 
     def thresholds(self, eps_abs=1e-6, eps_rel=1e-5):
         """Primal / dual thresholds of eq. primaldualthresholds for the last

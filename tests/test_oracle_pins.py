@@ -604,3 +604,40 @@ def test_constants_the_paper_prints():
     S = np.diag([-1e3, -1e3, -1e3])[None]
     P, p = O.p_step(S, np.array([1.0]), np.array([1e6]), O.SG)
     assert np.min(p) >= vals["p_eig_floor"] * (1 - 1e-15)
+
+
+def test_diagnostic_proxies_closed_forms():
+    """The two proxies of the figure with the UV-mapping bounds.
+    max |grad f(P)|: eigenvalues p - p^-3 (SD) and p - 1/p (SG), so 0 at the
+    identity and 15/8 (SD), 3/2 (SG) at P = diag(2, 1, 1).  Lambda ratio:
+    with U = I a symmetric step gives exactly 1 (U L^T U = L), an
+    antisymmetric one +inf (the denominator vanishes; up to rounding when the
+    states themselves are symmetric), no step 0; the ratio
+    is unchanged when the step and both states are rotated by one rotation R
+    applied as U -> R U R^T, L -> R L R^T."""
+    p = np.array([[2.0, 1.0, 1.0]])
+    assert math.sqrt(O.grad_norm_sq_of_spd_eigs(p, O.SD)[0]) == pytest.approx(15 / 8, rel=1e-15)
+    assert math.sqrt(O.grad_norm_sq_of_spd_eigs(p, O.SG)[0]) == pytest.approx(3 / 2, rel=1e-15)
+    w = mg.flat_grid(6)
+    r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+    r.init(w.x0)
+    r.iterate(2)
+    assert np.all(r.history.col("max_grad_f") < 1e-12)
+    rng = np.random.default_rng(3)
+    I = np.broadcast_to(np.eye(3), (4, 3, 3))
+    L0 = rng.normal(size=(4, 3, 3))
+    S = rng.normal(size=(4, 3, 3))
+    S = S + np.transpose(S, (0, 2, 1))
+    A = rng.normal(size=(4, 3, 3))
+    A = A - np.transpose(A, (0, 2, 1))
+    L0s = L0 + np.transpose(L0, (0, 2, 1))
+    assert np.allclose(O.lambda_ratio(I, L0s, I, L0s + S), 1.0, rtol=1e-14)
+    assert np.all(O.lambda_ratio(I, L0s, I, L0s + A) > 1e12)  # 0 up to rounding in the denominator
+    assert np.all(np.isinf(O.lambda_ratio(I[:1], np.zeros((1, 3, 3)), I[:1], A[:1])))
+    assert np.all(O.lambda_ratio(I, L0, I, L0) == 0.0)
+    U0 = np.linalg.qr(rng.normal(size=(4, 3, 3)))[0]
+    U1 = np.linalg.qr(rng.normal(size=(4, 3, 3)))[0]
+    L1 = L0 + rng.normal(size=(4, 3, 3))
+    R = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+    rot = lambda X: R @ X @ R.T
+    assert np.allclose(O.lambda_ratio(rot(U0), rot(L0), rot(U1), rot(L1)), O.lambda_ratio(U0, L0, U1, L1), rtol=1e-12)

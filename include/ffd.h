@@ -112,8 +112,15 @@ typedef struct {
  *  9 norm_GtLam  |G^T Lambda^k| over all vertex rows (eq. primaldualthresholds),
  *             recorded at the check iterations of ffd_iterate_until / ffd_run,
  *             NaN elsewhere
+ * 10 max_grad_f  max_i |grad f(P_i^k)| (the proxy for B_i of Condition "gradf"
+ *             plotted with the UV-mapping bounds)
+ * 11 max_lambda_ratio  max_i |L1 - L0| / |1/2 (L1 - L0 + U1 L1^T U1 - U0 L0^T U0)|
+ *             with L0, U0 = Lambda_i, U_i before and L1, U1 after the iteration
+ *             (the proxy for gamma^(1/2) of Condition "lambdabound"; +inf where
+ *             the denominator vanishes and the numerator does not); at the check
+ *             iterations of ffd_iterate_until / ffd_run, NaN elsewhere
  * J_i = (G W^k)_i.  Iterations are numbered from 1 after ffd_init. */
-#define FFD_HIST_FIELDS 10
+#define FFD_HIST_FIELDS 12
 
 /* Host set-up: geometry (B_i, w_i), L = G^T M G, pin elimination, nested
  * dissection, FP64 multifrontal Cholesky of L_FF, then upload to the current

@@ -14,9 +14,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libffd.so")
-HIST_FIELDS = 10
+HIST_FIELDS = 12
 HIST_NAMES = ("e_prim", "e_dual", "E_P", "E_map", "Phi", "flips", "nonfinite",
-              "norm_GW", "norm_P", "norm_GtLam")
+              "norm_GW", "norm_P", "norm_GtLam", "max_grad_f", "max_lambda_ratio")
 
 STATUS = {0: "FFD_OK", -1: "FFD_ERR_INVALID_ARG", -2: "FFD_ERR_DEGENERATE_ELEMENT",
           -3: "FFD_ERR_SINGULAR_SYSTEM", -4: "FFD_ERR_NOT_FINITE", -5: "FFD_ERR_DEVICE",

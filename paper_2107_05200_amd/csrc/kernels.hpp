@@ -13,20 +13,26 @@
 namespace ffd {
 
 constexpr int kBlock = 256;      // threads per block for element / vertex kernels
-constexpr int kNumPartials = 9;  // per-block partial sums of the local step
+constexpr int kNumSums = 9;       // per-block partial sums of the local step (fields 0 .. 8)
+constexpr int kNumPartials = 11;  // ... followed by two per-block maxima (fields 9, 10)
 
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
 
-template <int NF, int BS = kBlock>
+// fixed-order block reduction: fields below NSUM are summed, the others take
+// the maximum (fmax: NaN entries are neutral)
+template <int NF, int BS = kBlock, int NSUM = NF>
 __device__ __forceinline__ void block_reduce_store(double (&v)[NF], double* __restrict out) {
   __shared__ double red[BS / 64][NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
     double x = v[f];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    for (int off = 32; off > 0; off >>= 1) {
+      const double y = __shfl_down(x, off, 64);
+      x = f < NSUM ? x + y : fmax(x, y);
+    }
     v[f] = x;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -36,11 +42,22 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NF], double* __re
   }
   __syncthreads();
   if (threadIdx.x < NF) {
-    double s = 0.0;
+    const bool sum = static_cast<int>(threadIdx.x) < NSUM;
+    double s = sum ? 0.0 : red[0][threadIdx.x];
 #pragma unroll
-    for (int wv = 0; wv < BS / 64; ++wv) s += red[wv][threadIdx.x];
+    for (int wv = sum ? 0 : 1; wv < BS / 64; ++wv) s = sum ? s + red[wv][threadIdx.x] : fmax(s, red[wv][threadIdx.x]);
     out[threadIdx.x] = s;
   }
+}
+
+// the local step's partials: sums, then maxima; a NaN is the neutral value of a maximum
+__device__ __forceinline__ void partials_init(double (&v)[kNumPartials]) {
+#pragma unroll
+  for (int f = 0; f < kNumPartials; ++f) v[f] = f < kNumSums ? 0.0 : __longlong_as_double(0x7ff8000000000000LL);
+}
+__device__ __forceinline__ void partials_add(double (&v)[kNumPartials], const double* __restrict p) {
+#pragma unroll
+  for (int f = 0; f < kNumPartials; ++f) v[f] = f < kNumSums ? v[f] + p[f] : fmax(v[f], p[f]);
 }
 
 // element state sizes: U (2D: cos, sin; 3D: 9), P (sym: 3 / 6), Lambda d*d
@@ -195,6 +212,34 @@ template <int D, typename R>
 __device__ __forceinline__ void sym_eig(R S[D][D], R q[D], R V[D][D]) {
   if constexpr (D == 2) dm::eig2(S[0][0], S[0][1], S[1][1], q, V);
   else dm::eig3(S, q, V);
+}
+
+// The Lambda-ratio proxy of the figure with the UV-mapping bounds for one
+// element: |L1 - L0| / |1/2 (L1 - L0 + U1 L1^T U1 - U0 L0^T U0)|, with
+// |L1 - L0|^2 = num2 (the element's primal residual); +inf for a zero
+// denominator with a positive numerator, 0 when both vanish.
+template <int D, typename R>
+__device__ __forceinline__ double lambda_ratio(const R (&U0)[D][D], const R (&L0)[D][D], const R (&U1)[D][D],
+                                               const R (&L1)[D][D], double num2) {
+  double den2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      // (U L^T U)[a][b] = sum_ij U[a][i] L[j][i] U[j][b]
+      double t1 = 0.0, t0 = 0.0;
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          t1 += static_cast<double>(U1[a][i]) * static_cast<double>(L1[j][i]) * static_cast<double>(U1[j][b]);
+          t0 += static_cast<double>(U0[a][i]) * static_cast<double>(L0[j][i]) * static_cast<double>(U0[j][b]);
+        }
+      const double q = 0.5 * ((static_cast<double>(L1[a][b]) - static_cast<double>(L0[a][b])) + t1 - t0);
+      den2 += q * q;
+    }
+  if (den2 > 0.0) return sqrt(num2 / den2);
+  return num2 > 0.0 ? __longlong_as_double(0x7ff0000000000000LL) : 0.0;
 }
 
 // corner vectors of G^T r: g[c][k] = sum_a C[a][c] r[a][k], C[:,0] = -sum_j B[:,j]
@@ -827,8 +872,7 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
                                                   double* __restrict partials, R* __restrict glam) {
   const int64_t e = e0 + static_cast<int64_t>(blockIdx.x) * BS + threadIdx.x;
   double part[kNumPartials];
-#pragma unroll
-  for (int f = 0; f < kNumPartials; ++f) part[f] = 0.0;
+  partials_init(part);
   if (e < e1) {
     const R we = w[e];
     const R rho = rho_e ? rho_e[e] : rho_u;  // mu_e / w_e (per element after a rescaling)
@@ -894,6 +938,18 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
     load_P<D, R>(P, m, e, Pm);
 #pragma unroll
     for (int i = 0; i < D * D; ++i) L[i / D][i % D] = Lam[i * m + e];
+    // diagnostic iterations keep U^k and Lambda^k for the Lambda-ratio proxy
+    R Uo[D][D], Lo[D][D];
+    if (glam) {
+      if (D == 2 || h_mode == 1) {
+#pragma unroll
+        for (int i = 0; i < D * D; ++i) Uo[i / D][i % D] = Ur[i / D][i % D];
+      } else {
+        load_U<D, R>(U, m, e, Uo);
+      }
+#pragma unroll
+      for (int i = 0; i < D * D; ++i) Lo[i / D][i % D] = L[i / D][i % D];
+    }
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -981,13 +1037,15 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
       gn += gj * gj;
     }
     if (h_mode == 1 || store_u) gnorm2[e] = gn;
+    part[9] = static_cast<double>(gn);  // max |grad f(P)|^2 (proxy for B_i of Condition "gradf")
+    if (glam) part[10] = lambda_ratio<D, R>(Uo, Lo, Ur, L, ep);
     part[0] = ep;
     part[2] = wd * fP;
     part[4] = wd * fP + 0.5 * mud * (res2 - lam2);
     part[6] = finite ? 0.0 : 1.0;
     part[8] = p2;
   }
-  block_reduce_store<kNumPartials, BS>(part, partials + static_cast<int64_t>(blockIdx.x) * kNumPartials);
+  block_reduce_store<kNumPartials, BS, kNumSums>(part, partials + static_cast<int64_t>(blockIdx.x) * kNumPartials);
 }
 
 // first stage of the partial-sum reduction when the local step ran many small
@@ -1000,12 +1058,9 @@ __global__ __launch_bounds__(kBlock) void k_partials_reduce(const double* __rest
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kFinalizeRows;
   const int64_t r1 = r0 + kFinalizeRows < nb ? r0 + kFinalizeRows : nb;
   double v[kNumPartials];
-#pragma unroll
-  for (int f = 0; f < kNumPartials; ++f) v[f] = 0.0;
-  for (int64_t bi = r0 + threadIdx.x; bi < r1; bi += kBlock)
-#pragma unroll
-    for (int f = 0; f < kNumPartials; ++f) v[f] += partials[bi * kNumPartials + f];
-  block_reduce_store<kNumPartials>(v, out + static_cast<int64_t>(blockIdx.x) * kNumPartials);
+  partials_init(v);
+  for (int64_t bi = r0 + threadIdx.x; bi < r1; bi += kBlock) partials_add(v, partials + bi * kNumPartials);
+  block_reduce_store<kNumPartials, kBlock, kNumSums>(v, out + static_cast<int64_t>(blockIdx.x) * kNumPartials);
 }
 
 // fixed-order reduction of the block partials into one history record: at
@@ -1015,13 +1070,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict pa
                                                      double* __restrict hist, int64_t* __restrict k_dev,
                                                      int fields) {
   double v[kNumPartials];
-#pragma unroll
-  for (int f = 0; f < kNumPartials; ++f) v[f] = 0.0;
-  for (int64_t bi = threadIdx.x; bi < nb; bi += kBlock)
-#pragma unroll
-    for (int f = 0; f < kNumPartials; ++f) v[f] += partials[bi * kNumPartials + f];
+  partials_init(v);
+  for (int64_t bi = threadIdx.x; bi < nb; bi += kBlock) partials_add(v, partials + bi * kNumPartials);
   __shared__ double out[kNumPartials];
-  block_reduce_store<kNumPartials>(v, out);
+  block_reduce_store<kNumPartials, kBlock, kNumSums>(v, out);
   __syncthreads();
   if (threadIdx.x == 0) {
     if (k_dev) hist += *k_dev * fields;
@@ -1036,6 +1088,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict pa
     hist[7] = sqrt(out[7]);
     hist[8] = sqrt(out[8]);
     hist[9] = __longlong_as_double(0x7ff8000000000000LL);
+    hist[10] = sqrt(out[9]);
+    hist[11] = out[10];  // NaN unless the iteration recorded the diagnostics
     if (k_dev) *k_dev += 1;
   }
 }

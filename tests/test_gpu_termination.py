@@ -81,3 +81,41 @@ def test_iterate_until_argument_errors(gpu_lib):
             g.iterate_until(**args)
     done, conv = g.iterate_until(0)
     assert done == 0 and not conv
+
+
+@pytest.mark.parametrize("case", ["height_field_fp64", "height_field_fp64_h1", "cube_fp64", "sphere_cap_sg_fp32"])
+def test_bound_proxies_match_oracle(gpu_lib, case):
+    """The two proxies of the figure with the UV-mapping bounds:
+    max |grad f(P_i)| at every iteration (field 10) and the largest Lambda
+    ratio at the check iterations (field 11, NaN elsewhere), against the
+    oracle's history.  Float64: 1e-9 and 1e-6 relative; float32: 1e-4 on the
+    gradient and a finite, positive ratio."""
+    if case.startswith("height_field"):
+        w, prec, h_mode = mg.height_field_uv(), 64, 1 if case.endswith("h1") else 0
+    elif case == "cube_fp64":
+        w, prec, h_mode = mg.twisted_cube(6), 64, 0
+    else:
+        w, prec, h_mode = mg.sphere_cap_uv(R=15), 32, 0
+    every, K = 3, 15
+    say(f"case: bound proxies {case}")
+    from paper_2107_05200_amd.binding import Solver
+    g = Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=prec, h_mode=h_mode)
+    g.init(w.x0)
+    done, conv = g.iterate_until(K, check_every=every, eps_abs=0.0, eps_rel=0.0)
+    assert done == K and not conv
+    h = g.history()
+    r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, h_mode=h_mode)
+    r.init(w.x0)
+    r.iterate(K)
+    hr = r.history.array()
+    eg = np.max(np.abs(h[:, 10] - hr[:, 10]) / hr[:, 10])
+    checks = [k for k in range(K) if (k + 1) % every == 0]
+    er = max(abs(h[k, 11] - hr[k, 11]) / hr[k, 11] for k in checks)
+    say(f"  max |grad f| rel err {eg:.2e}; Lambda ratio rel err {er:.2e} "
+        f"(values {[round(hr[k, 11], 3) for k in checks]})")
+    assert eg < (1e-9 if prec == 64 else 1e-4)
+    if prec == 64:
+        assert er < 1e-6
+    else:
+        assert all(np.isfinite(h[k, 11]) and h[k, 11] > 0 for k in checks)
+    assert all(np.isnan(h[k, 11]) for k in range(K) if k not in checks)

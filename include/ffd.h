@@ -253,6 +253,14 @@ ffd_status ffd_iterate_until(ffd_handle h, int32_t max_iter, int32_t check_every
  * before the first iteration, FFD_ERR_INVALID_ARG for rho_r <= 2. */
 ffd_status ffd_rescale(ffd_handle h, double rho_r, void* stream);
 
+/* Where ffd_rescale refactorises: device = 1 (default when rocBLAS and
+ * rocSOLVER load) factorises the large top fronts of the nested-dissection
+ * tree on the device (assembly kernels plus rocSOLVER potrf / trtri and
+ * rocBLAS trsm / syrk / trmm) and the subtrees below them on the host;
+ * device = 0 factorises everything on the host.  Results agree to rounding.
+ * Errors: FFD_ERR_STATE for device = 1 without the libraries. */
+ffd_status ffd_set_refactor_mode(ffd_handle h, int32_t device);
+
 /* Algorithm 2: up to max_iter iterations from the current state with
  * rescaling events (rescale_rho > 2; 0 = none) after iterations 1..5 of the
  * run and then every 5 (3/2)^p iterations (p = past events, rounded half up),

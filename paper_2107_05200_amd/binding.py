@@ -71,6 +71,7 @@ _PROTOS = {
                                     C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ffd_rescale": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
     "ffd_create_constrained": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ffd_set_refactor_mode": (C.c_int, [C.c_void_p, C.c_int32]),
     "ffd_set_constraint_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ffd_tutte_map": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "ffd_run": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_int32,
@@ -273,6 +274,11 @@ class Solver:
         cs = self._dev(c, torch.float64).reshape(self.n_constraints, self.d)
         _check(self.lib.ffd_set_constraint_rhs(self.h, C.c_void_p(cs.data_ptr()), _stream(stream)))
         self._keep_rhs = cs
+        return self
+
+    def set_refactor_mode(self, device: bool):
+        """Refactorise the top fronts on the device (True) or on the host."""
+        _check(self.lib.ffd_set_refactor_mode(self.h, int(bool(device))))
         return self
 
     def rescale(self, rho_r: float = 5.0, stream=None):

@@ -363,6 +363,13 @@ ffd_status ffd_iterate_until(ffd_handle h, int32_t max_iter, int32_t check_every
   return FFD_OK;
 }
 
+ffd_status ffd_set_refactor_mode(ffd_handle h, int32_t device) {
+  if (!h) return fail(FFD_ERR_INVALID_ARG, "NULL handle");
+  if (device && !dense_lib().ok) return fail(FFD_ERR_STATE, "rocBLAS / rocSOLVER not available");
+  h->device_refactor = device != 0;
+  return FFD_OK;
+}
+
 ffd_status ffd_rescale(ffd_handle h, double rho_r, void* stream) {
   if (!h) return fail(FFD_ERR_INVALID_ARG, "NULL handle");
   if (!h->initialized || h->k < 1) return fail(FFD_ERR_STATE, "ffd_rescale needs an iteration after ffd_init");

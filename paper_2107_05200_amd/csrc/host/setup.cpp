@@ -840,7 +840,41 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
     while (!S.children[lo].empty()) lo = *std::min_element(S.children[lo].begin(), S.children[lo].end());
     for (int i = lo; i <= root; ++i) factor_node(i);
   }
-  for (int32_t i : top) factor_node(i);  // postorder: children before parents
+  if (in.device_top && !in.selfcheck) {
+    // gather what the device needs to assemble each front; no numeric work
+    for (int32_t i : top) {
+      const SolveNode& N = S.nodes[i];
+      const int c = N.c, nf = c + N.r;
+      const int32_t* sb = strct[i].data();
+      auto pos = [&](int32_t g) -> int64_t {
+        return g < N.first + c ? g - N.first : c + (std::lower_bound(sb, sb + N.r, g) - sb);
+      };
+      TopNode T;
+      T.node = i;
+      for (int j = 0; j < c; ++j) {
+        const int32_t gv = N.first + j;
+        const int32_t v = S.vnew2old[gv];
+        for (int64_t k = Lptr[v]; k < Lptr[v + 1]; ++k) {
+          const int32_t gu = S.vold2new[Lcol[k]];
+          if (gu >= S.nF || gu < gv) continue;
+          T.lidx.push_back(pos(gu) + static_cast<int64_t>(j) * nf);
+          T.lval.push_back(Lval[k]);
+        }
+      }
+      for (int32_t ch : S.children[i]) {
+        TopChild K;
+        K.node = ch;
+        K.host = small[ch] != 0;
+        K.rel.resize(S.nodes[ch].r);
+        for (int q = 0; q < S.nodes[ch].r; ++q) K.rel[q] = static_cast<int32_t>(pos(strct[ch][q]));
+        if (K.host) K.upd = std::move(upd[ch]);
+        T.kids.push_back(std::move(K));
+      }
+      S.top.push_back(std::move(T));
+    }
+  } else {
+    for (int32_t i : top) factor_node(i);  // postorder: children before parents
+  }
   for (int i = 0; i < nn; ++i)
     if (fail[i]) {
       err = "the W-step matrix is not positive definite (check the pins)";

@@ -42,6 +42,7 @@ struct SetupInput {
   int leaf_size = 0;             // 0: automatic
   const int8_t* elem_energy = nullptr;  // optional per-element energy (0 or 1), m entries
   bool selfcheck = false;        // solve with the panels on the host and record the residual
+  bool device_top = false;       // leave the nodes above the host subtrees to the device (Setup::top)
 };
 
 // One node of the nested-dissection tree; its columns are the contiguous free
@@ -53,6 +54,22 @@ struct SolveNode {
   int64_t uoff = 0;  // first row of this node's update vector in the update buffer
   int64_t soff = 0;  // offset into struct_idx
   int64_t poff = 0;  // offset into pull_ptr (c + r + 1 entries)
+};
+
+// A node above the host-factorised subtrees whose front the device assembles
+// and factorises (SetupInput::device_top): the entries of L in its columns and
+// the update matrices of its children.
+struct TopChild {
+  int32_t node = 0;
+  bool host = false;          // factorised on the host: its update matrix is upd
+  std::vector<int32_t> rel;   // front position of each of the child's update rows
+  std::vector<double> upd;    // r x r column-major, lower triangle valid (host children)
+};
+struct TopNode {
+  int32_t node = 0;
+  std::vector<int64_t> lidx;  // front entries p + j * (c + r), lower part, from L
+  std::vector<double> lval;
+  std::vector<TopChild> kids;
 };
 
 struct Setup {
@@ -90,6 +107,7 @@ struct Setup {
   std::vector<int32_t> struct_idx;
   std::vector<int32_t> pull_ptr, pull_idx;
   std::vector<std::vector<int32_t>> level_nodes;
+  std::vector<TopNode> top;     // device_top: the nodes left for the device, in postorder (panels zero)
   int64_t ubuf_rows = 0;
   // statistics
   double t_geometry = 0, t_order = 0, t_symbolic = 0, t_numeric = 0;

@@ -1390,6 +1390,53 @@ __global__ __launch_bounds__(kBlock) void k_con_gram(int64_t nF, int64_t ncon, c
   S[t] = acc;
 }
 
+// ---------------------------------------------------------------------------
+// Device factorisation of the top fronts (refactorisation after a rescaling
+// event): assembly of a front from L and its children's update matrices, a
+// lower-triangle copy, and the write of the node's panels [Linv; -M] into
+// both device copies.  The dense steps between them are library calls.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_front_scatter(int64_t n, const int64_t* __restrict idx,
+                                                          const double* __restrict val, double* __restrict F) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) F[idx[i]] += val[i];  // distinct entries
+}
+
+// F[rel[i] + rel[j] nf] += U[i + j ldu] for i >= j (lower triangle of one child)
+__global__ __launch_bounds__(kBlock) void k_front_extend(int64_t rc, const int32_t* __restrict rel,
+                                                         const double* __restrict U, int64_t ldu,
+                                                         double* __restrict F, int64_t nf) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= rc * rc) return;
+  const int64_t i = t % rc, j = t / rc;
+  if (i < j) return;
+  F[rel[i] + static_cast<int64_t>(rel[j]) * nf] += U[i + j * ldu];
+}
+
+// B = lower triangle of the n x n block A (zeros above the diagonal)
+__global__ __launch_bounds__(kBlock) void k_lower_copy(int64_t n, const double* __restrict A, int64_t lda,
+                                                       double* __restrict B, int64_t ldb) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= n * n) return;
+  const int64_t i = t % n, j = t / n;
+  B[i + j * ldb] = i >= j ? A[i + j * lda] : 0.0;
+}
+
+// panel entry (p, j) of [Linv; -M] into the column-major (ld ldc) and the
+// row-major (ld ldr) copies at offset pf
+__global__ __launch_bounds__(kBlock) void k_front_panels(int64_t c, int64_t r, const double* __restrict Linv,
+                                                         const double* __restrict M, int64_t pf,
+                                                         double* __restrict Pcol, int64_t ldc,
+                                                         double* __restrict Prow, int64_t ldr) {
+  const int64_t nf = c + r;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= nf * c) return;
+  const int64_t p = t % nf, j = t / nf;
+  const double v = p < c ? (p >= j ? Linv[p + j * c] : 0.0) : -M[(p - c) + j * r];
+  Pcol[pf + p + j * ldc] = v;
+  Prow[pf + j + p * ldr] = v;
+}
+
 // right-hand side of a solve whose only data are the fixed rows: b_F = -L_FC x_C
 // (the minimiser of a quadratic energy with fixed vertices); rows >= nF copy
 // the fixed positions into x

@@ -6,6 +6,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>  // types only: the library is loaded on first use
 
 #include <algorithm>
 #include <chrono>
@@ -137,6 +138,10 @@ struct ffd_ctx {
   int32_t *con_col = nullptr, *cont_rows = nullptr, *cont_ptr = nullptr, *cont_con = nullptr;
   double *con_val = nullptr, *cont_val = nullptr, *con_c = nullptr, *con_cp = nullptr, *con_t = nullptr;
   double *con_lam = nullptr, *con_Z = nullptr, *con_Sinv = nullptr, *con_tmp = nullptr;
+  // dense-library handle of the device refactorisation (created on first use)
+  bool device_refactor = true;  // factorise the top fronts of a refactorisation on the device
+  rocblas_handle blas = nullptr;
+  rocblas_status (*blas_destroy)(rocblas_handle) = nullptr;
   std::vector<LevelCfg> cfg_fwd, cfg_bwd;  // per-level launch configuration of both solve passes
   // The forest below level solve_top is split into solve_groups groups of
   // whole subtrees, each solved on its own stream (group 0 on the caller's);
@@ -201,6 +206,7 @@ struct ffd_ctx {
         if (e) (void)hipEventDestroy(e);
     }
     for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
+    if (blas && blas_destroy) (void)blas_destroy(blas);
     for (void* p : allocs) (void)hipFree(p);
   }
 };

@@ -28,6 +28,7 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
   in.leaf_size = opt.leaf_size;
   in.elem_energy = elem_energy.empty() ? nullptr : elem_energy.data();
   in.tutte = tutte;
+  in.device_top = dense_lib().ok;  // the large top fronts are factorised on the device
   if (con && con->n_rows > 0) {
     in.n_con = con->n_rows;
     in.con_ptr = con->row_ptr;
@@ -199,6 +200,10 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
   }
   UP(hipDeviceSynchronize());
 #undef UP
+  if (in.device_top) {
+    const ffd_status fst = device_factor_top(h, S, nullptr);
+    if (fst != FFD_OK) return cleanup(fst);
+  }
   if (h->ncon > 0) {
     const ffd_status cst = prepare_constraints(h, nullptr);
     if (cst != FFD_OK) return cleanup(cst);

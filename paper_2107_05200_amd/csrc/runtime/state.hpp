@@ -3,7 +3,7 @@
 // translation unit capi.hip.
 #pragma once
 
-#include "schedule.hpp"
+#include "devfactor.hpp"
 
 namespace {
 
@@ -37,6 +37,8 @@ ffd_status refactor(ffd_ctx* h, const std::vector<double>* mu_dev_order, hipStre
     for (int64_t e = 0; e < h->m; ++e) mu_in[h->enew2old_h[e]] = (*mu_dev_order)[e];
     in.mu_elem = mu_in.data();
   }
+  // the top fronts on the device when the dense libraries load
+  in.device_top = h->device_refactor && dense_lib().ok;
   Setup S;
   std::string err;
   const int st = build_setup(in, S, err);
@@ -61,6 +63,10 @@ ffd_status refactor(ffd_ctx* h, const std::vector<double>* mu_dev_order, hipStre
   if (!S.lcf_val.empty())
     HIP_TRY(hipMemcpyAsync(h->lcf_val, S.lcf_val.data(), S.lcf_val.size() * sizeof(double), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (in.device_top) {
+    const ffd_status st2 = device_factor_top(h, S, s);
+    if (st2 != FFD_OK) return st2;
+  }
   if (h->ncon > 0) {
     h->con_gamma = S.con_gamma;
     h->graph_valid = false;  // gamma is a kernel argument

@@ -226,3 +226,28 @@ def test_rescaling_a_batch_matches_each_chart(gpu_lib):
         worst = max(worst, rel(x[vo[i]:vo[i + 1]], r.x), rel(wel[eo[i]:eo[i + 1]], r.wel()))
     say(f"  worst rel err over the charts {worst:.2e}")
     assert worst < 1e-9
+
+
+@pytest.mark.parametrize("case", ["cube20_fp64", "sphere_cap_R60_fp64"])
+def test_device_refactorisation_matches_host(gpu_lib, case):
+    """Refactorisation with the top fronts on the device (rocSOLVER / rocBLAS)
+    and entirely on the host give the same iterations to rounding (1e-11)
+    through two rescaling events, and both follow the oracle."""
+    import torch
+    w = mg.twisted_cube(20) if case.startswith("cube") else mg.sphere_cap_uv(R=60)
+    say(f"case: device vs host refactorisation {case} m={w.m}")
+    states = []
+    for device in (True, False):
+        g = _solver(w, 64)
+        g.set_refactor_mode(device)
+        g.init(w.x0)
+        for n_before in (3, 4):
+            g.iterate(n_before)
+            g.rescale(5.0)
+        g.iterate(5)
+        st = g.get_state()
+        torch.cuda.synchronize()
+        states.append({k: host(v) for k, v in st.items()})
+    e = max(rel(states[0][k], states[1][k]) for k in ("map", "Wel", "Lam"))
+    say(f"  device vs host rel diff {e:.2e}")
+    assert e < 1e-11

@@ -821,7 +821,9 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
   for (int i = 0; i < nn; ++i)
     if (parent[i] < 0) total += work[i];
   const int nth = std::max(1, omp_get_max_threads());
-  const double cut = total / (8.0 * nth);
+  // with the top fronts on the device a finer cut balances the host part better
+  const bool dev_top = in.device_top && !in.selfcheck;
+  const double cut = total / ((dev_top ? 64.0 : 8.0) * nth);
   // a node is in the parallel part if its subtree work is below the cut; the
   // parallel subtrees are the maximal such subtrees
   std::vector<uint8_t> small(nn, 0);
@@ -840,7 +842,7 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
     while (!S.children[lo].empty()) lo = *std::min_element(S.children[lo].begin(), S.children[lo].end());
     for (int i = lo; i <= root; ++i) factor_node(i);
   }
-  if (in.device_top && !in.selfcheck) {
+  if (dev_top) {
     // gather what the device needs to assemble each front; no numeric work
     for (int32_t i : top) {
       const SolveNode& N = S.nodes[i];
@@ -1035,8 +1037,7 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
   return OK;
 }
 
-int64_t build_device_panels(const Setup& S, std::vector<double>& prow, std::vector<double>& pcol,
-                            std::vector<int64_t>& off) {
+int64_t device_panel_offsets(const Setup& S, std::vector<int64_t>& off) {
   const size_t nn = S.nodes.size();
   off.assign(nn, 0);
   int64_t tot = 0;
@@ -1047,15 +1048,34 @@ int64_t build_device_panels(const Setup& S, std::vector<double>& prow, std::vect
     tot += std::max(nf * ldr, c * ldc);
     tot = (tot + 1) & ~int64_t(1);
   }
-  prow.assign(tot, 0.0);
-  pcol.assign(tot, 0.0);
+  return tot;
+}
+
+int64_t build_host_panels(const Setup& S, const std::vector<int64_t>& off, int64_t tot, std::vector<int64_t>& coff,
+                          std::unique_ptr<double[]>& prow, std::unique_ptr<double[]>& pcol) {
+  const size_t nn = S.nodes.size();
+  std::vector<uint8_t> skip(nn, 0);
+  for (const TopNode& T : S.top) skip[T.node] = 1;
+  coff.assign(nn, -1);
+  int64_t len = 0;
+  for (size_t i = 0; i < nn; ++i) {
+    if (skip[i]) continue;
+    coff[i] = len;
+    len += (i + 1 < nn ? off[i + 1] : tot) - off[i];
+  }
+  prow.reset(new double[std::max<int64_t>(len, 1)]);
+  pcol.reset(new double[std::max<int64_t>(len, 1)]);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t i = 0; i < static_cast<int64_t>(nn); ++i) {
+    if (skip[i]) continue;
     const int64_t c = S.nodes[i].c, nf = S.nodes[i].c + S.nodes[i].r;
     const int64_t ldr = (c + 1) & ~int64_t(1), ldc = (nf + 1) & ~int64_t(1);
+    const int64_t seg = (i + 1 < static_cast<int64_t>(nn) ? off[i + 1] : tot) - off[i];
+    double* R = prow.get() + coff[i];
+    double* Cc = pcol.get() + coff[i];
+    std::fill(R, R + seg, 0.0);
+    std::fill(Cc, Cc + seg, 0.0);
     const double* src = S.panel_f.data() + S.nodes[i].pf;  // column-major, ld = nf
-    double* R = prow.data() + off[i];
-    double* Cc = pcol.data() + off[i];
     for (int64_t j = 0; j < c; ++j)
       for (int64_t p = 0; p < nf; ++p) {
         const double v = src[p + j * nf];
@@ -1063,7 +1083,7 @@ int64_t build_device_panels(const Setup& S, std::vector<double>& prow, std::vect
         Cc[j * ldc + p] = v;
       }
   }
-  return tot;
+  return len;
 }
 
 }  // namespace ffd

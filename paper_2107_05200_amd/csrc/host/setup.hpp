@@ -5,6 +5,7 @@
 // read (CSR of D^T, level schedule, extend-add pull lists).
 #pragma once
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -122,10 +123,18 @@ int build_setup(const SetupInput& in, Setup& out, std::string& err);
 
 // Device panel copies: for node s with c columns and nf = c + r rows, a
 // row-major copy (row length c rounded up to even) and a column-major copy
-// (column length nf rounded up to even), both at offset off[s] (even), padding
-// zero.  Returns the total length of each copy.
-int64_t build_device_panels(const Setup& S, std::vector<double>& prow, std::vector<double>& pcol,
-                            std::vector<int64_t>& off);
+// (column length nf rounded up to even), both at offset off[s] (even),
+// padding zero.  device_panel_offsets fills off and returns the length of
+// each copy.
+int64_t device_panel_offsets(const Setup& S, std::vector<int64_t>& off);
+
+// Compact host copies of the panels of the nodes not in S.top (off, tot from
+// device_panel_offsets): node s's segment of each copy (its device layout,
+// padding zero) at coff[s] (-1 for top nodes); runs of consecutive such
+// nodes are contiguous both here and on the device.  Returns the compact
+// length (the arrays are allocated here).
+int64_t build_host_panels(const Setup& S, const std::vector<int64_t>& off, int64_t tot, std::vector<int64_t>& coff,
+                          std::unique_ptr<double[]>& prow, std::unique_ptr<double[]>& pcol);
 
 // Element geometry only (B_i = Dm_i^{-T}, w_i) in the input element order.
 int element_geometry(int d, int din, int64_t m, const double* V, int64_t n, const int32_t* T,

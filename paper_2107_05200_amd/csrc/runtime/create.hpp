@@ -160,14 +160,15 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
   UP(upload(h, &h->lcf_val, S.lcf_val));
   UP(h->alloc(&h->hist_scratch, FFD_HIST_FIELDS));
   {
-    std::vector<double> prow, pcol;
     std::vector<int64_t> poff;
-    build_device_panels(S, prow, pcol, poff);
+    const int64_t ptot = device_panel_offsets(S, poff);
+    UP(h->alloc(&h->Prow, static_cast<size_t>(ptot)));
+    UP(h->alloc(&h->Pcol, static_cast<size_t>(ptot)));
+    UP(hipMemset(h->Prow, 0, static_cast<size_t>(ptot) * sizeof(double)));
+    UP(hipMemset(h->Pcol, 0, static_cast<size_t>(ptot) * sizeof(double)));
+    const ffd_status pst = upload_host_panels(h, S, poff, ptot, nullptr);
+    if (pst != FFD_OK) return cleanup(pst);
     std::vector<double>().swap(S.panel_f);
-    UP(upload(h, &h->Prow, prow));
-    std::vector<double>().swap(prow);
-    UP(upload(h, &h->Pcol, pcol));
-    std::vector<double>().swap(pcol);
     h->hpoff = poff;
     h->hnodes = S.nodes;
     h->hlevels = S.level_nodes;

@@ -68,6 +68,31 @@ struct DevScratch {
   }
 };
 
+// The host-built panels (every node but the top fronts) into both device
+// copies, one copy per run of consecutive nodes.  Synchronous.
+ffd_status upload_host_panels(ffd_ctx* h, const Setup& S, const std::vector<int64_t>& off, int64_t tot,
+                              hipStream_t s) {
+  std::vector<int64_t> coff;
+  std::unique_ptr<double[]> prow, pcol;
+  build_host_panels(S, off, tot, coff, prow, pcol);
+  const size_t nn = S.nodes.size();
+  for (size_t i = 0; i < nn;) {
+    if (coff[i] < 0) {
+      ++i;
+      continue;
+    }
+    size_t j = i;
+    while (j + 1 < nn && coff[j + 1] >= 0) ++j;
+    const int64_t end = j + 1 < nn ? off[j + 1] : tot;
+    const size_t bytes = static_cast<size_t>(end - off[i]) * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(h->Prow + off[i], prow.get() + coff[i], bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->Pcol + off[i], pcol.get() + coff[i], bytes, hipMemcpyHostToDevice, s));
+    i = j + 1;
+  }
+  HIP_TRY(hipStreamSynchronize(s));  // the host copies are freed on return
+  return FFD_OK;
+}
+
 #define BLAS_TRY(expr)                                                                   \
   do {                                                                                   \
     if ((expr) != rocblas_status_success) return fail(FFD_ERR_DEVICE, "dense library call failed: " #expr); \

@@ -47,17 +47,18 @@ ffd_status refactor(ffd_ctx* h, const std::vector<double>* mu_dev_order, hipStre
               S.lcf_val.size() == h->n_lcf_val && S.panel_entries == h->info.panel_entries;
   for (size_t i = 0; same && i < S.nodes.size(); ++i)
     same = S.nodes[i].first == h->hnodes[i].first && S.nodes[i].c == h->hnodes[i].c && S.nodes[i].r == h->hnodes[i].r;
-  std::vector<double> prow, pcol;
   std::vector<int64_t> poff;
+  int64_t ptot = 0;
   if (same) {
-    build_device_panels(S, prow, pcol, poff);
+    ptot = device_panel_offsets(S, poff);
     same = poff == h->hpoff;
   }
   if (!same) return fail(FFD_ERR_STATE, "the factor structure changed on refactorisation");
-  // on the caller's stream, after its pending work; the host vectors live
-  // until the stream has drained
-  HIP_TRY(hipMemcpyAsync(h->Prow, prow.data(), prow.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(h->Pcol, pcol.data(), pcol.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  // on the caller's stream, after its pending work; every node's segment is
+  // rewritten (the top fronts by the device below), padding included
+  HIP_TRY(hipStreamSynchronize(s));
+  const ffd_status pst = upload_host_panels(h, S, poff, ptot, s);
+  if (pst != FFD_OK) return pst;
   if (!S.pin_val.empty())
     HIP_TRY(hipMemcpyAsync(h->pin_val, S.pin_val.data(), S.pin_val.size() * sizeof(double), hipMemcpyHostToDevice, s));
   if (!S.lcf_val.empty())

@@ -29,8 +29,8 @@ FP32_PEAK_TFLOPS = 78.6  # no packed FP32: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 # hash of the kernel sources they were measured on: a changed kernel reports
 # no traffic until it is measured again.
 MEASURED_TRAFFIC = {
-    "38a2290778fb321f": {"solve": 3203.4e6, "local": 527.0e6,
-                         "local_flop_per_elem": 2266.1, "local_valu_per_wave": 2689.2},
+    "e4f60063383c88c9": {"solve": 3259.9e6, "local": 527.1e6,
+                         "local_flop_per_elem": 2282.0, "local_valu_per_wave": 2689.1},
 }
 
 

@@ -555,6 +555,24 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
 
   // ---- ordering -------------------------------------------------------------
   t0 = now();
+  int nn = 0;                                 // tree nodes
+  std::vector<std::vector<int32_t>> strct;    // row structure below each node's diagonal block
+  int64_t pf = 0;                             // panel entries
+  if (in.structure) {
+    // the structure of an earlier set-up (it depends on the pattern only)
+    const Setup& P = *in.structure;
+    S.vnew2old = P.vnew2old;
+    S.vold2new = P.vold2new;
+    S.nodes = P.nodes;
+    S.children = P.children;
+    S.struct_idx = P.struct_idx;
+    S.panel_entries = P.panel_entries;
+    nn = static_cast<int>(S.nodes.size());
+    strct.resize(nn);
+    for (int i = 0; i < nn; ++i)
+      strct[i].assign(S.struct_idx.begin() + S.nodes[i].soff, S.struct_idx.begin() + S.nodes[i].soff + S.nodes[i].r);
+    pf = S.panel_entries;
+  } else {
   std::vector<int64_t> aptr(n + 1, 0);
   std::vector<int32_t> adjv;
   adjv.reserve(Lptr[n]);
@@ -600,7 +618,7 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
       roots.insert(roots.end(), r.begin(), r.end());
     }
   }
-  const int nn = static_cast<int>(nd.cols.size());
+  nn = static_cast<int>(nd.cols.size());
   // postorder numbering
   S.vnew2old.assign(n, -1);
   S.vold2new.assign(n, -1);
@@ -648,7 +666,7 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
 
   // ---- symbolic ---------------------------------------------------------------
   t0 = now();
-  std::vector<std::vector<int32_t>> strct(nn);
+  strct.assign(nn, {});
   for (int i = 0; i < nn; ++i) {
     SolveNode& N = S.nodes[i];
     const int32_t last = N.first + N.c - 1;
@@ -671,7 +689,8 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
     for (int32_t ch : S.children[i]) lvl = std::max(lvl, S.nodes[ch].level + 1);
     N.level = lvl;
   }
-  int64_t pf = 0, uo = 0, so = 0, po = 0;
+  int64_t uo = 0, so = 0, po = 0;
+  pf = 0;
   double flops = 0;
   int64_t fnnz = 0;
   int nlev = 0;
@@ -747,10 +766,11 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
   S.level_nodes.assign(nlev, {});
   for (int i = 0; i < nn; ++i) S.level_nodes[S.nodes[i].level].push_back(i);
   S.t_symbolic = now() - t0;
+  }  // ordering and symbolic
 
   // ---- numeric multifrontal factorisation --------------------------------------
   t0 = now();
-  S.panel_f.assign(pf, 0.0);
+  S.panel_f.resize(pf);  // not zero-filled: each host node writes its whole region
   std::vector<std::vector<double>> upd(nn);
   std::vector<int> fail(nn, 0);
   auto factor_node = [&](int i) {
@@ -885,6 +905,7 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
   S.t_numeric = now() - t0;
 
   // ---- element order and device tables -------------------------------------------
+  if (!in.structure) {
   std::vector<int32_t> key(m);
   for (int64_t e = 0; e < m; ++e) {
     int32_t k = INT32_MAX;
@@ -1010,6 +1031,7 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
     for (int64_t e = 0; e < m; ++e)
       for (int c = 0; c < nc; ++c) S.av_idx[fill[S.T[e * nc + c]]++] = static_cast<int32_t>(e * nc + c);
   }
+  }  // element order and device tables
   S.lcf_ptr.assign(S.nC + 1, 0);
   for (int64_t i = 0; i < S.nC; ++i) {
     const int32_t v = S.vnew2old[S.nF + i];

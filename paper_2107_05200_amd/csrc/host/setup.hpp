@@ -6,6 +6,7 @@
 #pragma once
 #include <cstdint>
 #include <memory>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -44,6 +45,11 @@ struct SetupInput {
   const int8_t* elem_energy = nullptr;  // optional per-element energy (0 or 1), m entries
   bool selfcheck = false;        // solve with the panels on the host and record the residual
   bool device_top = false;       // leave the nodes above the host subtrees to the device (Setup::top)
+  // refactorisation: the ordering and symbolic structure of an earlier set-up
+  // of the same mesh, pins and constraints (vnew2old, vold2new, nodes,
+  // children, struct_idx, panel_entries); only the values are computed
+  // (panel_f, top, pin_val, lcf_val, con_gamma), the other tables are left empty
+  const struct Setup* structure = nullptr;
 };
 
 // One node of the nested-dissection tree; its columns are the contiguous free
@@ -55,6 +61,28 @@ struct SolveNode {
   int64_t uoff = 0;  // first row of this node's update vector in the update buffer
   int64_t soff = 0;  // offset into struct_idx
   int64_t poff = 0;  // offset into pull_ptr (c + r + 1 entries)
+};
+
+// Allocator whose resize leaves doubles uninitialised: the panels of a large
+// factor are written once by the factorisation threads (first touch there),
+// never zero-filled first.
+template <typename T>
+struct UninitAlloc : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = UninitAlloc<U>;
+  };
+  UninitAlloc() = default;
+  template <typename U>
+  UninitAlloc(const UninitAlloc<U>&) noexcept {}
+  template <typename U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <typename U, typename... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
 };
 
 // A node above the host-factorised subtrees whose front the device assembles
@@ -104,7 +132,9 @@ struct Setup {
   // factor of L_FF (+ gamma A_F^T A_F)
   std::vector<SolveNode> nodes;
   std::vector<std::vector<int32_t>> children;
-  std::vector<double> panel_f;  // [Linv; -M] per node; the backward pass reads it transposed
+  // [Linv; -M] per node (the backward pass reads it transposed); every node the
+  // host factorises is written whole, the regions of S.top are not initialised
+  std::vector<double, UninitAlloc<double>> panel_f;
   std::vector<int32_t> struct_idx;
   std::vector<int32_t> pull_ptr, pull_idx;
   std::vector<std::vector<int32_t>> level_nodes;

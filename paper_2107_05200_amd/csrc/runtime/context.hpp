@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <sstream>
 #include <string>
 #include <unordered_map>
@@ -124,6 +125,7 @@ struct ffd_ctx {
   std::vector<int8_t> in_energy;
   int in_leaf = 0;
   size_t n_pin_val = 0, n_lcf_val = 0;
+  std::unique_ptr<Setup> hstruct;  // ordering and symbolic structure, reused by refactorisations
   double* gtl_part = nullptr;    // per-block partial sums of |G^T Lambda|^2
   // general linear constraints A W = c: rows of A (device numbering; host and
   // device copies), the transposed free part over the rows it touches, the

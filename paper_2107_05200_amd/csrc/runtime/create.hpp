@@ -70,6 +70,13 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
   h->in_energy = elem_energy;
   h->in_leaf = opt.leaf_size;
   h->enew2old_h = S.enew2old;
+  h->hstruct.reset(new Setup());
+  h->hstruct->vnew2old = S.vnew2old;
+  h->hstruct->vold2new = S.vold2new;
+  h->hstruct->nodes = S.nodes;
+  h->hstruct->children = S.children;
+  h->hstruct->struct_idx = S.struct_idx;
+  h->hstruct->panel_entries = S.panel_entries;
   if (in.n_con > 0) {
     h->ncon = in.n_con;
     h->in_con_ptr.assign(in.con_ptr, in.con_ptr + in.n_con + 1);
@@ -168,7 +175,7 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
     UP(hipMemset(h->Pcol, 0, static_cast<size_t>(ptot) * sizeof(double)));
     const ffd_status pst = upload_host_panels(h, S, poff, ptot, nullptr);
     if (pst != FFD_OK) return cleanup(pst);
-    std::vector<double>().swap(S.panel_f);
+    decltype(S.panel_f)().swap(S.panel_f);
     h->hpoff = poff;
     h->hnodes = S.nodes;
     h->hlevels = S.level_nodes;

@@ -9,9 +9,9 @@ namespace {
 
 // Rebuilds the factor of L = G^T M G for per-element penalties mu_dev_order
 // (device element order; nullptr: rho w_e) from the kept set-up input and
-// writes the new panels and pinned-coupling values into the existing buffers:
-// the ordering and the factor structure do not depend on the penalties
-// (checked).  Synchronous.
+// structure (the ordering and the factor structure do not depend on the
+// penalties; the result is checked against them) and writes the new panels
+// and pinned-coupling values into the existing buffers.  Synchronous.
 ffd_status refactor(ffd_ctx* h, const std::vector<double>* mu_dev_order, hipStream_t s) {
   std::vector<double> mu_in;
   SetupInput in;
@@ -37,8 +37,10 @@ ffd_status refactor(ffd_ctx* h, const std::vector<double>* mu_dev_order, hipStre
     for (int64_t e = 0; e < h->m; ++e) mu_in[h->enew2old_h[e]] = (*mu_dev_order)[e];
     in.mu_elem = mu_in.data();
   }
-  // the top fronts on the device when the dense libraries load
+  // the top fronts on the device when the dense libraries load; the ordering
+  // and symbolic structure of the set-up are reused
   in.device_top = h->device_refactor && dense_lib().ok;
+  in.structure = h->hstruct.get();
   Setup S;
   std::string err;
   const int st = build_setup(in, S, err);

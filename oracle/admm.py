@@ -523,6 +523,8 @@ class OracleSolver:
         b = rhs[self.free] - self.L_FC @ self.pin_pos
         x = np.empty((self.n, self.d))
         x[self.pins] = self.pin_pos
+        if self.free.size == 0:  # every vertex fixed: the W-step is the constraint itself
+            return x
         if self.A is None:
             if self._lu is None:
                 self._lu = spla.splu(self.L_FF)

@@ -113,7 +113,8 @@ typedef struct {
  *             recorded at the check iterations of ffd_iterate_until / ffd_run,
  *             NaN elsewhere
  * 10 max_grad_f  max_i |grad f(P_i^k)| (the proxy for B_i of Condition "gradf"
- *             plotted with the UV-mapping bounds)
+ *             plotted with the UV-mapping bounds); at the check iterations of
+ *             ffd_iterate_until / ffd_run, NaN elsewhere
  * 11 max_lambda_ratio  max_i |L1 - L0| / |1/2 (L1 - L0 + U1 L1^T U1 - U0 L0^T U0)|
  *             with L0, U0 = Lambda_i, U_i before and L1, U1 after the iteration
  *             (the proxy for gamma^(1/2) of Condition "lambdabound"; +inf where

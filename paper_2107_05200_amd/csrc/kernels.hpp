@@ -55,9 +55,11 @@ __device__ __forceinline__ void partials_init(double (&v)[kNumPartials]) {
 #pragma unroll
   for (int f = 0; f < kNumPartials; ++f) v[f] = f < kNumSums ? 0.0 : __longlong_as_double(0x7ff8000000000000LL);
 }
-__device__ __forceinline__ void partials_add(double (&v)[kNumPartials], const double* __restrict p) {
+// nf = kNumSums (an iteration without diagnostics: the maxima are not read) or kNumPartials
+__device__ __forceinline__ void partials_add(double (&v)[kNumPartials], const double* __restrict p, int nf) {
 #pragma unroll
-  for (int f = 0; f < kNumPartials; ++f) v[f] = f < kNumSums ? v[f] + p[f] : fmax(v[f], p[f]);
+  for (int f = 0; f < kNumPartials; ++f)
+    if (f < nf) v[f] = f < kNumSums ? v[f] + p[f] : fmax(v[f], p[f]);
 }
 
 // element state sizes: U (2D: cos, sin; 3D: 9), P (sym: 3 / 6), Lambda d*d
@@ -1037,15 +1039,20 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
       gn += gj * gj;
     }
     if (h_mode == 1 || store_u) gnorm2[e] = gn;
-    part[9] = static_cast<double>(gn);  // max |grad f(P)|^2 (proxy for B_i of Condition "gradf")
-    if (glam) part[10] = lambda_ratio<D, R>(Uo, Lo, Ur, L, ep);
+    if (glam) {  // the bound proxies (diagnostic iterations)
+      part[9] = static_cast<double>(gn);  // max |grad f(P)|^2 (proxy for B_i of Condition "gradf")
+      part[10] = lambda_ratio<D, R>(Uo, Lo, Ur, L, ep);
+    }
     part[0] = ep;
     part[2] = wd * fP;
     part[4] = wd * fP + 0.5 * mud * (res2 - lam2);
     part[6] = finite ? 0.0 : 1.0;
     part[8] = p2;
   }
-  block_reduce_store<kNumPartials, BS, kNumSums>(part, partials + static_cast<int64_t>(blockIdx.x) * kNumPartials);
+  // the maxima only on diagnostic iterations (their slots are not read otherwise)
+  double* out = partials + static_cast<int64_t>(blockIdx.x) * kNumPartials;
+  if (glam) block_reduce_store<kNumPartials, BS, kNumSums>(part, out);
+  else block_reduce_store<kNumSums, BS, kNumSums>(*reinterpret_cast<double(*)[kNumSums]>(part), out);
 }
 
 // first stage of the partial-sum reduction when the local step ran many small
@@ -1054,12 +1061,12 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
 constexpr int kFinalizeRows = 1024;
 
 __global__ __launch_bounds__(kBlock) void k_partials_reduce(const double* __restrict partials, int64_t nb,
-                                                            double* __restrict out) {
+                                                            double* __restrict out, int nf) {
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kFinalizeRows;
   const int64_t r1 = r0 + kFinalizeRows < nb ? r0 + kFinalizeRows : nb;
   double v[kNumPartials];
   partials_init(v);
-  for (int64_t bi = r0 + threadIdx.x; bi < r1; bi += kBlock) partials_add(v, partials + bi * kNumPartials);
+  for (int64_t bi = r0 + threadIdx.x; bi < r1; bi += kBlock) partials_add(v, partials + bi * kNumPartials, nf);
   block_reduce_store<kNumPartials, kBlock, kNumSums>(v, out + static_cast<int64_t>(blockIdx.x) * kNumPartials);
 }
 
@@ -1068,10 +1075,10 @@ __global__ __launch_bounds__(kBlock) void k_partials_reduce(const double* __rest
 // advanced (an iteration counter kept on the device for replayed graphs)
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict partials, int64_t nb,
                                                      double* __restrict hist, int64_t* __restrict k_dev,
-                                                     int fields) {
+                                                     int fields, int nf) {
   double v[kNumPartials];
   partials_init(v);
-  for (int64_t bi = threadIdx.x; bi < nb; bi += kBlock) partials_add(v, partials + bi * kNumPartials);
+  for (int64_t bi = threadIdx.x; bi < nb; bi += kBlock) partials_add(v, partials + bi * kNumPartials, nf);
   __shared__ double out[kNumPartials];
   block_reduce_store<kNumPartials, kBlock, kNumSums>(v, out);
   __syncthreads();
@@ -1088,8 +1095,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict pa
     hist[7] = sqrt(out[7]);
     hist[8] = sqrt(out[8]);
     hist[9] = __longlong_as_double(0x7ff8000000000000LL);
-    hist[10] = sqrt(out[9]);
-    hist[11] = out[10];  // NaN unless the iteration recorded the diagnostics
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    hist[10] = nf > kNumSums ? sqrt(out[9]) : nan;  // the bound proxies: diagnostic iterations only
+    hist[11] = nf > kNumSums ? out[10] : nan;
     if (k_dev) *k_dev += 1;
   }
 }

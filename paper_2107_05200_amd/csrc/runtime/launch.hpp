@@ -360,13 +360,15 @@ void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true
   if (ev) (void)hipEventRecord(ev[3], s);
   double* rec = dev_k ? h->hist : record ? h->hist + h->k * FFD_HIST_FIELDS : h->hist_scratch;
   int64_t* kd = dev_k ? h->k_dev : nullptr;
+  const int nf = diag ? kNumPartials : kNumSums;  // the maxima exist on diagnostic iterations only
   if (h->nparts > 2 * kFinalizeRows) {
     const int64_t nb2 = (h->nparts + kFinalizeRows - 1) / kFinalizeRows;
     hipLaunchKernelGGL(k_partials_reduce, dim3(static_cast<unsigned>(nb2)), dim3(kBlock), 0, s, h->partials,
-                       h->nparts, h->partials2);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials2, nb2, rec, kd, FFD_HIST_FIELDS);
+                       h->nparts, h->partials2, nf);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials2, nb2, rec, kd, FFD_HIST_FIELDS, nf);
   } else {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials, h->nparts, rec, kd, FFD_HIST_FIELDS);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, h->partials, h->nparts, rec, kd, FFD_HIST_FIELDS,
+                       nf);
   }
   if (diag && !dev_k) {
     const int64_t nb = (4 * h->n + kBlock - 1) / kBlock;

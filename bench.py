@@ -29,8 +29,8 @@ FP32_PEAK_TFLOPS = 78.6  # no packed FP32: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 # hash of the kernel sources they were measured on: a changed kernel reports
 # no traffic until it is measured again.
 MEASURED_TRAFFIC = {
-    "e4f60063383c88c9": {"solve": 3259.9e6, "local": 527.1e6,
-                         "local_flop_per_elem": 2282.0, "local_valu_per_wave": 2689.1},
+    "95991b0a21fe0692": {"solve": 3250.3e6, "local": 527.0e6,
+                         "local_flop_per_elem": 2282.0, "local_valu_per_wave": 2666.2},
 }
 
 

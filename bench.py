@@ -29,8 +29,8 @@ FP32_PEAK_TFLOPS = 78.6  # no packed FP32: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 # hash of the kernel sources they were measured on: a changed kernel reports
 # no traffic until it is measured again.
 MEASURED_TRAFFIC = {
-    "95991b0a21fe0692": {"solve": 3250.3e6, "local": 527.0e6,
-                         "local_flop_per_elem": 2282.0, "local_valu_per_wave": 2666.2},
+    "c5f70227b98466de": {"solve": 3256.1e6, "local": 520.6e6,
+                         "local_flop_per_elem": 2282.0, "local_valu_per_wave": 2666.4},
 }
 
 
@@ -272,6 +272,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the adjoint, batched, constraints and UV-pipeline legs")
     ap.add_argument("--tune-cache", default=None, help="launch-shape cache file (read, or written after tuning)")
     ap.add_argument("--no-graph", action="store_true", help="time direct launches instead of replayed HIP graphs")
+    ap.add_argument("--leaf-size", type=int, default=0, help="nested-dissection leaf size (0: the library's default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain elementwise copy (negation) of MIB MiB ten times (counter calibration)")
     args = ap.parse_args()
@@ -301,7 +302,8 @@ def main():
     w = meshgen.twisted_cube(args.cube)
     log(f"workload {w.name}: m={w.m} n={w.n} pins={len(w.pinned_idx)} ({time.perf_counter() - t0:.1f}s)")
     t0 = time.perf_counter()
-    s = binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=args.precision)
+    s = binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=args.precision,
+                       leaf_size=args.leaf_size)
     setup_s = time.perf_counter() - t0
     info = s.info()
     log(f"setup {setup_s:.1f}s: factor nnz {info['factor_nnz']:.3e}, levels {info['n_levels']}, "
@@ -346,7 +348,7 @@ def main():
     solve_gbs = solve_bytes / (solve_ms * 1e-3) / 1e9
     local_gbs = local_bytes / (local_ms * 1e-3) / 1e9
     dominant = "solve" if solve_ms >= local_ms else "local"
-    traffic = MEASURED_TRAFFIC.get(kernel_source_hash(), {}) if (args.cube, args.precision) == (64, 32) else {}
+    traffic = MEASURED_TRAFFIC.get(kernel_source_hash(), {}) if (args.cube, args.precision, args.leaf_size) == (64, 32, 0) else {}
     roof_solve = {"bound": "hbm", "achieved": round(solve_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round(solve_gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get("solve"),
                   "kernel": "k_solve_fwd + k_solve_bwd (one W-step solve, all levels)",

@@ -581,7 +581,9 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
       if (Lcol[k] != v && !pinned[Lcol[k]]) adjv.push_back(Lcol[k]);
     aptr[v + 1] = static_cast<int64_t>(adjv.size());
   }
-  int leaf = in.leaf_size > 0 ? in.leaf_size : (d == 3 ? 48 : 64);
+  // default leaf sizes: on the 64^3 tet cube 60 gives one level fewer than
+  // 48 for 1% more factor bytes, and the shallower level chain solves faster
+  int leaf = in.leaf_size > 0 ? in.leaf_size : (d == 3 ? 60 : 64);
   NDBuilder nd(aptr, adjv, in.V, din, leaf, pinned, n);
   std::vector<int32_t> freev;
   freev.reserve(S.nF);

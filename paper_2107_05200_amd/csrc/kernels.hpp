@@ -510,16 +510,68 @@ struct SolveTask {
 };
 static_assert(sizeof(SolveTask) == 80, "SolveTask layout");
 
-// carried part of forward output i (an update row): children's update rows
+// Carried part of forward rows: the children's update rows that extend-add
+// into row ra of a node's front (pull-list entry ra, when ea) are added to aa
+// in pull order, and likewise for row rb into ab.  The two rows' chains run
+// side by side and the first two pulls of each are fetched together (pull
+// range, then both indices, then both update rows: three dependent loads,
+// which covers every row of a binary dissection tree); further pulls follow
+// one at a time.
+template <int D>
+__device__ __forceinline__ void fwd_carried2(const int32_t* __restrict pull_ptr, const int32_t* __restrict pull_idx,
+                                             const double* __restrict ub, int64_t ra, bool ea, double (&aa)[D],
+                                             int64_t rb, bool eb, double (&ab)[D]) {
+  int32_t qa0 = 0, qa1 = 0, qb0 = 0, qb1 = 0;
+  if (ea) {
+    qa0 = pull_ptr[ra];
+    qa1 = pull_ptr[ra + 1];
+  }
+  if (eb) {
+    qb0 = pull_ptr[rb];
+    qb1 = pull_ptr[rb + 1];
+  }
+  int32_t ia[2], ib[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    ia[u] = qa0 + u < qa1 ? pull_idx[qa0 + u] : -1;
+    ib[u] = qb0 + u < qb1 ? pull_idx[qb0 + u] : -1;
+  }
+  double va[2][D], vb[2][D];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      va[u][k] = ia[u] >= 0 ? ub[static_cast<int64_t>(ia[u]) * D + k] : 0.0;
+      vb[u][k] = ib[u] >= 0 ? ub[static_cast<int64_t>(ib[u]) * D + k] : 0.0;
+    }
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      if (ia[u] >= 0) aa[k] += va[u][k];
+      if (ib[u] >= 0) ab[k] += vb[u][k];
+    }
+  for (int32_t q = qa0 + 2; q < qa1; ++q) {
+    const int64_t o = static_cast<int64_t>(pull_idx[q]) * D;
+#pragma unroll
+    for (int k = 0; k < D; ++k) aa[k] += ub[o + k];
+  }
+  for (int32_t q = qb0 + 2; q < qb1; ++q) {
+    const int64_t o = static_cast<int64_t>(pull_idx[q]) * D;
+#pragma unroll
+    for (int k = 0; k < D; ++k) ab[k] += ub[o + k];
+  }
+}
+
+// carried part of forward output i (an update row) alone
 template <int D>
 __device__ __forceinline__ void fwd_carried(const SolveTask& tk, int i, const int32_t* __restrict pull_ptr,
                                             const int32_t* __restrict pull_idx, const double* __restrict ub,
                                             double (&cv)[D]) {
-  for (int32_t q = pull_ptr[tk.poff + i]; q < pull_ptr[tk.poff + i + 1]; ++q) {
-    const int64_t o = static_cast<int64_t>(pull_idx[q]) * D;
+  double none[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) cv[k] += ub[o + k];
-  }
+  for (int k = 0; k < D; ++k) none[k] = 0.0;
+  fwd_carried2<D>(pull_ptr, pull_idx, ub, tk.poff + i, true, cv, 0, false, none);
 }
 
 template <int D>
@@ -609,19 +661,26 @@ __global__ __launch_bounds__(NW * 64) void k_solve_fwd(const SolveTask* __restri
   double cv[D], acc[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) cv[k] = acc[k] = 0.0;
-  if (tk.slot < 0 && threadIdx.x < OPT && live && i >= tk.c) fwd_carried<D>(tk, i, pull_ptr, pull_idx, ub, cv);
+  // the carried part of this thread's output row is gathered side by side
+  // with the first chunk's staging (in a pass of its own for a thread that
+  // stages no row)
+  bool cv_todo = tk.slot < 0 && threadIdx.x < OPT && live && i >= tk.c;
   auto stage = [&](int j0, int jn) {
-    for (int t = threadIdx.x; t < jn; t += NW * 64) {
-      const int p = j0 + t;
+    for (int t = threadIdx.x; t < jn || cv_todo; t += NW * 64) {
+      const bool sg = t < jn;
       double a[D];
 #pragma unroll
-      for (int k = 0; k < D; ++k) a[k] = b[static_cast<int64_t>(tk.first + p) * D + k];
-      fwd_carried<D>(tk, p, pull_ptr, pull_idx, ub, a);
+      for (int k = 0; k < D; ++k) a[k] = sg ? b[static_cast<int64_t>(tk.first + j0 + t) * D + k] : 0.0;
+      fwd_carried2<D>(pull_ptr, pull_idx, ub, tk.poff + j0 + t, sg, a, tk.poff + i, cv_todo, cv);
+      cv_todo = false;
+      if (sg) {
 #pragma unroll
-      for (int k = 0; k < D; ++k) vs[t][k] = a[k];
+        for (int k = 0; k < D; ++k) vs[t][k] = a[k];
+      }
     }
   };
   solve_stream<D, NS>(Pcol + tk.pf + i, tk.ld, live, tk.lo, tk.hi, st, vs, acc, stage);
+  if (cv_todo) fwd_carried<D>(tk, i, pull_ptr, pull_idx, ub, cv);
   solve_streams_sum<D, OPT, NW>(acc, o, st);
   if (threadIdx.x >= OPT || !live) return;
   if (tk.slot >= 0) {
@@ -742,6 +801,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_bwd_reduce(const SolveTask* __
 // a wave-private LDS slice and adds its streams with a fixed xor tree.  There
 // is no block barrier, so a CU keeps up to 32 independent tasks in flight.
 constexpr int kWaveKC = 64;
+constexpr int kWavePF = 16;  // panel entries per lane loaded before the gather
 
 // orders this wave's LDS writes before its later LDS reads (LDS operations of
 // one wave complete in order; the fences keep the compiler from moving them)
@@ -778,23 +838,42 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd_wave(const SolveTask* __re
   double cv[D], acc[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) cv[k] = acc[k] = 0.0;
-  if (st == 0 && live && i >= tk.c) fwd_carried<D>(tk, i, pull_ptr, pull_idx, ub, cv);
+  bool cv_todo = st == 0 && live && i >= tk.c;
   const double* __restrict col = Pcol + tk.pf + i;
   for (int j0 = tk.lo; j0 < tk.hi; j0 += kWaveKC) {
     const int jn = min(kWaveKC, tk.hi - j0);
-    if (lane < jn) {
-      const int p = j0 + lane;
+    // the chunk's first panel entries are in flight while the inner vector
+    // is gathered
+    double pf[kWavePF];
+#pragma unroll
+    for (int u = 0; u < kWavePF; ++u) {
+      const int jj = st + u * IS;
+      pf[u] = (live && jj < jn) ? col[static_cast<int64_t>(j0 + jj) * tk.ld] : 0.0;
+    }
+    {  // stage the chunk; the carried part of the output row rides along
+      const bool sg = lane < jn;
       double a[D];
 #pragma unroll
-      for (int k = 0; k < D; ++k) a[k] = b[static_cast<int64_t>(tk.first + p) * D + k];
-      fwd_carried<D>(tk, p, pull_ptr, pull_idx, ub, a);
+      for (int k = 0; k < D; ++k) a[k] = sg ? b[static_cast<int64_t>(tk.first + j0 + lane) * D + k] : 0.0;
+      fwd_carried2<D>(pull_ptr, pull_idx, ub, tk.poff + j0 + lane, sg, a, tk.poff + i, cv_todo, cv);
+      cv_todo = false;
+      if (sg) {
 #pragma unroll
-      for (int k = 0; k < D; ++k) vs[wave][lane][k] = a[k];
+        for (int k = 0; k < D; ++k) vs[wave][lane][k] = a[k];
+      }
     }
     wave_lds_sync();
     if (live) {
+#pragma unroll
+      for (int u = 0; u < kWavePF; ++u) {
+        const int jj = st + u * IS;
+        if (jj < jn) {
+#pragma unroll
+          for (int k = 0; k < D; ++k) acc[k] += pf[u] * vs[wave][jj][k];
+        }
+      }
 #pragma unroll 8
-      for (int jj = st; jj < jn; jj += IS) {
+      for (int jj = st + kWavePF * IS; jj < jn; jj += IS) {
         const double pv = col[static_cast<int64_t>(j0 + jj) * tk.ld];
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] += pv * vs[wave][jj][k];
@@ -802,6 +881,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd_wave(const SolveTask* __re
     }
     wave_lds_sync();
   }
+  if (cv_todo) fwd_carried<D>(tk, i, pull_ptr, pull_idx, ub, cv);
   wave_streams_sum<D, OPT>(acc);
   if (st != 0 || !live) return;
 #pragma unroll
@@ -833,6 +913,12 @@ __global__ __launch_bounds__(kBlock) void k_solve_bwd_wave(const SolveTask* __re
   const double* __restrict rowp = Prow + tk.pf + j;
   for (int p0 = tk.lo; p0 < tk.hi; p0 += kWaveKC) {
     const int pn = min(kWaveKC, tk.hi - p0);
+    double pf[kWavePF];
+#pragma unroll
+    for (int u = 0; u < kWavePF; ++u) {
+      const int pp = st + u * IS;
+      pf[u] = (live && pp < pn) ? rowp[static_cast<int64_t>(p0 + pp) * tk.ld] : 0.0;
+    }
     if (lane < pn) {
       const int p = p0 + lane;
       const int64_t src = p < tk.c ? static_cast<int64_t>(tk.first + p) : static_cast<int64_t>(sidx[tk.soff + p - tk.c]);
@@ -842,8 +928,16 @@ __global__ __launch_bounds__(kBlock) void k_solve_bwd_wave(const SolveTask* __re
     }
     wave_lds_sync();
     if (live) {
+#pragma unroll
+      for (int u = 0; u < kWavePF; ++u) {
+        const int pp = st + u * IS;
+        if (pp < pn) {
+#pragma unroll
+          for (int k = 0; k < D; ++k) acc[k] += pf[u] * vs[wave][pp][k];
+        }
+      }
 #pragma unroll 8
-      for (int pp = st; pp < pn; pp += IS) {
+      for (int pp = st + kWavePF * IS; pp < pn; pp += IS) {
         const double pv = rowp[static_cast<int64_t>(p0 + pp) * tk.ld];
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] += pv * vs[wave][pp][k];

@@ -104,8 +104,48 @@ def cpu_baseline(w, state, n_sample: int, passes: int):
             "sample": f"{len(sel)} contiguous elements of the {w.m:,}-element workload at the GPU state "
                       f"after the timed run; oracle element steps (U, P, Lambda, diagnostics), best of "
                       f"{passes} passes, 1 thread; the oracle's sparse LU does not factor this L_FF "
-                      f"within the benchmark budget, so no oracle iteration rate",
+                      f"within the benchmark budget, so no oracle iteration rate at this size "
+                      f"(oracle_iterations: whole iterations on two workloads it can factor)",
             "host_cpu": _cpu_name(), "host_nproc": os.cpu_count()}
+
+
+def oracle_iteration_rates():
+    """The oracle's whole iterations (W-step with its sparse LU, element steps,
+    diagnostics) where it can factor L_FF: the 32x32 height field (float64,
+    20 iterations) and the sphere cap (501,126 triangles, set-up and 4
+    iterations), one thread, beside the device's plain iterations of the same
+    workloads (float64 and float32 element steps, as in the parity tests)."""
+    import numpy as np
+    import torch
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    from paper_2107_05200_amd import binding, meshgen
+
+    rows = {}
+    for label, mk, k_cpu, k_gpu, prec in (
+            ("height field UV, 1,922 triangles, SD", lambda: meshgen.height_field_uv(), 20, 200, 64),
+            ("sphere cap UV, 501,126 triangles, SG", lambda: meshgen.sphere_cap_uv(), 4, 200, 32)):
+        w = mk()
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+            r.init(w.x0)
+            t1 = time.perf_counter()
+            r.iterate(k_cpu)
+            t2 = time.perf_counter()
+        g = binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=prec)
+        g.init(w.x0)
+        g.iterate(5)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        g.iterate(k_gpu)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        g.close()
+        cpu_it, gpu_it = (t2 - t1) / k_cpu, (t4 - t3) / k_gpu
+        rows[label] = {"oracle_s_per_iter": cpu_it, "oracle_setup_s": t1 - t0, "oracle_iters": k_cpu,
+                       "device_s_per_iter": gpu_it, "device_precision": prec, "ratio": cpu_it / gpu_it}
+    return rows
 
 
 def adjoint_leg(K: int = 100, every: int = 10, reps: int = 3):
@@ -419,6 +459,9 @@ def main():
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(w, st, args.cpu_sample, 3)
         log(f"cpu baseline {out['cpu_baseline']['value']:.0f} elems/s ({time.perf_counter() - t0:.1f}s)")
+        t0 = time.perf_counter()
+        out["cpu_baseline"]["oracle_iterations"] = oracle_iteration_rates()
+        log(f"oracle iterations: {out['cpu_baseline']['oracle_iterations']} ({time.perf_counter() - t0:.1f}s)")
     print(json.dumps(out), flush=True)
 
 

@@ -151,11 +151,15 @@ def oracle_iteration_rates():
 def adjoint_leg(K: int = 100, every: int = 10, reps: int = 3):
     """Disk deformation (99,846 triangles, 16 handles): fwd+bwd seconds per
     iteration of the checkpointed adjoint divided by plain seconds per
-    iteration (best of `reps` runs of each)."""
+    iteration (best of `reps` runs of each), both with the autotuned launch
+    shapes."""
     import torch
     from paper_2107_05200_amd import binding, meshgen
     w = meshgen.disk_deformation()
     s = binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32)
+    t0 = time.perf_counter()
+    launch = s.init(w.V).autotune()
+    tune = time.perf_counter() - t0
     s.init(w.V).iterate(10)
     s.init(w.V).adjoint_forward(10, every)
     s.adjoint_backward(energy_loss=True)
@@ -173,7 +177,8 @@ def adjoint_leg(K: int = 100, every: int = 10, reps: int = 3):
         fb.append((time.perf_counter() - t0) / K)
     s.close()
     return {"workload": f"disk deformation, {w.m:,} triangles, 16 handles, K={K}, checkpoint every {every}",
-            "plain_s_per_iter": min(plain), "fwd_bwd_s_per_iter": min(fb), "ratio": min(fb) / min(plain)}
+            "plain_s_per_iter": min(plain), "fwd_bwd_s_per_iter": min(fb), "ratio": min(fb) / min(plain),
+            "autotune_s": tune, "launch": launch}
 
 
 def batched_leg(iters: int = 200):

@@ -641,8 +641,7 @@ ffd_status ffd_adjoint_backward(ffd_handle h, const void* Pbar_dev, int32_t ener
   const int64_t nseg = (K + every - 1) / every;
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t start = seg * every, len = std::min(every, K - start);
-    HIP_TRY(load_state(h, h->adj_ck + sb * seg, s));
-    HIP_TRY(save_state(h, h->adj_seg, s));
+    HIP_TRY(copy_state3(h, h->adj_ck + sb * seg, nullptr, h->adj_seg, s));  // live state and slot 0
     for (int64_t t = 1; t <= len; ++t) {
       one_iteration(h, s, nullptr, false);
       HIP_TRY(save_state(h, h->adj_seg + sb * t, s));

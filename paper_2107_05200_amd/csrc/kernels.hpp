@@ -1335,6 +1335,39 @@ __global__ __launch_bounds__(kBlock) void k_gtlam_finalize(const double* __restr
   if (threadIdx.x == 0) rec[9] = sqrt(out[0]);
 }
 
+// Several device-to-device copies in one launch (checkpoint slots of the
+// adjoint: element state and map); 16-byte moves where both ends allow, 4-byte
+// otherwise (every length is a multiple of 4).
+constexpr int kMaxCopyJobs = 12;
+struct CopyJobs {
+  const char* src[kMaxCopyJobs];
+  char* dst[kMaxCopyJobs];
+  int64_t bytes[kMaxCopyJobs];
+  int32_t n;
+};
+
+__global__ __launch_bounds__(kBlock) void k_copy_jobs(CopyJobs J) {
+  const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int q = 0; q < J.n; ++q) {
+    const char* __restrict src = J.src[q];
+    char* __restrict dst = J.dst[q];
+    const int64_t nb = J.bytes[q];
+    int64_t done = 0;
+    if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0) {
+      const int64_t n16 = nb / 16;
+      const uint4* __restrict s16 = reinterpret_cast<const uint4*>(src);
+      uint4* __restrict d16 = reinterpret_cast<uint4*>(dst);
+      for (int64_t i = tid; i < n16; i += stride) d16[i] = s16[i];
+      done = n16 * 16;
+    }
+    const int64_t n4 = (nb - done) / 4;
+    const uint32_t* __restrict s4 = reinterpret_cast<const uint32_t*>(src + done);
+    uint32_t* __restrict d4 = reinterpret_cast<uint32_t*>(dst + done);
+    for (int64_t i = tid; i < n4; i += stride) d4[i] = s4[i];
+  }
+}
+
 __global__ void k_set_counter(int64_t* __restrict p, int64_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }

@@ -148,24 +148,49 @@ SlotView slot_view(ffd_ctx* h, char* base) {
   return v;
 }
 
-// element state and map, copied in both directions
-hipError_t copy_state(ffd_ctx* h, char* slot, bool save, hipStream_t s) {
+// Element state and map (U, P, Lambda, |grad f|^2, corner vectors, map):
+// copies from slot `from` (nullptr: the live state) to slot `to` (nullptr:
+// the live state) and, when `to2` is given, to that slot as well, all in one
+// launch.
+hipError_t copy_state3(ffd_ctx* h, char* from, char* to, char* to2, hipStream_t s) {
   const size_t nU = h->d == 2 ? 2 : 9, nP = h->d == 2 ? 3 : 6, rs = h->rsize(), m = h->m, d = h->d;
-  SlotView v = slot_view(h, slot);
-  void* live[6] = {h->U, h->P, h->L, h->gn, h->g, h->x[h->cur]};
-  void* saved[6] = {v.U, v.P, v.L, v.gn, v.g, v.x};
+  auto parts = [&](char* slot, void* (&p)[6]) {
+    if (!slot) {
+      void* live[6] = {h->U, h->P, h->L, h->gn, h->g, h->x[h->cur]};
+      for (int i = 0; i < 6; ++i) p[i] = live[i];
+    } else {
+      const SlotView v = slot_view(h, slot);
+      void* saved[6] = {v.U, v.P, v.L, v.gn, v.g, v.x};
+      for (int i = 0; i < 6; ++i) p[i] = saved[i];
+    }
+  };
   const size_t bytes[6] = {rs * m * nU, rs * m * nP, rs * m * d * d, rs * m, rs * m * (d + 1) * d,
                            sizeof(double) * h->n * d};
+  void *src[6], *dst[6], *dst2[6];
+  parts(from, src);
+  parts(to, dst);
+  if (to2) parts(to2, dst2);
+  CopyJobs J{};
+  size_t most = 0;
   for (int i = 0; i < 6; ++i) {
-    hipError_t e = save ? hipMemcpyAsync(saved[i], live[i], bytes[i], hipMemcpyDeviceToDevice, s)
-                        : hipMemcpyAsync(live[i], saved[i], bytes[i], hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
+    if (bytes[i] % 4 != 0) return hipErrorInvalidValue;  // the copy kernel moves 4-byte words
+    J.src[J.n] = static_cast<const char*>(src[i]);
+    J.dst[J.n] = static_cast<char*>(dst[i]);
+    J.bytes[J.n++] = static_cast<int64_t>(bytes[i]);
+    if (to2) {
+      J.src[J.n] = static_cast<const char*>(src[i]);
+      J.dst[J.n] = static_cast<char*>(dst2[i]);
+      J.bytes[J.n++] = static_cast<int64_t>(bytes[i]);
+    }
+    most = std::max(most, bytes[i]);
   }
-  return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(2048, std::max<int64_t>(1, static_cast<int64_t>(most / 16 + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_copy_jobs, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, J);
+  return hipGetLastError();
 }
 
-hipError_t save_state(ffd_ctx* h, char* slot, hipStream_t s) { return copy_state(h, slot, true, s); }
-hipError_t load_state(ffd_ctx* h, char* slot, hipStream_t s) { return copy_state(h, slot, false, s); }
+hipError_t save_state(ffd_ctx* h, char* slot, hipStream_t s) { return copy_state3(h, nullptr, slot, nullptr, s); }
+hipError_t load_state(ffd_ctx* h, char* slot, hipStream_t s) { return copy_state3(h, slot, nullptr, nullptr, s); }
 
 template <int D, typename R, int E>
 void launch_adj_seed(ffd_ctx* h, const ffd_ctx::Seg& g, const void* Pbar_ext, int energy_loss, hipStream_t s) {

@@ -801,7 +801,8 @@ __global__ __launch_bounds__(kBlock) void k_solve_bwd_reduce(const SolveTask* __
 // a wave-private LDS slice and adds its streams with a fixed xor tree.  There
 // is no block barrier, so a CU keeps up to 32 independent tasks in flight.
 constexpr int kWaveKC = 64;
-constexpr int kWavePF = 16;  // panel entries per lane loaded before the gather
+constexpr int kWavePF = 16;   // panel entries per lane loaded before the gather (backward)
+constexpr int kWavePFf = 8;   // forward: its two pull chains need the registers
 
 // orders this wave's LDS writes before its later LDS reads (LDS operations of
 // one wave complete in order; the fences keep the compiler from moving them)
@@ -819,8 +820,10 @@ __device__ __forceinline__ void wave_streams_sum(double (&acc)[D]) {
     for (int k = 0; k < D; ++k) acc[k] += __shfl_xor(acc[k], off, 64);
 }
 
+// (at least 4 waves per SIMD, which the register budget allows without
+// spilling at this prefetch depth)
 template <int D, int OPT>
-__global__ __launch_bounds__(kBlock) void k_solve_fwd_wave(const SolveTask* __restrict tasks, int ntasks,
+__global__ __launch_bounds__(kBlock, 4) void k_solve_fwd_wave(const SolveTask* __restrict tasks, int ntasks,
                                                            const double* __restrict Pcol,
                                                            const int32_t* __restrict pull_ptr,
                                                            const int32_t* __restrict pull_idx,
@@ -844,9 +847,9 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd_wave(const SolveTask* __re
     const int jn = min(kWaveKC, tk.hi - j0);
     // the chunk's first panel entries are in flight while the inner vector
     // is gathered
-    double pf[kWavePF];
+    double pf[kWavePFf];
 #pragma unroll
-    for (int u = 0; u < kWavePF; ++u) {
+    for (int u = 0; u < kWavePFf; ++u) {
       const int jj = st + u * IS;
       pf[u] = (live && jj < jn) ? col[static_cast<int64_t>(j0 + jj) * tk.ld] : 0.0;
     }
@@ -865,7 +868,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd_wave(const SolveTask* __re
     wave_lds_sync();
     if (live) {
 #pragma unroll
-      for (int u = 0; u < kWavePF; ++u) {
+      for (int u = 0; u < kWavePFf; ++u) {
         const int jj = st + u * IS;
         if (jj < jn) {
 #pragma unroll
@@ -873,7 +876,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd_wave(const SolveTask* __re
         }
       }
 #pragma unroll 8
-      for (int jj = st + kWavePF * IS; jj < jn; jj += IS) {
+      for (int jj = st + kWavePFf * IS; jj < jn; jj += IS) {
         const double pv = col[static_cast<int64_t>(j0 + jj) * tk.ld];
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] += pv * vs[wave][jj][k];
@@ -889,8 +892,10 @@ __global__ __launch_bounds__(kBlock) void k_solve_fwd_wave(const SolveTask* __re
   fwd_store<D>(tk, i, acc, y, ub);
 }
 
+// (at least 5 waves per SIMD: the level is bound by load latency, and the
+// kernel fits the register budget of 5 without spilling)
 template <int D, int OPT>
-__global__ __launch_bounds__(kBlock) void k_solve_bwd_wave(const SolveTask* __restrict tasks, int ntasks,
+__global__ __launch_bounds__(kBlock, 5) void k_solve_bwd_wave(const SolveTask* __restrict tasks, int ntasks,
                                                            const double* __restrict Prow,
                                                            const int32_t* __restrict sidx, double* y,
                                                            double* __restrict x, const SolveTask* __restrict yred,
@@ -1152,7 +1157,7 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
 // first stage of the partial-sum reduction when the local step ran many small
 // blocks: block j adds rows [j kFinalizeRows, (j + 1) kFinalizeRows) in a fixed
 // order (strided per thread, then the shuffle tree)
-constexpr int kFinalizeRows = 1024;
+constexpr int kFinalizeRows = 256;
 
 __global__ __launch_bounds__(kBlock) void k_partials_reduce(const double* __restrict partials, int64_t nb,
                                                             double* __restrict out, int nf) {

@@ -29,7 +29,7 @@ FP32_PEAK_TFLOPS = 78.6  # no packed FP32: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 # hash of the kernel sources they were measured on: a changed kernel reports
 # no traffic until it is measured again.
 MEASURED_TRAFFIC = {
-    "c5f70227b98466de": {"solve": 3256.1e6, "local": 520.6e6,
+    "ef335600c3953d6b": {"solve": 3249.1e6, "local": 526.6e6,
                          "local_flop_per_elem": 2282.0, "local_valu_per_wave": 2666.4},
 }
 

@@ -341,8 +341,9 @@ ffd_status ffd_adjoint_backward(ffd_handle h, const void* Pbar_dev, int32_t ener
  * right-hand side (2 / 4 / 8); level by level for both triangular-solve
  * passes, the task shape (blocks of 4 / 8 / 16 waves or one wave per task,
  * 64 / 32 / 16 outputs per task, inner-range splitting: none, 2048 .. 256,
- * with the partials added right away or, for forward blocks of y rows, by
- * the backward pass); and the
+ * with the partials added right away, or, for forward blocks of y rows, by
+ * the backward pass, or, for backward levels above the lowest, by the next
+ * backward launch, which reads the pending rows from the partials); and the
  * number of streams (1 .. 4, the caller's stream plus streams of the handle,
  * all of default priority) over which the subtrees below a top level are
  * spread.  With cache_path (may be NULL) the choice is read from / appended
@@ -353,7 +354,7 @@ ffd_status ffd_adjoint_backward(ffd_handle h, const void* Pbar_dev, int32_t ener
  * lanes per row, solve levels run one wave per task, solve levels with split
  * inner ranges (both passes counted), streams, top level).  Element results
  * do not depend on the choice; history sums and the solve's rounding order
- * may change in the last bits. */
+ * may change in the last bits (deferral and the stream count change nothing). */
 ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int32_t* choice_out);
 
 void ffd_destroy(ffd_handle h);

@@ -779,7 +779,7 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
             for (int chunk : {0, 2048, 1024, 512, 256})
               if ((chunk == 0 || chunk < max_inner) && (nw == 4 || chunk == 0 || chunk >= 1024))
                 for (int defer : {0, 1})
-                  if (defer == 0 || (pass == 0 && chunk > 0)) cands.push_back(LevelCfg{0, opt, chunk, nw, defer});
+                  if (defer == 0 || (chunk > 0 && (pass == 0 || l > 0))) cands.push_back(LevelCfg{0, opt, chunk, nw, defer});
         }
         const LevelCfg keep = cfg[l];
         LevelCfg bestc = keep;

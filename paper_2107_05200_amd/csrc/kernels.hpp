@@ -735,17 +735,79 @@ __device__ __forceinline__ void fwd_y_reduce(const SolveTask& tk, int lane, cons
   for (int k = 0; k < D; ++k) y[static_cast<int64_t>(tk.first + i) * D + k] = acc[k];
 }
 
+// The backward counterpart: a split backward level may leave its chunk
+// partials to the next backward launch.  Its tasks read the pending rows
+// straight from the partials (an entry of the structure list coded
+// -(1 + (slot << 12 | lane << 6 | (nk - 1))) instead of a row index), and
+// waves appended to its grid write those rows of x for the launches after it.
+constexpr int kDeferNkMax = 64, kDeferSlotLimit = 1 << 19;
+
+template <int D>
+__device__ __forceinline__ void bwd_x_reduce(const SolveTask& tk, int lane, const double* __restrict part,
+                                             double* x) {
+  const int j = tk.out0 + lane;
+  if (lane >= tk.hi || j >= tk.c) return;
+  double acc[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc[k] = 0.0;
+  for (int q = 0; q < tk.nk; ++q)
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc[k] += part[(static_cast<int64_t>(tk.slot + q) * kSolveOutMax + lane) * D + k];
+#pragma unroll
+  for (int k = 0; k < D; ++k) x[static_cast<int64_t>(tk.first + j) * D + k] = acc[k];
+}
+
+// inner-vector entry p of a backward task: its own y row, an ancestor's x
+// row, or an ancestor's row still held as chunk partials (added in the
+// reduction's order, so the value is the one bwd_x_reduce writes)
+template <int D>
+__device__ __forceinline__ void bwd_entry(const SolveTask& tk, int p, const int32_t* __restrict sidx, const double* y,
+                                          const double* x, const double* __restrict part, double (&v)[D]) {
+  if (p < tk.c) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = y[static_cast<int64_t>(tk.first + p) * D + k];
+    return;
+  }
+  const int32_t e = sidx[tk.soff + p - tk.c];
+  if (e >= 0) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] = x[static_cast<int64_t>(e) * D + k];
+    return;
+  }
+  const uint32_t code = static_cast<uint32_t>(-(e + 1));
+  const int nk = static_cast<int>(code & 63u) + 1, lane = static_cast<int>((code >> 6) & 63u);
+  const int64_t slot = static_cast<int64_t>(code >> 12);
+#pragma unroll
+  for (int k = 0; k < D; ++k) v[k] = 0.0;
+  for (int q = 0; q < nk; ++q)
+#pragma unroll
+    for (int k = 0; k < D; ++k) v[k] += part[((slot + q) * kSolveOutMax + lane) * D + k];
+}
+
+// waves appended to a backward launch: pending forward y-row reductions
+// [0, nyred), then pending backward x-row reductions [nyred, nyred + nxred)
+template <int D>
+__device__ __forceinline__ void bwd_appended(int t, int lane, const SolveTask* __restrict yred, int nyred,
+                                             const double* __restrict fpart, double* y,
+                                             const SolveTask* __restrict xred, int nxred,
+                                             const double* __restrict part, double* x) {
+  if (t < nyred) fwd_y_reduce<D>(yred[t], lane, fpart, y);
+  else if (t - nyred < nxred) bwd_x_reduce<D>(xred[t - nyred], lane, part, x);
+}
+
 template <int D, int OPT, int NW>
 __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const SolveTask* __restrict tasks, int nmain,
                                                        const double* __restrict Prow, const int32_t* __restrict sidx,
-                                                       double* y, double* __restrict x, double* __restrict part,
+                                                       double* y, double* x, double* part,
                                                        const SolveTask* __restrict yred, int nyred,
-                                                       const double* __restrict fpart) {
+                                                       const double* __restrict fpart,
+                                                       const SolveTask* __restrict xred, int nxred,
+                                                       const double* xpart) {
   constexpr int NS = NW * (64 / OPT);
   __shared__ double vs[kSolveKC][D];
-  if (static_cast<int>(blockIdx.x) >= nmain) {  // the whole block: pending forward y-row reductions
+  if (static_cast<int>(blockIdx.x) >= nmain) {  // the whole block: pending reductions
     const int t = (static_cast<int>(blockIdx.x) - nmain) * NW + static_cast<int>(threadIdx.x >> 6);
-    if (t < nyred) fwd_y_reduce<D>(yred[t], threadIdx.x & 63, fpart, y);
+    bwd_appended<D>(t, threadIdx.x & 63, yred, nyred, fpart, y, xred, nxred, xpart, x);
     return;
   }
   const SolveTask tk = tasks[blockIdx.x];
@@ -758,11 +820,10 @@ __global__ __launch_bounds__(NW * 64) void k_solve_bwd(const SolveTask* __restri
   for (int k = 0; k < D; ++k) acc[k] = 0.0;
   auto stage = [&](int p0, int pn) {
     for (int t = threadIdx.x; t < pn; t += NW * 64) {
-      const int p = p0 + t;
-      const int64_t src = p < tk.c ? static_cast<int64_t>(tk.first + p) : static_cast<int64_t>(sidx[tk.soff + p - tk.c]);
-      const double* vsrc = p < tk.c ? y : x;
+      double v[D];
+      bwd_entry<D>(tk, p0 + t, sidx, y, x, xpart, v);
 #pragma unroll
-      for (int k = 0; k < D; ++k) vs[t][k] = vsrc[src * D + k];
+      for (int k = 0; k < D; ++k) vs[t][k] = v[k];
     }
   };
   solve_stream<D, NS>(Prow + tk.pf + j, tk.ld, live, tk.lo, tk.hi, st, vs, acc, stage);
@@ -782,18 +843,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_bwd_reduce(const SolveTask* __
                                                              double* __restrict x, const double* __restrict part) {
   const int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (t >= ntasks) return;
-  const SolveTask tk = tasks[t];
-  const int lane = threadIdx.x & 63;
-  const int j = tk.out0 + lane;
-  if (lane >= tk.hi || j >= tk.c) return;
-  double acc[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) acc[k] = 0.0;
-  for (int q = 0; q < tk.nk; ++q)
-#pragma unroll
-    for (int k = 0; k < D; ++k) acc[k] += part[(static_cast<int64_t>(tk.slot + q) * kSolveOutMax + lane) * D + k];
-#pragma unroll
-  for (int k = 0; k < D; ++k) x[static_cast<int64_t>(tk.first + j) * D + k] = acc[k];
+  bwd_x_reduce<D>(tasks[t], threadIdx.x & 63, part, x);
 }
 
 // Wave-per-task form for levels of small nodes: each wave owns one task (OPT
@@ -897,15 +947,17 @@ __global__ __launch_bounds__(kBlock, 4) void k_solve_fwd_wave(const SolveTask* _
 template <int D, int OPT>
 __global__ __launch_bounds__(kBlock, 5) void k_solve_bwd_wave(const SolveTask* __restrict tasks, int ntasks,
                                                            const double* __restrict Prow,
-                                                           const int32_t* __restrict sidx, double* y,
-                                                           double* __restrict x, const SolveTask* __restrict yred,
-                                                           int nyred, const double* __restrict fpart) {
+                                                           const int32_t* __restrict sidx, double* y, double* x,
+                                                           const SolveTask* __restrict yred, int nyred,
+                                                           const double* __restrict fpart,
+                                                           const SolveTask* __restrict xred, int nxred,
+                                                           const double* xpart) {
   constexpr int IS = 64 / OPT;
   __shared__ double vs[kBlock / 64][kWaveKC][D];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t = blockIdx.x * (kBlock / 64) + wave;
-  if (t >= ntasks) {  // the whole wave: a pending forward y-row reduction, if any
-    if (t - ntasks < nyred) fwd_y_reduce<D>(yred[t - ntasks], lane, fpart, y);
+  if (t >= ntasks) {  // the whole wave: a pending reduction, if any
+    bwd_appended<D>(t - ntasks, lane, yred, nyred, fpart, y, xred, nxred, xpart, x);
     return;
   }
   const SolveTask tk = tasks[t];
@@ -925,11 +977,10 @@ __global__ __launch_bounds__(kBlock, 5) void k_solve_bwd_wave(const SolveTask* _
       pf[u] = (live && pp < pn) ? rowp[static_cast<int64_t>(p0 + pp) * tk.ld] : 0.0;
     }
     if (lane < pn) {
-      const int p = p0 + lane;
-      const int64_t src = p < tk.c ? static_cast<int64_t>(tk.first + p) : static_cast<int64_t>(sidx[tk.soff + p - tk.c]);
-      const double* vsrc = p < tk.c ? y : x;
+      double v[D];
+      bwd_entry<D>(tk, p0 + lane, sidx, y, x, xpart, v);
 #pragma unroll
-      for (int k = 0; k < D; ++k) vs[wave][lane][k] = vsrc[src * D + k];
+      for (int k = 0; k < D; ++k) vs[wave][lane][k] = v[k];
     }
     wave_lds_sync();
     if (live) {

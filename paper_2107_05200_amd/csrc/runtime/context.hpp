@@ -57,7 +57,10 @@ inline unsigned nblk(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) 
 // blocks of y rows, by the backward pass.
 struct LevelCfg {
   int32_t mode = 0, opt = 64, chunk = 0, nw = 4;  // nw: waves per block (block mode: 4, 8, 16)
-  int32_t defer = 0;  // forward only: split y-row blocks only and add their partials in the backward pass
+  // forward: split y-row blocks only and add their partials in the backward
+  // pass; backward (split levels above the lowest): the next backward launch
+  // reads the partials and writes the rows
+  int32_t defer = 0;
   bool operator==(const LevelCfg& o) const {
     return mode == o.mode && opt == o.opt && chunk == o.chunk && nw == o.nw && defer == o.defer;
   }
@@ -65,7 +68,8 @@ struct LevelCfg {
 struct LevelRun {
   int32_t mode = 0, opt = 64, nw = 4, t0 = 0, nt = 0, r0 = 0, nr = 0;  // tasks [t0, t0+nt), reductions [r0, r0+nr)
   int32_t y0 = 0, ny = 0;  // backward runs: pending forward y-row reductions [y0, y0+ny) of yred
-  bool reduce_now = true;  // forward runs: add the split partials right after the level
+  int32_t x0 = 0, nx = 0;  // backward runs: the level above's pending x-row reductions [x0, x0+nx) of xred
+  bool reduce_now = true;  // add the split partials right after the level
 };
 
 struct ffd_ctx {
@@ -159,9 +163,13 @@ struct ffd_ctx {
   SolveTask *tasks_fwd = nullptr, *tasks_bwd = nullptr, *red_fwd = nullptr, *red_bwd = nullptr;
   size_t cap_tf = 0, cap_tb = 0, cap_rf = 0, cap_rb = 0, cap_slots = 0;  // capacities (entries)
   SolveTask* yred = nullptr;  // forward y-row reductions, in the order the backward launches run them
+  SolveTask* xred = nullptr;  // deferred backward x-row reductions, likewise
+  size_t cap_xr = 0, cap_sd = 0;
+  int32_t* sidx_def = nullptr;  // structure lists with deferred rows coded (read instead of sidx
+  bool sidx_coded = false;      // by the backward launches when sidx_coded)
   double* fpart = nullptr;    // forward split partials (kept until the backward pass adds them)
   size_t cap_yr = 0, cap_fslots = 0;
-  double* solve_part = nullptr;                   // split-K partials (reused level by level)
+  double* solve_part = nullptr;                   // backward split-K partials, a region per level
   int64_t device_bytes = 0;
   std::vector<void*> allocs;
   std::vector<hipEvent_t> events;

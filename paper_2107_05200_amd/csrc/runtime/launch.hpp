@@ -87,11 +87,13 @@ void launch_fwd_block(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, con
                      h->pull_idx, b, h->y, h->ub, h->fpart);
 }
 
+inline const int32_t* bwd_sidx(const ffd_ctx* h) { return h->sidx_coded ? h->sidx_def : h->sidx; }
+
 template <int D, int OPT, int NW>
 void launch_bwd_block(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, double* x, hipStream_t s) {
-  const int grid = r.nt + (r.ny + NW - 1) / NW;
-  hipLaunchKernelGGL((k_solve_bwd<D, OPT, NW>), dim3(grid), dim3(NW * 64), 0, s, tasks, r.nt, h->Prow, h->sidx, h->y,
-                     x, h->solve_part, h->yred + r.y0, r.ny, h->fpart);
+  const int grid = r.nt + (r.ny + r.nx + NW - 1) / NW;
+  hipLaunchKernelGGL((k_solve_bwd<D, OPT, NW>), dim3(grid), dim3(NW * 64), 0, s, tasks, r.nt, h->Prow, bwd_sidx(h),
+                     h->y, x, h->solve_part, h->yred + r.y0, r.ny, h->fpart, h->xred + r.x0, r.nx, h->solve_part);
 }
 
 template <int D, int OPT>
@@ -110,8 +112,9 @@ void launch_fwd_opt(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, const
 template <int D, int OPT>
 void launch_bwd_opt(ffd_ctx* h, const LevelRun& r, const SolveTask* tasks, double* x, hipStream_t s) {
   if (r.mode == 1)
-    hipLaunchKernelGGL((k_solve_bwd_wave<D, OPT>), dim3((r.nt + r.ny + 3) / 4), dim3(kBlock), 0, s, tasks, r.nt,
-                       h->Prow, h->sidx, h->y, x, h->yred + r.y0, r.ny, h->fpart);
+    hipLaunchKernelGGL((k_solve_bwd_wave<D, OPT>), dim3((r.nt + r.ny + r.nx + 3) / 4), dim3(kBlock), 0, s, tasks,
+                       r.nt, h->Prow, bwd_sidx(h), h->y, x, h->yred + r.y0, r.ny, h->fpart, h->xred + r.x0, r.nx,
+                       h->solve_part);
   else if (r.nw == 16)
     launch_bwd_block<D, OPT, 16>(h, r, tasks, x, s);
   else if (r.nw == 8)
@@ -137,12 +140,12 @@ void launch_fwd_level(ffd_ctx* h, const LevelRun& r, const double* b, hipStream_
 template <int D>
 void launch_bwd_level(ffd_ctx* h, const LevelRun& r, double* x, hipStream_t s) {
   const SolveTask* tasks = h->tasks_bwd + r.t0;
-  if (r.nt > 0 || r.ny > 0) {
+  if (r.nt > 0 || r.ny > 0 || r.nx > 0) {
     if (r.opt == 16) launch_bwd_opt<D, 16>(h, r, tasks, x, s);
     else if (r.opt == 32) launch_bwd_opt<D, 32>(h, r, tasks, x, s);
     else launch_bwd_opt<D, 64>(h, r, tasks, x, s);
   }
-  if (r.nr > 0)
+  if (r.nr > 0 && r.reduce_now)  // otherwise the next backward launch adds them
     hipLaunchKernelGGL((k_solve_bwd_reduce<D>), dim3((r.nr + 3) / 4), dim3(kBlock), 0, s, h->red_bwd + r.r0, r.nr, x,
                        h->solve_part);
 }

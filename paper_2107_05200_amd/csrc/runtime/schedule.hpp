@@ -202,12 +202,12 @@ ffd_status build_solve_schedule(ffd_ctx* h) {
       if (h->hnodes[i].level < top && group[i] == G) group[i] = group[h->hparent[i]];
   }
   std::vector<SolveTask> tf, tb, rf, rb;
-  int64_t total_slots = 1;  // backward split partials: per group, reused level by level
+  int64_t total_slots = 1;  // backward split partials: a region per level and group (a deferring
+                            // level's partials are read by the next launch)
   int64_t fslots = 1;       // forward split partials: kept until the backward pass
   h->grun_fwd.assign(G + 1, std::vector<LevelRun>(nlev));
   h->grun_bwd.assign(G + 1, std::vector<LevelRun>(nlev));
   for (int g = 0; g <= G; ++g) {
-    int64_t gmax = 0;  // slots of this group: reused level by level, disjoint from other groups
     for (size_t l = 0; l < nlev; ++l) {
       if ((g < G) != (static_cast<int>(l) < top)) continue;
       std::vector<int32_t> nodes;
@@ -250,12 +250,19 @@ ffd_status build_solve_schedule(ffd_ctx* h) {
         if (h->xcd_lanes) xcd_order(tasks, static_cast<size_t>(run.t0), cfg.mode == 1 ? 4 : 1);
         run.nt = static_cast<int32_t>(tasks.size()) - run.t0;
         run.nr = static_cast<int32_t>(red.size()) - run.r0;
-        run.reduce_now = !fwd || !cfg.defer || l + 1 == nlev;
+        // a backward level defers to the next backward launch of its stream
+        // (there is none after level 0, nor after the top group's lowest
+        // level when the forest below runs on several streams)
+        const bool bwd_defer = !fwd && cfg.defer && l >= 1 && (g < G || static_cast<int>(l) - 1 >= top) &&
+                               run.nr > 0 && base + slots <= kDeferSlotLimit;
+        run.reduce_now = fwd ? (!cfg.defer || l + 1 == nlev) : !bwd_defer;
+        if (bwd_defer)
+          for (int32_t q = 0; q < run.nr; ++q)
+            if (red[run.r0 + q].nk > kDeferNkMax) run.reduce_now = true;
         if (fwd) fslots += slots;
-        else gmax = std::max<int64_t>(gmax, slots);
+        else total_slots += slots;
       }
     }
-    total_slots += gmax;
   }
   const int64_t max_slots = total_slots;
   // forward y-row reductions of level l run in the backward launch of level
@@ -281,6 +288,44 @@ ffd_status build_solve_schedule(ffd_ctx* h) {
         attach(br, g, l - 1);
       }
     }
+  // deferred backward reductions: appended to the next backward launch of
+  // the same stream, whose structure lists read those rows from the partials
+  std::vector<SolveTask> xr;
+  std::vector<int32_t> coded;
+  {
+    const std::vector<int32_t>& sidx_h = h->hstruct->struct_idx;
+    std::vector<int32_t> rowcode;
+    for (int g = 0; g <= G; ++g)
+      for (size_t l = 1; l < nlev; ++l) {
+        if ((g < G) != (static_cast<int>(l) < top)) continue;
+        const LevelRun& br = h->grun_bwd[g][l];
+        if (br.reduce_now || br.nr == 0) continue;
+        LevelRun& nx = h->grun_bwd[g][l - 1];
+        nx.x0 = static_cast<int32_t>(xr.size());
+        nx.nx = br.nr;
+        if (coded.empty()) coded = sidx_h;
+        if (rowcode.empty()) rowcode.assign(static_cast<size_t>(h->nF), 0);
+        for (int32_t q = 0; q < br.nr; ++q) {
+          const SolveTask& t = rb[br.r0 + q];
+          xr.push_back(t);
+          for (int32_t ln = 0; ln < t.hi && t.out0 + ln < t.c; ++ln)
+            rowcode[t.first + t.out0 + ln] =
+                -(1 + static_cast<int32_t>((static_cast<uint32_t>(t.slot) << 12) | (static_cast<uint32_t>(ln) << 6) |
+                                           static_cast<uint32_t>(t.nk - 1)));
+        }
+        for (int32_t i : h->hlevels[l - 1]) {
+          if (group[i] != g) continue;
+          const SolveNode& N = h->hnodes[i];
+          for (int64_t e = N.soff; e < N.soff + N.r; ++e)
+            if (rowcode[sidx_h[e]] != 0) coded[e] = rowcode[sidx_h[e]];
+        }
+        for (int32_t q = 0; q < br.nr; ++q) {
+          const SolveTask& t = rb[br.r0 + q];
+          for (int32_t ln = 0; ln < t.hi && t.out0 + ln < t.c; ++ln) rowcode[t.first + t.out0 + ln] = 0;
+        }
+      }
+  }
+  h->sidx_coded = !coded.empty();
   h->solve_groups = G;
   h->solve_top = top;
   if (hipDeviceSynchronize() != hipSuccess) return fail(FFD_ERR_DEVICE, "device error before a schedule upload");
@@ -288,7 +333,9 @@ ffd_status build_solve_schedule(ffd_ctx* h) {
             upload_cap(h, &h->tasks_bwd, &h->cap_tb, tb) == hipSuccess &&
             upload_cap(h, &h->red_fwd, &h->cap_rf, rf) == hipSuccess &&
             upload_cap(h, &h->red_bwd, &h->cap_rb, rb) == hipSuccess &&
-            upload_cap(h, &h->yred, &h->cap_yr, yr) == hipSuccess;
+            upload_cap(h, &h->yred, &h->cap_yr, yr) == hipSuccess &&
+            upload_cap(h, &h->xred, &h->cap_xr, xr) == hipSuccess &&
+            upload_cap(h, &h->sidx_def, &h->cap_sd, coded) == hipSuccess;
   if (ok && static_cast<size_t>(fslots) > h->cap_fslots) {
     if (h->fpart) {
       for (auto& a : h->allocs)

@@ -148,7 +148,9 @@ def _forced(line, fwd, bwd):
 
 @pytest.mark.parametrize("fwd,bwd", [((0, 64, 256, 4, 1), (0, 64, 256, 4, 0)),
                                      ((0, 32, 256, 8, 0), (0, 16, 256, 16, 0)),
-                                     ((0, 16, 512, 4, 1), (1, 32, 0, 4, 0))])
+                                     ((0, 16, 512, 4, 1), (1, 32, 0, 4, 0)),
+                                     ((0, 64, 256, 4, 1), (0, 64, 256, 4, 1)),
+                                     ((0, 32, 256, 8, 0), (0, 16, 256, 16, 1))])
 def test_forced_split_schedules(gpu_lib, fwd, bwd, tmp_path):
     """Every level split (forward partials added right away or by the backward
     pass): the solve matches SciPy's sparse LU and twelve iterations match
@@ -191,3 +193,48 @@ def test_forced_split_schedules(gpu_lib, fwd, bwd, tmp_path):
     for k in sa:
         nrm = np.linalg.norm(np.nan_to_num(sa[k]))
         assert np.linalg.norm(np.nan_to_num(sa[k]) - np.nan_to_num(sb[k])) <= 1e-10 * max(nrm, 1e-300), k
+
+
+@pytest.mark.parametrize("case", ["cube", "batch"])
+def test_deferred_backward_reductions_are_invisible(gpu_lib, case, tmp_path):
+    """Backward split levels that leave their chunk partials to the next
+    backward launch (which reads the pending rows from them and writes the
+    rows) give bitwise the states, history and solves of the same split
+    schedule reduced after every level: one stream and several, direct
+    launches and replayed graphs."""
+    import torch
+    from paper_2107_05200_amd.binding import BatchSolver, Solver
+    if case == "batch":
+        ws = mg.batched_charts(n_charts=7, seed_c=5, m_lo=200.0, m_hi=3000.0)
+        x0 = np.concatenate([w.x0 for w in ws])
+        mk = lambda: BatchSolver(ws, precision=32)
+    else:
+        w = mg.twisted_cube(9)
+        x0 = w.x0
+        mk = lambda: Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32)
+    say(f"case: deferred backward reductions {case}")
+    base = str(tmp_path / "tune0.txt")
+    s0 = mk()
+    s0.init(x0)
+    s0.autotune(base)
+    line0 = open(base).read().strip().splitlines()[-1]
+    nlev = int(line0.split()[3])
+    ref = None
+    for defer in (0, 1):
+        line = _forced(line0, (0, 64, 256, 4, 1), (0, 32, 256, 4, defer)).strip()
+        for groups, top in ((1, nlev), (2, nlev - 1), (3, max(1, nlev - 3))):
+            c = str(tmp_path / f"tune_{defer}_{groups}_{top}.txt")
+            open(c, "w").write(_with_streams(line, groups, top))
+            for graph in (False, True):
+                s = mk()
+                s.init(x0)
+                s.autotune(c)
+                s.iterate(11, graph=graph)
+                x = s.solve(torch.ones((s.info()["n_free"], s.d), dtype=torch.float64, device="cuda"))
+                st = _state(s)
+                st["solve"] = x.cpu().numpy()
+                st["hist"] = s.history()
+                if ref is None:
+                    ref = st
+                else:
+                    _same(ref, st)

@@ -29,7 +29,7 @@ FP32_PEAK_TFLOPS = 78.6  # no packed FP32: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 # hash of the kernel sources they were measured on: a changed kernel reports
 # no traffic until it is measured again.
 MEASURED_TRAFFIC = {
-    "ef335600c3953d6b": {"solve": 3249.1e6, "local": 526.6e6,
+    "fba45cf5fd7dcd12": {"solve": 3266.3e6, "local": 525.4e6,
                          "local_flop_per_elem": 2282.0, "local_valu_per_wave": 2666.4},
 }
 

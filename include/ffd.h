@@ -85,7 +85,9 @@ typedef struct {
   const double* pinned_pos;  /* host, n_pinned x d row-major, may be NULL (then taken from the
                                 initial map in ffd_init)                                      */
   int32_t auto_pin;          /* 1: pin vertex 0 when n_pinned == 0                             */
-  int32_t leaf_size;         /* nested-dissection leaf size, 0 = automatic (60 tets, 64 tris)  */
+  int32_t leaf_size;         /* nested-dissection leaf size; 0 = automatic: 60 (tets) or 64
+                                (triangles) for the largest connected component of the free
+                                vertices, 32 for components of at most a quarter of its size */
 } ffd_options;
 
 /* Set-up statistics (filled by ffd_create / ffd_get_info). */

@@ -614,8 +614,14 @@ int build_setup(const SetupInput& in, Setup& S, std::string& err) {
       ++ncomp;
     }
     std::vector<int32_t>().swap(freev);
+    // the level count is set by the tallest tree, the largest component's:
+    // components of at most a quarter of its size take leaves of 32, which
+    // cuts their factor bytes (leaf blocks are dense) without adding levels
+    size_t nmax = 0;
+    for (const auto& mem : members) nmax = std::max(nmax, mem.size());
     for (auto& mem : members) {
       std::sort(mem.begin(), mem.end());
+      nd.leaf = in.leaf_size > 0 || 4 * mem.size() > nmax ? leaf : std::min(leaf, 32);
       std::vector<int32_t> r = nd.run(mem);
       roots.insert(roots.end(), r.begin(), r.end());
     }

@@ -182,7 +182,7 @@ def kuhn_cube(k: int):
 def height_field_uv(grid: int = 32, sigma: float = 0.02, seed_c: int = 1,
                     rho: float = 10.0, iters: int = 200,
                     energy: int = SYMMETRIC_DIRICHLET) -> Workload:
-    """Height-field UV chart (C1 at grid=32).
+    """Height-field UV chart (1,922 triangles at grid=32).
 
     Vertex (i, j), i, j in 0..grid-1, index j*grid+i, source
     V = (x, y, 0.3 sin(3x) cos(2y)) with x = i/(grid-1), y = j/(grid-1).
@@ -206,7 +206,7 @@ def height_field_uv(grid: int = 32, sigma: float = 0.02, seed_c: int = 1,
 def sphere_cap_uv(R: int = 289, seed_c: int = 2, rho: float = 10.0, iters: int = 500,
                   energy: int = SYMMETRIC_GRADIENT) -> Workload:
     """Noisy sphere cap, geodesic radius 1.2 rad, UV-mapped with the symmetric
-    gradient energy (C2 at R=289: 501,126 triangles).
+    gradient energy (501,126 triangles at R=289).
 
     A hexagonal-ring disk of R rings; ring fraction s = r/R maps to polar
     angle theta = 1.2 s and azimuth phi = 2 pi t/(6r).
@@ -235,7 +235,7 @@ def sphere_cap_uv(R: int = 289, seed_c: int = 2, rho: float = 10.0, iters: int =
 def twisted_cube(k: int = 64, twist_deg: float = 45.0, lift: float = 0.3,
                  rho: float = 10.0, iters: int = 300,
                  energy: int = SYMMETRIC_DIRICHLET) -> Workload:
-    """Tet cube deformation (C3 at k=64: 1,572,864 tets, 274,625 vertices).
+    """Tet cube deformation (1,572,864 tets, 274,625 vertices at k=64).
 
     Bottom face (z = 0) pinned at rest; top face (z = 1) rotated by
     ``twist_deg`` about the vertical axis through (0.5, 0.5) and lifted by
@@ -259,7 +259,7 @@ def twisted_cube(k: int = 64, twist_deg: float = 45.0, lift: float = 0.3,
 
 def batched_charts(n_charts: int = 256, seed_c: int = 4, m_lo: float = 200.0,
                    m_hi: float = 50000.0, rho: float = 10.0, iters: int = 200):
-    """Many independent height-field charts of uneven size (C4 at 256 charts).
+    """Many independent height-field charts of uneven size (256 charts by default).
 
     Per chart j, in order: m_j = exp(U(ln m_lo, ln m_hi)); a_j ~ U(0.1, 0.4);
     b_j, c_j ~ U(1, 4); then the initial-map noise N(0, (0.62/k_j)^2) per
@@ -293,7 +293,7 @@ def batched_charts(n_charts: int = 256, seed_c: int = 4, m_lo: float = 200.0,
 def disk_deformation(R: int = 129, n_handles: int = 16, seed_c: int = 5,
                      rho: float = 10.0, iters: int = 100,
                      energy: int = SYMMETRIC_DIRICHLET) -> Workload:
-    """2D disk deformation with displaced handles (C5 at R=129: 99,846 triangles).
+    """2D disk deformation with displaced handles (99,846 triangles at R=129).
 
     Planar hexagonal-ring disk of radius 1.  Draws: ``n_handles`` handle
     vertices without replacement, then targets V_h + N(0, 0.1^2) per
@@ -374,9 +374,9 @@ def circle_boundary(V, T, radius: float = 1.0):
     return loop, radius * np.stack([np.cos(ang), np.sin(ang)], axis=1)
 
 
-CONFIGS = {
-    "C1": lambda: height_field_uv(),
-    "C2": lambda: sphere_cap_uv(),
-    "C3": lambda: twisted_cube(),
-    "C5": lambda: disk_deformation(),
+WORKLOADS = {
+    "height_field_uv": lambda: height_field_uv(),
+    "sphere_cap_uv": lambda: sphere_cap_uv(),
+    "twisted_cube": lambda: twisted_cube(),
+    "disk_deformation": lambda: disk_deformation(),
 }

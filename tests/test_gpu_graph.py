@@ -238,3 +238,51 @@ def test_deferred_backward_reductions_are_invisible(gpu_lib, case, tmp_path):
                     ref = st
                 else:
                     _same(ref, st)
+
+
+@pytest.mark.parametrize("case", ["adjoint_disk", "constrained_cube"])
+def test_deferred_backward_reductions_in_adjoint_and_constraints(gpu_lib, case, tmp_path):
+    """The adjoint's solves and the constrained W-step run the same backward
+    launches: with every split backward level deferred, the gradients (disk,
+    float64) and the constrained iterations (cube, float32) are bitwise those
+    of the same split schedule reduced after every level."""
+    import torch
+    from paper_2107_05200_amd.binding import Solver
+    if case == "adjoint_disk":
+        w = mg.disk_deformation(R=24)
+        mk = lambda: Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=64)
+        x0 = w.V
+    else:
+        w = mg.twisted_cube(8)
+        rng = np.random.default_rng(3)
+        v = rng.choice(np.setdiff1d(np.arange(w.n), w.pinned_idx), size=6, replace=False)
+        A = np.zeros((2, w.n))
+        A[0, v[:3]] = [1.0, -0.5, -0.5]
+        A[1, v[3:]] = 1.0 / 3.0
+        c = np.stack([np.zeros(3), w.V[v[3:]].mean(axis=0) + 0.01])
+        mk = lambda: Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32, constraints=(A, c))
+        x0 = w.x0
+    say(f"case: deferred backward reductions, {case}")
+    base = str(tmp_path / "tune0.txt")
+    s0 = mk()
+    s0.init(x0)
+    s0.autotune(base)
+    line0 = open(base).read().strip().splitlines()[-1]
+    out = []
+    for defer in (0, 1):
+        c_path = str(tmp_path / f"tune_{defer}.txt")
+        open(c_path, "w").write(_forced(line0, (0, 64, 256, 4, 1), (0, 16, 256, 4, defer)))
+        s = mk()
+        s.init(x0)
+        s.autotune(c_path)
+        if case == "adjoint_disk":
+            s.init(x0).adjoint_forward(12, 4)
+            pb, vb = s.adjoint_backward(energy_loss=True)
+            torch.cuda.synchronize()
+            out.append({"pins_bar": pb.cpu().numpy(), "V_bar": vb.cpu().numpy()})
+        else:
+            s.iterate(9)
+            st = _state(s)
+            st["hist"] = s.history()
+            out.append(st)
+    _same(out[0], out[1])

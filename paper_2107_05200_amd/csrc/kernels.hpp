@@ -490,8 +490,9 @@ __global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const in
 // rounded up to even).  The first batch of panel loads is issued before the
 // LDS staging of the inner vector so the gather latency overlaps the stream.
 // Streams are added in a fixed order.  Levels that still offer too few blocks
-// split the inner ranges into chunks whose partials a reduction kernel adds in
-// chunk order (no atomics; bitwise reproducible).
+// split the inner ranges into chunks whose partials are added in chunk order
+// (no atomics; bitwise reproducible) by a reduction kernel, or by waves of a
+// later launch (see fwd_y_reduce and bwd_entry).
 // ---------------------------------------------------------------------------
 constexpr int kSolveOutMax = 64;  // outputs per task at most (partial slot stride)
 constexpr int kSolveKC = 512;     // inner entries staged in LDS at a time

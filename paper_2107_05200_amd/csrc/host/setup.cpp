@@ -1073,9 +1073,8 @@ int64_t device_panel_offsets(const Setup& S, std::vector<int64_t>& off) {
   int64_t tot = 0;
   for (size_t i = 0; i < nn; ++i) {
     const int64_t c = S.nodes[i].c, nf = S.nodes[i].c + S.nodes[i].r;
-    const int64_t ldr = (c + 1) & ~int64_t(1), ldc = (nf + 1) & ~int64_t(1);
     off[i] = tot;
-    tot += std::max(nf * ldr, c * ldc);
+    tot += nf * c;
     tot = (tot + 1) & ~int64_t(1);
   }
   return tot;
@@ -1099,7 +1098,6 @@ int64_t build_host_panels(const Setup& S, const std::vector<int64_t>& off, int64
   for (int64_t i = 0; i < static_cast<int64_t>(nn); ++i) {
     if (skip[i]) continue;
     const int64_t c = S.nodes[i].c, nf = S.nodes[i].c + S.nodes[i].r;
-    const int64_t ldr = (c + 1) & ~int64_t(1), ldc = (nf + 1) & ~int64_t(1);
     const int64_t seg = (i + 1 < static_cast<int64_t>(nn) ? off[i + 1] : tot) - off[i];
     double* R = prow.get() + coff[i];
     double* Cc = pcol.get() + coff[i];
@@ -1109,8 +1107,8 @@ int64_t build_host_panels(const Setup& S, const std::vector<int64_t>& off, int64
     for (int64_t j = 0; j < c; ++j)
       for (int64_t p = 0; p < nf; ++p) {
         const double v = src[p + j * nf];
-        R[p * ldr + j] = v;
-        Cc[j * ldc + p] = v;
+        R[panel_tile_index(j, p, c, nf)] = v;
+        Cc[panel_tile_index(p, j, nf, c)] = v;
       }
   }
   return len;

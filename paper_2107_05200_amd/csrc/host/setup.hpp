@@ -151,11 +151,20 @@ struct Setup {
 // Returns a Status; on error fills err.
 int build_setup(const SetupInput& in, Setup& out, std::string& err);
 
-// Device panel copies: for node s with c columns and nf = c + r rows, a
-// row-major copy (row length c rounded up to even) and a column-major copy
-// (column length nf rounded up to even), both at offset off[s] (even),
-// padding zero.  device_panel_offsets fills off and returns the length of
-// each copy.
+// Device panel copies, both at offset off[s] (even) for node s with c
+// columns and nf = c + r rows, tiled by kPanelTile outputs so that a solve
+// task (at most kPanelTile consecutive outputs) reads one contiguous tile:
+// the forward copy holds entry (output row i, inner column j) of tile
+// t = i / kPanelTile, height h = min(kPanelTile, nf - t kPanelTile), at
+// t kPanelTile c + j h + (i - t kPanelTile); the backward copy entry (output
+// column j, inner row p) at panel_tile_index(j, p, c, nf) likewise.
+// device_panel_offsets fills off and returns the length of each copy.
+constexpr int64_t kPanelTile = 64;
+inline int64_t panel_tile_index(int64_t out, int64_t in, int64_t nout, int64_t nin) {
+  const int64_t t = out / kPanelTile, base = t * kPanelTile;
+  const int64_t h = nout - base < kPanelTile ? nout - base : kPanelTile;
+  return base * nin + in * h + (out - base);
+}
 int64_t device_panel_offsets(const Setup& S, std::vector<int64_t>& off);
 
 // Compact host copies of the panels of the nodes not in S.top (off, tot from

@@ -9,6 +9,7 @@
 #include <cstdint>
 
 #include "device_math.hpp"
+#include "host/setup.hpp"  // the device panel layout (kPanelTile)
 
 namespace ffd {
 
@@ -484,10 +485,9 @@ __global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const in
 // inner streams; the NW waves of a block (4, 8 or 16) add streams, so a block
 // runs NS = NW * 64 / OPT interleaved streams over its inner range and every
 // wave load reads 64 / OPT runs of OPT contiguous doubles (whole 128-byte
-// lines).  The
-// forward reads a column-major copy of the panel (column length ldc = nf
-// rounded up to even), the backward a row-major copy (row length ldr = c
-// rounded up to even).  The first batch of panel loads is issued before the
+// lines).  The forward reads a copy of the panel tiled by 64 output rows,
+// the backward a copy tiled by 64 output columns: a task's entries are one
+// contiguous tile, its columns (rows) of height ld = the tile's height.  The first batch of panel loads is issued before the
 // LDS staging of the inner vector so the gather latency overlaps the stream.
 // Streams are added in a fixed order.  Levels that still offer too few blocks
 // split the inner ranges into chunks whose partials are added in chunk order
@@ -495,6 +495,14 @@ __global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const in
 // later launch (see fwd_y_reduce and bwd_entry).
 // ---------------------------------------------------------------------------
 constexpr int kSolveOutMax = 64;  // outputs per task at most (partial slot stride)
+static_assert(kSolveOutMax == kPanelTile, "a task's outputs lie in one panel tile");
+
+// entry (output, inner) of a tiled panel copy (the layout of panel_tile_index)
+__device__ __forceinline__ int64_t panel_tile_index_dev(int64_t out, int64_t in, int64_t nout, int64_t nin) {
+  const int64_t t = out / kPanelTile, base = t * kPanelTile;
+  const int64_t h = nout - base < kPanelTile ? nout - base : kPanelTile;
+  return base * nin + in * h + (out - base);
+}
 constexpr int kSolveKC = 512;     // inner entries staged in LDS at a time
 constexpr int kSolveBatch = 8;    // panel loads in flight per lane
 
@@ -1618,15 +1626,14 @@ __global__ __launch_bounds__(kBlock) void k_lower_copy(int64_t n, const double* 
 // row-major (ld ldr) copies at offset pf
 __global__ __launch_bounds__(kBlock) void k_front_panels(int64_t c, int64_t r, const double* __restrict Linv,
                                                          const double* __restrict M, int64_t pf,
-                                                         double* __restrict Pcol, int64_t ldc,
-                                                         double* __restrict Prow, int64_t ldr) {
+                                                         double* __restrict Pcol, double* __restrict Prow) {
   const int64_t nf = c + r;
   const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (t >= nf * c) return;
   const int64_t p = t % nf, j = t / nf;
   const double v = p < c ? (p >= j ? Linv[p + j * c] : 0.0) : -M[(p - c) + j * r];
-  Pcol[pf + p + j * ldc] = v;
-  Prow[pf + j + p * ldr] = v;
+  Pcol[pf + panel_tile_index_dev(p, j, nf, c)] = v;  // forward copy: output row p, inner column j
+  Prow[pf + panel_tile_index_dev(j, p, c, nf)] = v;  // backward copy: output column j, inner row p
 }
 
 // right-hand side of a solve whose only data are the fixed rows: b_F = -L_FC x_C

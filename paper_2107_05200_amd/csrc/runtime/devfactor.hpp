@@ -190,7 +190,7 @@ ffd_status device_factor_top(ffd_ctx* h, const Setup& S, hipStream_t s) {
                        static_cast<rocblas_int>(r)));
     }
     hipLaunchKernelGGL(k_front_panels, blocks(nf * c), dim3(kBlock), 0, s, c, r, Li, M, h->hpoff[T.node], h->Pcol,
-                       static_cast<int64_t>((nf + 1) & ~1), h->Prow, static_cast<int64_t>((c + 1) & ~1));
+                       h->Prow);
     HIP_TRY(hipGetLastError());
   }
   std::vector<int32_t> hinfo(2 * ntop);

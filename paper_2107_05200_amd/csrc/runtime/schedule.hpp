@@ -107,9 +107,9 @@ void xcd_order(std::vector<SolveTask>& tasks, size_t t0, int g) {
   const size_t nt = tasks.size() - t0;
   if (nt < static_cast<size_t>(2 * X * g)) return;
   std::vector<std::vector<SolveTask>> byn;
-  std::unordered_map<int64_t, size_t> slot_of;  // node (panel offset) -> its list
+  std::unordered_map<int64_t, size_t> slot_of;  // node (first row) -> its list
   for (size_t t = t0; t < tasks.size(); ++t) {
-    const auto it = slot_of.emplace(tasks[t].pf, byn.size());
+    const auto it = slot_of.emplace(tasks[t].first, byn.size());
     if (it.second) byn.emplace_back();
     byn[it.first->second].push_back(tasks[t]);
   }
@@ -158,11 +158,14 @@ ffd_status build_solve_schedule(ffd_ctx* h) {
     const SolveNode& N = h->hnodes[o.node];
     const int32_t nf = N.c + N.r;
     SolveTask t{};
-    t.pf = h->hpoff[o.node];
+    // the task's tile of the panel copy: base shifted so that output i sits
+    // at pf + i + j * ld (outputs of one task never cross a tile)
+    const int64_t tile = (o.out0 / kPanelTile) * kPanelTile, nout = fwd ? nf : N.c, nin = fwd ? N.c : nf;
+    t.pf = h->hpoff[o.node] + tile * nin - tile;
     t.poff = N.poff;
     t.uoff = N.uoff;
     t.soff = N.soff;
-    t.ld = fwd ? ((nf + 1) & ~1) : ((N.c + 1) & ~1);
+    t.ld = static_cast<int32_t>(std::min<int64_t>(kPanelTile, nout - tile));
     t.first = N.first;
     t.c = N.c;
     t.nf = nf;

@@ -765,9 +765,12 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
       const double tb = time_solve_pass(h, s, false, 3);
       return pass == 0 ? time_solve_pass(h, s, true, 3) + tb : tb;
     };
+    // two sweeps; each level's current choice is timed afresh before its
+    // candidates (a stale minimum from earlier levels would favour it), and a
+    // candidate must beat it by 0.5%
+    for (int sweep = 0; sweep < 2; ++sweep)
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<LevelCfg>& cfg = pass == 0 ? h->cfg_fwd : h->cfg_bwd;
-      double tcur = timed(pass);
       for (size_t l = 0; l < nlev; ++l) {
         int64_t max_inner = 0;
         for (const OutBlock& o : level_blocks(h, h->hlevels[l], pass == 0, 64))
@@ -782,6 +785,9 @@ ffd_status ffd_autotune(ffd_handle h, const char* cache_path, void* stream, int3
                   if (defer == 0 || (chunk > 0 && (pass == 0 || l > 0))) cands.push_back(LevelCfg{0, opt, chunk, nw, defer});
         }
         const LevelCfg keep = cfg[l];
+        st = build_solve_schedule(h);
+        if (st != FFD_OK) return st;
+        double tcur = 0.995 * timed(pass);
         LevelCfg bestc = keep;
         for (const LevelCfg& c : cands) {
           if (c == keep) continue;

@@ -91,6 +91,9 @@ CASES = {
     "sphere_cap_sg_fp32": (lambda: mg.sphere_cap_uv(R=15), 32, 0),
     "disk_sd_fp64": (lambda: mg.disk_deformation(R=14), 64, 0),
     "cube7_sd_fp32_leaf5": (lambda: mg.twisted_cube(7), 32, 0, 5),
+    "cube5_sg_fp64_h1": (lambda: mg.twisted_cube(5, energy=mg.SYMMETRIC_GRADIENT), 64, 1),
+    "cube6_sd_fp32_h1": (lambda: mg.twisted_cube(6), 32, 1),
+    "sphere_cap_sg_fp64": (lambda: mg.sphere_cap_uv(R=15), 64, 0),
 }
 
 

@@ -67,7 +67,27 @@ def test_batch_matches_oracle_per_chart(gpu_lib):
         assert rel(st["Wel"][eo[i]:eo[i + 1]], r.wel()) < 1e-9
 
 
-def test_batch_full_c4_runs(gpu_lib):
+def test_batch_with_proximal_term_matches_oracle_per_chart(gpu_lib):
+    """h_mode 1 (the proximal term of the U-step) in a batch of charts of
+    both energies: each chart follows its own oracle (float64, 1e-9)."""
+    from paper_2107_05200_amd.binding import BatchSolver
+    ws = _charts(4, seed_c=9)
+    say(f"case: batch with h, m = {[w.m for w in ws]}, energies {[w.energy for w in ws]}")
+    bs = BatchSolver(ws, precision=64, h_mode=1)
+    vo, eo = bs.layout()
+    bs.init(np.concatenate([w.x0 for w in ws])).iterate(15)
+    st = {k: v.cpu().numpy() for k, v in bs.get_state().items()}
+    worst = 0.0
+    for i, w in enumerate(ws):
+        r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, h_mode=1)
+        r.init(w.x0)
+        r.iterate(15)
+        worst = max(worst, rel(st["map"][vo[i]:vo[i + 1]], r.x), rel(st["Wel"][eo[i]:eo[i + 1]], r.wel()))
+    say(f"  worst rel err {worst:.2e}")
+    assert worst < 1e-9
+
+
+def test_batch_full_size_runs(gpu_lib):
     """256 charts, 200..50k triangles, mixed energies, 20 iterations."""
     import torch
     from paper_2107_05200_amd.binding import BatchSolver

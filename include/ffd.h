@@ -315,7 +315,9 @@ ffd_status ffd_get_vertex_order(ffd_handle h, int32_t* order_host);
 /* Adjoint, forward part: run n_iter iterations of Algorithm 1 from the
  * current state (as ffd_iterate, appending history) and keep a device
  * checkpoint of the state every checkpoint_every iterations, for
- * ffd_adjoint_backward. */
+ * ffd_adjoint_backward.  The adjoint differentiates the iteration with
+ * mu_i = rho w_i, no general constraints and no proximal term: a rescaled
+ * handle, a constrained one and one with h_mode 1 give FFD_ERR_STATE. */
 ffd_status ffd_adjoint_forward(ffd_handle h, int32_t n_iter, int32_t checkpoint_every, void* stream);
 
 /* Adjoint, reverse part: gradients of a loss of the final element state

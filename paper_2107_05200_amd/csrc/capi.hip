@@ -579,6 +579,8 @@ ffd_status ffd_adjoint_forward(ffd_handle h, int32_t n_iter, int32_t checkpoint_
   if (n_iter <= 0 || checkpoint_every <= 0) return fail(FFD_ERR_INVALID_ARG, "n_iter and checkpoint_every must be > 0");
   if (h->rescaled) return fail(FFD_ERR_STATE, "the adjoint differentiates mu_i = rho w_i: not after a rescaling");
   if (h->ncon > 0) return fail(FFD_ERR_STATE, "the adjoint is not built for general constraints");
+  if (h->h_mode != 0)
+    return fail(FFD_ERR_STATE, "the adjoint differentiates the U-step without the proximal term (h_mode 0)");
   hipStream_t s = static_cast<hipStream_t>(stream);
   ffd_status st = ensure_hist(h, h->k + n_iter, s);
   if (st != FFD_OK) return st;

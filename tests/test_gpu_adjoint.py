@@ -245,3 +245,18 @@ def test_adjoint_fullsize_central_differences(gpu_lib):
     w = mg.disk_deformation()
     say(f"case: adjoint vs central differences, full disk m={w.m} K=10")
     _fd_check(w, 10, 10, 5, 1e-6, 1e-5, 22, 10)
+
+
+def test_adjoint_refuses_the_proximal_term(gpu_lib):
+    """The adjoint differentiates the U-step without the proximal term: a
+    handle with h_mode 1 is refused (FFD_ERR_STATE), one with h_mode 0 of
+    the same mesh is not."""
+    from paper_2107_05200_amd.binding import FFDError, Solver
+    w = mg.disk_deformation(R=10)
+    s = Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=64, h_mode=1)
+    s.init(w.V)
+    with pytest.raises(FFDError):
+        s.adjoint_forward(3, 2)
+    s0 = Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=64)
+    s0.init(w.V).adjoint_forward(3, 2)
+    s0.adjoint_backward(energy_loss=True)

@@ -33,7 +33,7 @@ class FlipFreeEnergy(torch.autograd.Function):
         pb, vb = s.adjoint_backward(energy_loss=True)
         g = gout.to(torch.float64)
         gp = (pb * g.to(pb.device)).to(ctx.devices[0])
-        gv = (vb * g.to(vb.device)).to(ctx.devices[1])
+        gv = None if vb is None else (vb * g.to(vb.device)).to(ctx.devices[1])
         ctx.solver = None
         s.close()
         return gp, gv, None, None, None, None, None, None, None

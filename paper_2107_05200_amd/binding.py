@@ -190,6 +190,7 @@ class Solver:
         V = np.asarray(V)
         T = np.asarray(T)
         self.d = T.shape[1] - 1
+        self.din = V.shape[1]
         self.n = V.shape[0]
         self.m = T.shape[0]
         self.precision = precision
@@ -358,13 +359,14 @@ class Solver:
 
     def adjoint_backward(self, Pbar=None, energy_loss: bool = True, stream=None):
         """Gradients (pins_bar (n_pinned, d), V_bar (n, d), float64 device tensors) of
-        sum_i w_i f(P_i^K) (energy_loss) plus <Pbar, P^K> through the last adjoint_forward."""
+        sum_i w_i f(P_i^K) (energy_loss) plus <Pbar, P^K> through the last adjoint_forward.
+        V_bar is None for a surface map (rest vertices in 3D, map in 2D)."""
         import torch
         pb = torch.zeros((max(self.n_pinned, 1), self.d), dtype=torch.float64, device=self.device)
-        vb = torch.zeros((self.n, self.d), dtype=torch.float64, device=self.device)
+        vb = torch.zeros((self.n, self.d), dtype=torch.float64, device=self.device) if self.din == self.d else None
         Pt = None if Pbar is None else self._dev(Pbar, self.dtype).reshape(self.m, self.d, self.d)
         _check(self.lib.ffd_adjoint_backward(self.h, C.c_void_p(_dptr(Pt)), int(bool(energy_loss)),
-                                             C.c_void_p(pb.data_ptr()), C.c_void_p(vb.data_ptr()),
+                                             C.c_void_p(pb.data_ptr()), C.c_void_p(_dptr(vb)),
                                              _stream(stream)))
         return pb[: self.n_pinned], vb
 
@@ -386,6 +388,7 @@ class BatchSolver(Solver):
         self.lib = load()
         ws = list(workloads)
         self.d = ws[0].T.shape[1] - 1
+        self.din = ws[0].V.shape[1]
         self.n = int(sum(w.V.shape[0] for w in ws))
         self.m = int(sum(w.T.shape[0] for w in ws))
         self.precision = precision

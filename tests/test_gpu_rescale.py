@@ -251,3 +251,34 @@ def test_device_refactorisation_matches_host(gpu_lib, case):
     e = max(rel(states[0][k], states[1][k]) for k in ("map", "Wel", "Lam"))
     say(f"  device vs host rel diff {e:.2e}")
     assert e < 1e-11
+
+
+def test_batch_run_stops_where_the_oracle_stops(gpu_lib):
+    """Algorithm 2 with rescaling on a batch of three SD charts: the
+    termination test and the events act on the whole batch, so the device run
+    stops where the oracle's run on the union of the charts (one mesh of
+    three components) stops, after the same number of events (float64)."""
+    import torch
+    from paper_2107_05200_amd.binding import BatchSolver
+    ws = mg.batched_charts(n_charts=6, seed_c=12, m_lo=200.0, m_hi=1200.0)[0::2]
+    assert all(w.energy == ws[0].energy for w in ws)
+    say(f"case: batch Algorithm 2, m = {[w.m for w in ws]}")
+    voff = np.cumsum([0] + [w.n for w in ws])
+    V = np.vstack([w.V for w in ws])
+    T = np.vstack([w.T + voff[i] for i, w in enumerate(ws)])
+    pins = np.concatenate([w.pinned_idx + voff[i] for i, w in enumerate(ws)])
+    ppos = np.vstack([w.pinned_pos for w in ws])
+    x0 = np.vstack([w.x0 for w in ws])
+    r = O.OracleSolver(V, T, ws[0].energy, ws[0].rho, pins, ppos)
+    r.init(x0)
+    expect = r.run(400, check_every=10, eps_abs=1e-6, eps_rel=1e-5, flip_free=True, rescale=True, rho_r=5.0)
+    bs = BatchSolver(ws, precision=64)
+    bs.init(x0)
+    got = bs.run(400, check_every=10, eps_abs=1e-6, eps_rel=1e-5, flip_free=True, rescale_rho=5.0)
+    say(f"  device (iterations, converged, events) {got}, oracle {expect}")
+    assert got == expect
+    st = bs.get_state()
+    torch.cuda.synchronize()
+    ex = rel(host(st["map"]), r.x)
+    say(f"  final map rel err {ex:.2e}")
+    assert ex < 1e-7

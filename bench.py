@@ -112,9 +112,10 @@ def cpu_baseline(w, state, n_sample: int, passes: int):
 def oracle_iteration_rates():
     """The oracle's whole iterations (W-step with its sparse LU, element steps,
     diagnostics) where it can factor L_FF: the 32x32 height field (float64,
-    20 iterations) and the sphere cap (501,126 triangles, set-up and 4
-    iterations), one thread, beside the device's plain iterations of the same
-    workloads (float64 and float32 element steps, as in the parity tests)."""
+    20 iterations), the sphere cap (501,126 triangles, set-up and 4
+    iterations) and the tet cube at 16^3 (set-up and 5 iterations), one
+    thread, beside the device's plain iterations of the same workloads
+    (float64 and float32 element steps, as in the parity tests)."""
     import numpy as np
     import torch
     from threadpoolctl import threadpool_limits
@@ -124,7 +125,8 @@ def oracle_iteration_rates():
     rows = {}
     for label, mk, k_cpu, k_gpu, prec in (
             ("height field UV, 1,922 triangles, SD", lambda: meshgen.height_field_uv(), 20, 200, 64),
-            ("sphere cap UV, 501,126 triangles, SG", lambda: meshgen.sphere_cap_uv(), 4, 200, 32)):
+            ("sphere cap UV, 501,126 triangles, SG", lambda: meshgen.sphere_cap_uv(), 4, 200, 32),
+            ("twisted tet cube 16^3, 24,576 tets, SD", lambda: meshgen.twisted_cube(16), 5, 200, 32)):
         w = mk()
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()

@@ -16,3 +16,4 @@ supplement.  It is plain NumPy / SciPy in float64; library primitives
 from .admm import *  # noqa: F401,F403
 from . import adjoint  # noqa: F401
 from . import tutte  # noqa: F401
+from . import ordering  # noqa: F401

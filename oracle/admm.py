@@ -18,6 +18,8 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from .ordering import SymmetricSolve
+
 __all__ = [
     "EPS_M", "SD", "SG", "element_geometry", "gradient_operator", "global_matrix",
     "jacobians", "energy_density", "energy_of_spd_eigs", "grad_norm_sq_of_spd_eigs",
@@ -423,6 +425,7 @@ class OracleSolver:
         self.L_FF = self.L[self.free][:, self.free].tocsc()
         self.L_FC = self.L[self.free][:, pins].tocsr()
         self._lu = None  # factorised at the first W-step (once: mu is fixed)
+        self.problems = None  # one problem: the whole mesh (set_problems)
         self.k = 0
         self.history = History()
 
@@ -491,11 +494,13 @@ class OracleSolver:
 
     def run(self, max_iter: int, check_every: int = 1, eps_abs: float = 1e-6, eps_rel: float = 1e-5,
             flip_free: bool = True, rescale: bool = True, rho_r: float = 5.0):
-        """Algorithm 2 (the paper's implementation of Algorithm 1): iterate,
-        rescale at the iterations of rescale_schedule, and stop at the first
-        check iteration (every check_every-th, not a rescaling one) whose
-        record meets eq. primaldualthresholds (and the flip-free condition).
-        Returns (iterations run, converged, rescaling events)."""
+        """Algorithm 2 (the paper's implementation of Algorithm 1): iterate;
+        after the iterations of rescale_schedule rescale mu and Lambda; then, in
+        the same iteration and after any rescaling (the order of Algorithm 2's
+        loop body), take the termination test at every check_every-th
+        iteration: eq. primaldualthresholds plus the flip-free condition, on
+        the state as it stands (termination_values).  Returns (iterations run,
+        converged, rescaling events)."""
         events = set(rescale_schedule(max_iter)) if rescale else set()
         nres = 0
         for k in range(1, max_iter + 1):
@@ -503,13 +508,60 @@ class OracleSolver:
             if k in events:
                 self.rescale(rho_r)
                 nres += 1
-                continue
-            if k % check_every == 0:
-                pr, du = self.thresholds(eps_abs, eps_rel)
-                h = self.history.array()[-1]
-                if h[0] < pr and h[1] < du and (not flip_free or h[5] == 0):
-                    return k, True, nres
+            if k % check_every == 0 and self.termination_test(eps_abs, eps_rel, flip_free):
+                return k, True, nres
         return max_iter, False, nres
+
+    def set_problems(self, element_offsets, vertex_offsets):
+        """Declare the mesh a union of independent problems (a batch): problem
+        c owns elements [element_offsets[c], element_offsets[c+1]) and vertices
+        [vertex_offsets[c], vertex_offsets[c+1]).  The termination test is
+        then taken per problem (each with its own m), and passes when it
+        passes for every problem."""
+        self.problems = list(zip(element_offsets[:-1], element_offsets[1:], vertex_offsets[:-1], vertex_offsets[1:]))
+        return self
+
+    def termination_values(self, problem=None):
+        """The quantities of Algorithm 2's termination test for the current
+        state (W^k, U^k, P^k, Lambda^k) with the current penalties mu: e_prim
+        and e_dual of eq. primaldualerror, |G W^k|, |P^k| and |G^T Lambda^k| of
+        eq. primaldualthresholds, the number of elements with det J <= 0, and
+        m; over the whole mesh or over problem (e0, e1, v0, v1) (its elements
+        and its vertex rows).  Reading: after a rescaling event of the same
+        iteration, e_dual uses the new mu_i and |G^T Lambda| the rescaled
+        Lambda (e_prim, |G W|, |P| and the flips do not depend on mu or
+        Lambda); otherwise these are the values of the iteration's history
+        record."""
+        e0, e1, v0, v1 = problem if problem is not None else (0, self.m, 0, self.n)
+        J = jacobians(self.G, self.x, self.d)[e0:e1]
+        J_prev = jacobians(self.G, self.x_prev, self.d)[e0:e1]
+        UP = (self.U @ self.P)[e0:e1]
+        GtLam = np.asarray(self.G.T @ self.Lam.reshape(self.m * self.d, self.d))[v0:v1]
+        mu = self.mu[e0:e1]
+        return {"e_prim": math.sqrt(np.sum((J - UP) ** 2)),
+                "e_dual": math.sqrt(np.sum(mu[:, None, None] ** 2 * (J - J_prev) ** 2)),
+                "norm_GW": math.sqrt(np.sum(J * J)), "norm_P": math.sqrt(np.sum(self.P[e0:e1] ** 2)),
+                "norm_GtLam": math.sqrt(np.sum(GtLam ** 2)),
+                "flips": int(np.sum(np.linalg.det(J) <= 0)), "m": e1 - e0}
+
+    def thresholds(self, eps_abs=1e-6, eps_rel=1e-5, problem=None):
+        """Primal / dual thresholds of eq. primaldualthresholds for the current
+        state: eps_abs sqrt(d m) + eps_rel max(|G W|, |P|) and eps_abs sqrt(d m)
+        + eps_rel |G^T Lambda| (sqrt(d m) as printed; m of the problem)."""
+        v = self.termination_values(problem)
+        base = eps_abs * math.sqrt(self.d * v["m"])
+        return base + eps_rel * max(v["norm_GW"], v["norm_P"]), base + eps_rel * v["norm_GtLam"]
+
+    def termination_test(self, eps_abs=1e-6, eps_rel=1e-5, flip_free=True):
+        """Algorithm 2's termination condition: both residuals below their
+        thresholds and, with flip_free, no element with det J <= 0; for a
+        union of problems, for each of them."""
+        for pr in (self.problems if self.problems else [None]):
+            v = self.termination_values(pr)
+            prim, dual = self.thresholds(eps_abs, eps_rel, pr)
+            if not (v["e_prim"] < prim and v["e_dual"] < dual and (not flip_free or v["flips"] == 0)):
+                return False
+        return True
 
     # -- sub-steps -----------------------------------------------------------
     def w_step(self, U, P, Lam):
@@ -526,8 +578,8 @@ class OracleSolver:
         if self.free.size == 0:  # every vertex fixed: the W-step is the constraint itself
             return x
         if self.A is None:
-            if self._lu is None:
-                self._lu = spla.splu(self.L_FF)
+            if self._lu is None:  # SPD: nested-dissection order (oracle/ordering.py), then SuperLU
+                self._lu = SymmetricSolve(self.L_FF, self.V[self.free])
             x[self.free] = self._lu.solve(b)
             return x
         AF = self.A[:, self.free]
@@ -594,16 +646,6 @@ class OracleSolver:
         return [e_prim, e_dual, E_P, E_map, Phi, flips, nonfinite,
                 math.sqrt(np.sum(J * J)), math.sqrt(np.sum(self.P ** 2)),
                 math.sqrt(np.sum(GtLam ** 2)), gmax]
-
-    def thresholds(self, eps_abs=1e-6, eps_rel=1e-5):
-        """Primal / dual thresholds of eq. primaldualthresholds for the last
-        iterate (sqrt(d m) as printed; recorded only, never used to stop)."""
-        h = self.history.array()[-1]
-        f = HIST_FIELDS
-        base = eps_abs * math.sqrt(self.d * self.m)
-        prim = base + eps_rel * max(h[f.index("norm_GW")], h[f.index("norm_P")])
-        dual = base + eps_rel * h[f.index("norm_GtLam")]
-        return prim, dual
 
     def wel(self):
         """Per-element U_i P_i (the flip-free Jacobian estimate)."""

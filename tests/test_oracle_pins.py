@@ -641,3 +641,237 @@ def test_diagnostic_proxies_closed_forms():
     R = np.linalg.qr(rng.normal(size=(3, 3)))[0]
     rot = lambda X: R @ X @ R.T
     assert np.allclose(O.lambda_ratio(rot(U0), rot(L0), rot(U1), rot(L1)), O.lambda_ratio(U0, L0, U1, L1), rtol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 2: energies, Phi, thresholds, stop rule, rescaling direction,
+# flipped initialisation
+# ----------------------------------------------------------------------------
+
+def _rand_rot(r, d, n):
+    Q = np.linalg.qr(r.normal(size=(n, d, d)))[0]
+    Q[np.linalg.det(Q) < 0, :, 0] *= -1.0
+    return Q
+
+
+def test_energy_density_closed_forms():
+    """f at matrices whose values follow by hand from Table 1's definitions
+    (SD: 1/2(|X|^2 + |X^-1|^2), SG: 1/2|X|^2 - log det X), for X = R1 S R2
+    with rotations R1, R2 (f depends on the singular values only), a shear
+    with det 1 and |X|^2 = |X^-1|^2 = 3, and +inf for det X <= 0."""
+    r = rng(21)
+    for d, S, sd, sg in ((2, [2.0, 1.0], 3.125, 2.5 - math.log(2.0)),
+                         (3, [2.0, 1.0, 1.0], 4.125, 3.0 - math.log(2.0)),
+                         (3, [0.5, 2.0, 3.0], 0.5 * (13.25 + 4.0 + 0.25 + 1 / 9), 0.5 * 13.25 - math.log(3.0))):
+        X = _rand_rot(r, d, 8) @ np.diag(S) @ _rand_rot(r, d, 8)
+        assert np.allclose(O.energy_density(X, O.SD), sd, rtol=1e-13)
+        assert np.allclose(O.energy_density(X, O.SG), sg, rtol=1e-13)
+        Xf = X.copy()
+        Xf[:, :, 0] *= -1.0
+        assert np.all(np.isinf(O.energy_density(Xf, O.SD))) and np.all(np.isinf(O.energy_density(Xf, O.SG)))
+    shear = np.array([[[1.0, 1.0], [0.0, 1.0]]])
+    assert O.energy_density(shear, O.SD)[0] == pytest.approx(3.0, rel=1e-15)
+    assert O.energy_density(shear, O.SG)[0] == pytest.approx(1.5, rel=1e-15)
+    # the eigenvalue form used for E_P agrees with the matrix form on S+
+    P = np.diag([0.5, 2.0, 3.0])[None]
+    for e in (O.SD, O.SG):
+        assert O.energy_of_spd_eigs(np.array([[0.5, 2.0, 3.0]]), e)[0] == pytest.approx(
+            O.energy_density(P, e)[0], rel=1e-15)
+
+
+@pytest.mark.parametrize("energy", [O.SD, O.SG])
+def test_history_phi_is_the_augmented_lagrangian(energy):
+    """Field Phi of each history record equals eq. augmentedlagrangian
+    evaluated at the state the iteration produced, (W^k, U^k, P^k, Lambda^k),
+    with f(P) in its matrix form."""
+    w = mg.height_field_uv(grid=10, energy=energy)
+    s = O.OracleSolver(w.V, w.T, energy, w.rho, w.pinned_idx, w.pinned_pos)
+    s.init(w.x0)
+    for _ in range(12):
+        s.iterate(1)
+        J = O.jacobians(s.G, s.x, s.d)
+        R = J - s.U @ s.P + s.Lam
+        phi = np.sum(s.w * O.energy_density(s.P, energy)
+                     + 0.5 * s.mu * (np.sum(R * R, axis=(1, 2)) - np.sum(s.Lam * s.Lam, axis=(1, 2))))
+        assert s.history.col("Phi")[-1] == pytest.approx(phi, rel=1e-12)
+
+
+def test_thresholds_use_sqrt_dm():
+    """eq. primaldualthresholds: eps_abs sqrt(d m).  The 32x32 chart has
+    d m = 2 * 1922 = 3844 = 62^2; the flat 8x8 grid d m = 2 * 98 = 196 = 14^2
+    and, at its identity fixed point (J = P = I, Lambda = 0), |G W| = |P| =
+    sqrt(d m) = 14 and |G^T Lambda| = 0."""
+    w = mg.height_field_uv()
+    s = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+    s.init(w.x0)
+    s.iterate(2)
+    assert s.thresholds(1.0, 0.0) == pytest.approx((62.0, 62.0), rel=1e-15)
+    f = mg.flat_grid(8)
+    t = O.OracleSolver(f.V, f.T, f.energy, f.rho, f.pinned_idx, f.pinned_pos)
+    t.init(f.x0)
+    t.iterate(1)
+    assert t.thresholds(1.0, 0.0) == pytest.approx((14.0, 14.0), rel=1e-15)
+    prim, dual = t.thresholds(0.0, 1.0)
+    assert prim == pytest.approx(14.0, rel=1e-13) and abs(dual) < 1e-12
+
+
+@pytest.mark.parametrize("check_every,flip_free", [(1, True), (7, True), (1, False)])
+def test_run_stop_iteration_by_hand(check_every, flip_free):
+    """Without rescaling, Algorithm 2 stops at the first check iteration whose
+    record meets both inequalities of eq. primaldualthresholds (and, with
+    flip_free, has no flipped element): the rule applied by hand to the
+    history of a plain run, with sqrt(d m) = 62 on the 32x32 chart."""
+    w = mg.height_field_uv()
+    a = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+    a.init(w.x0)
+    done, conv, nres = a.run(400, check_every=check_every, eps_abs=1e-6, eps_rel=1e-5,
+                             flip_free=flip_free, rescale=False)
+    b = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+    b.init(w.x0)
+    b.iterate(400)
+    H = b.history.array()
+    prim = H[:, 0] < 1e-6 * 62.0 + 1e-5 * np.maximum(H[:, 7], H[:, 8])
+    dual = H[:, 1] < 1e-6 * 62.0 + 1e-5 * H[:, 9]
+    ok = prim & dual & ((H[:, 5] == 0) | (not flip_free))
+    ks = np.arange(1, 401)
+    hit = ks[ok & (ks % check_every == 0)]
+    assert conv and nres == 0 and hit.size > 0 and done == hit[0]
+    # the two inequalities are met at different iterations, so swapping
+    # "and" for "or" or dropping one would move the stop
+    assert np.any(prim[:done - 1] != dual[:done - 1])
+
+
+def test_run_takes_the_test_on_rescaling_iterations():
+    """Algorithm 2 evaluates the termination condition after the rescaling
+    block of the same iteration.  From the identity fixed point of the flat
+    grid (both residuals 0 at every iteration) the run must stop at
+    iteration 1, which is also the first rescaling event."""
+    f = mg.flat_grid(8)
+    t = O.OracleSolver(f.V, f.T, f.energy, f.rho, f.pinned_idx, f.pinned_pos)
+    t.init(f.x0)
+    assert t.run(20, check_every=1, rescale=True) == (1, True, 1)
+
+
+def _rescale_state(rho, dims):
+    w = mg.height_field_uv(grid=12, rho=rho) if dims == 2 else mg.twisted_cube(3, rho=rho)
+    s = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+    s.init(w.x0)
+    s.iterate(4)
+    return s
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_rescale_direction_by_construction(dims):
+    """The rescaling passage: e_prim_i > 5 e_dual_i multiplies mu_i by 5/2 and
+    divides Lambda_i by 5/2; e_dual_i > 5 e_prim_i divides mu_i by 5/2 and
+    multiplies Lambda_i by it.  States are built so that every element is on
+    one side: W^k = W^{k-1} gives e_dual_i = 0 < e_prim_i (all up);
+    U_i P_i = J_i (the polar factors of J_i) gives e_prim_i ~ 0 < e_dual_i
+    (all down).  rho = 1000 keeps mu_i far above the floor.  After a uniform
+    factor s the post-event test values scale as e_dual * s and
+    |G^T Lambda| / s."""
+    s = _rescale_state(1000.0, dims)
+    x, xp, U, P, L = s.x.copy(), s.x_prev.copy(), s.U.copy(), s.P.copy(), s.Lam.copy()
+    mu0 = s.mu.copy()
+    # all up: no change of the map in the last iteration
+    s.set_state(x, U, P, L, x_prev=x)
+    J = O.jacobians(s.G, x, s.d)
+    assert np.all(np.sqrt(np.sum((J - U @ P) ** 2, axis=(1, 2))) > 0)
+    v0 = s.termination_values()
+    s.rescale(5.0)
+    assert np.allclose(s.mu, 2.5 * mu0, rtol=1e-15)
+    assert np.allclose(s.Lam, L / 2.5, rtol=1e-15, atol=0)
+    v1 = s.termination_values()
+    assert v1["norm_GtLam"] == pytest.approx(v0["norm_GtLam"] / 2.5, rel=1e-13)
+    assert v1["e_prim"] == v0["e_prim"] and v1["e_dual"] == 0.0
+    # all down: U P = J per element, the map moved in the last iteration
+    assert np.all(np.linalg.det(J) > 0)
+    R1, S, R2t = np.linalg.svd(J)
+    Up, Pp = R1 @ R2t, np.transpose(R2t, (0, 2, 1)) @ (S[:, :, None] * R2t)
+    t = _rescale_state(1000.0, dims)
+    t.set_state(x, Up, Pp, L, x_prev=xp)
+    v0 = t.termination_values()
+    assert v0["e_prim"] < 1e-12 and v0["e_dual"] > 1e-3
+    t.rescale(5.0)
+    assert np.allclose(t.mu, mu0 / 2.5, rtol=1e-15)
+    assert np.allclose(t.Lam, L * 2.5, rtol=1e-15, atol=0)
+    v1 = t.termination_values()
+    assert v1["e_dual"] == pytest.approx(v0["e_dual"] / 2.5, rel=1e-13)
+    assert v1["norm_GtLam"] == pytest.approx(v0["norm_GtLam"] * 2.5, rel=1e-13)
+
+
+def test_flipped_init_is_the_closest_rotation():
+    """For a flipped J0 (det <= 0) the reading of the initialisation passage
+    gives U0 = the rotation maximising tr(U^T J0) over SO(d) (the closest
+    rotation): checked by a brute-force angle search in 2D and by Horn's
+    quaternion method in 3D (no SVD); P0 = eps I."""
+    r = rng(22)
+    J = r.normal(size=(400, 2, 2))
+    J = J[np.linalg.det(J) < 0][:60]
+    U, P, flipped = O.polar_init(J, O.SD)
+    assert np.all(flipped)
+    phis = np.linspace(0, 2 * np.pi, 400001)
+    for i in range(J.shape[0]):
+        val = np.cos(phis) * (J[i, 0, 0] + J[i, 1, 1]) + np.sin(phis) * (J[i, 1, 0] - J[i, 0, 1])
+        phi = phis[int(np.argmax(val))]
+        Ub = np.array([[math.cos(phi), -math.sin(phi)], [math.sin(phi), math.cos(phi)]])
+        assert np.abs(U[i] - Ub).max() < 1e-4
+    J = r.normal(size=(400, 3, 3))
+    J = J[np.linalg.det(J) < 0][:80]
+    U, P, flipped = O.polar_init(J, O.SG)
+    assert np.all(flipped)
+    for i in range(J.shape[0]):
+        Rh, ev = _horn(J[i])
+        assert ev[-1] - ev[-2] > 1e-6
+        assert np.abs(U[i] - Rh).max() < 1e-9
+        assert np.sum(U[i] * J[i]) == pytest.approx(ev[-1], rel=1e-12)
+    assert np.allclose(P, O.init_epsilon(O.SG) * np.eye(3), atol=1e-15)
+
+
+def test_union_of_problems_stops_when_every_problem_passes():
+    """A mesh made of two independent charts, declared as two problems, stops
+    at the first check where both charts meet eq. primaldualthresholds with
+    their own m (sqrt(2 * 98) = 14 and sqrt(2 * 1058) = 46): the later of the
+    stops found by hand from each chart's own history."""
+    ws = [mg.height_field_uv(grid=8), mg.height_field_uv(grid=24, seed_c=7)]
+    oks = []
+    for w, root in zip(ws, (14.0, 46.0)):
+        r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+        r.init(w.x0)
+        r.iterate(300)
+        H = r.history.array()
+        oks.append((H[:, 0] < 1e-6 * root + 1e-5 * np.maximum(H[:, 7], H[:, 8]))
+                   & (H[:, 1] < 1e-6 * root + 1e-5 * H[:, 9]) & (H[:, 5] == 0))
+    ks = np.arange(1, 301)
+    both = ks[oks[0] & oks[1] & (ks % 5 == 0)][0]
+    assert ks[oks[0] & (ks % 5 == 0)][0] != ks[oks[1] & (ks % 5 == 0)][0]
+    voff = np.cumsum([0] + [w.n for w in ws])
+    eoff = np.cumsum([0] + [w.m for w in ws])
+    u = O.OracleSolver(np.vstack([w.V for w in ws]), np.vstack([w.T + voff[i] for i, w in enumerate(ws)]),
+                       ws[0].energy, ws[0].rho, np.concatenate([w.pinned_idx + voff[i] for i, w in enumerate(ws)]),
+                       np.vstack([w.pinned_pos for w in ws])).set_problems(eoff, voff)
+    u.init(np.vstack([w.x0 for w in ws]))
+    assert u.run(300, check_every=5, rescale=False) == (both, True, 0)
+
+
+def test_nested_dissection_order_is_a_separator_order():
+    """The oracle's W-step permutation is a permutation of the free vertices,
+    the permuted solve returns the same x as SciPy's sparse solve of the
+    unpermuted system, and the dissection order cuts the factor's fill
+    against the natural order."""
+    import scipy.sparse.linalg as spla
+    from oracle import ordering
+    w = mg.twisted_cube(6)
+    s = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+    A = s.L_FF.tocsr()
+    X = w.V[s.free]
+    p = ordering.nested_dissection(A, X, leaf=16)
+    assert np.array_equal(np.sort(p), np.arange(A.shape[0]))
+    b = rng(31).normal(size=(A.shape[0], 3))
+    x = ordering.SymmetricSolve(A, X).solve(b)
+    assert np.linalg.norm(x - spla.spsolve(A.tocsc(), b)) <= 1e-12 * np.linalg.norm(x)
+    # an ordering by dissection has a lower-triangular factor much sparser than the natural one
+    lu_nd = spla.splu(A[p][:, p].tocsc(), permc_spec="NATURAL", diag_pivot_thresh=0.0,
+                      options=dict(SymmetricMode=True))
+    lu_nat = spla.splu(A.tocsc(), permc_spec="NATURAL", diag_pivot_thresh=0.0, options=dict(SymmetricMode=True))
+    assert lu_nd.L.nnz < 0.7 * lu_nat.L.nnz

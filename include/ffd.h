@@ -227,12 +227,15 @@ ffd_status ffd_iterate_graph(ffd_handle h, int32_t n_iter, void* stream);
 
 /* Algorithm 2's loop with its termination test: up to max_iter iterations;
  * every check_every-th iteration (and the last) also records |G^T Lambda|
- * (history field 9, otherwise NaN) and the loop stops once that record meets
+ * (history field 9, otherwise NaN) and the loop stops once the state meets
  * both thresholds of eq. primaldualthresholds,
  *   e_prim < eps_abs sqrt(d m) + eps_rel max(|G W|, |P|),
  *   e_dual < eps_abs sqrt(d m) + eps_rel |G^T Lambda|,
  * and, with require_flip_free, no element of the map has det J <= 0 (the
- * paper's added condition).  The paper uses eps_abs = 1e-6, eps_rel = 1e-5
+ * paper's added condition).  The test is evaluated in float64 from the state
+ * after the check iteration, per problem: on a batched handle every mesh is
+ * tested on its own (its m, its elements and vertex rows), and the loop stops
+ * when all meshes pass.  The paper uses eps_abs = 1e-6, eps_rel = 1e-5
  * (5e-10, 5e-9 for deformations).  use_graph: the iterations between checks
  * replay the captured graph (ffd_iterate_graph).  Synchronises `stream` at
  * every check.  iters_done / converged (host, may be NULL): iterations run,
@@ -268,7 +271,10 @@ ffd_status ffd_set_refactor_mode(ffd_handle h, int32_t device);
  * rescaling events (rescale_rho > 2; 0 = none) after iterations 1..5 of the
  * run and then every 5 (3/2)^p iterations (p = past events, rounded half up),
  * and the termination test of ffd_iterate_until at every check_every-th
- * iteration that is not a rescaling one.  iters_done / converged /
+ * iteration, taken in Algorithm 2's order: after the rescaling block of the
+ * same iteration, on the state as it stands (an event's new mu_i enter
+ * e_dual and its rescaled Lambda enters |G^T Lambda|).  Per problem on a
+ * batched handle, as in ffd_iterate_until.  iters_done / converged /
  * rescales_done (host, may be NULL). */
 ffd_status ffd_run(ffd_handle h, int32_t max_iter, int32_t check_every, double eps_abs, double eps_rel,
                    int32_t require_flip_free, double rescale_rho, int32_t use_graph, void* stream, int32_t* iters_done,
@@ -282,6 +288,24 @@ ffd_status ffd_run(ffd_handle h, int32_t max_iter, int32_t check_every, double e
  * and phase_ms_host[5] the total from the first to the last event. */
 #define FFD_PROFILE_FIELDS 6
 ffd_status ffd_iterate_profiled(ffd_handle h, int32_t n_iter, void* stream, double* phase_ms_host);
+
+/* Per-level timing of the W-step's two triangular-solve passes (the
+ * back-substitution of eq. solvinginw with the level-scheduled factor): n_rep
+ * timed solves of the current right-hand side (after one untimed one), with
+ * a HIP event on `stream` after every level of each pass; the solution goes
+ * to the map buffer the next W-step overwrites, so the state is unchanged.
+ * out_host (host, cap_levels x FFD_LEVEL_FIELDS float64) per level l from the
+ * leaves up: 0 forward ms, 1 backward ms (averages per solve; a level's
+ * launches include its split-partial reduction), 2 algorithmic bytes of the
+ * level's factor entries (8 (c (c + 1) / 2 + c r) per node, read once per
+ * pass), 3 nodes, 4 largest c, 5 largest r, 6 forward tasks, 7 backward
+ * tasks, 8 forward reduction tasks, 9 backward reduction tasks run right
+ * after the level.  *n_levels receives the level count.  Synchronises.
+ * Errors: FFD_ERR_INVALID_ARG when cap_levels is smaller than the level
+ * count, FFD_ERR_STATE for a schedule split over several streams. */
+#define FFD_LEVEL_FIELDS 10
+ffd_status ffd_profile_solve_levels(ffd_handle h, int32_t n_rep, void* stream, double* out_host, int32_t cap_levels,
+                                   int32_t* n_levels);
 
 /* Copy the state out; any pointer may be NULL.  map: n x d float64; Wel, U,
  * P, Lambda: m x d x d in the handle's precision. */

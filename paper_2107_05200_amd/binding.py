@@ -77,6 +77,8 @@ _PROTOS = {
     "ffd_run": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_int32,
                           C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ffd_iterate_profiled": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
+    "ffd_profile_solve_levels": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double), C.c_int32,
+                                           C.POINTER(C.c_int32)]),
     "ffd_get_state": (C.c_int, [C.c_void_p] + [C.c_void_p] * 5 + [C.c_void_p]),
     "ffd_set_state": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4 + [C.c_int64, C.c_void_p]),
     "ffd_get_history": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_double)]),
@@ -303,6 +305,17 @@ class Solver:
         _check(self.lib.ffd_iterate_profiled(self.h, int(n_iter), _stream(stream), out))
         names = ("wrhs", "solve_fwd", "solve_bwd", "local", "finalize", "total")
         return {k: out[i] for i, k in enumerate(names)}
+
+    def profile_solve_levels(self, n_rep: int = 10, stream=None) -> list:
+        """Per-level timing of both triangular-solve passes (ffd_profile_solve_levels):
+        one dict per level from the leaves up."""
+        cap = 64
+        out = (C.c_double * (cap * 10))()
+        nl = C.c_int32(0)
+        _check(self.lib.ffd_profile_solve_levels(self.h, int(n_rep), _stream(stream), out, cap, C.byref(nl)))
+        names = ("fwd_ms", "bwd_ms", "bytes", "nodes", "c_max", "r_max", "fwd_tasks", "bwd_tasks",
+                 "fwd_reduce_tasks", "bwd_reduce_tasks")
+        return [{k: out[l * 10 + i] for i, k in enumerate(names)} for l in range(nl.value)]
 
     def get_state(self, stream=None):
         """Returns dict of device tensors: map (n, d) float64; U, P, Lam, Wel (m, d, d)."""

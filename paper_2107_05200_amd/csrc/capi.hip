@@ -331,9 +331,7 @@ ffd_status ffd_iterate_until(ffd_handle h, int32_t max_iter, int32_t check_every
   if (st != FFD_OK) return st;
   if (!h->glam) HIP_TRY(h->alloc(reinterpret_cast<char**>(&h->glam), h->rsize() * h->m * (h->d + 1) * h->d));
   if (!h->gtl_part) HIP_TRY(h->alloc(&h->gtl_part, static_cast<size_t>((4 * h->n + kBlock - 1) / kBlock)));
-  const double base = eps_abs * std::sqrt(static_cast<double>(h->d) * static_cast<double>(h->m));
   int32_t done = 0, conv = 0;
-  double rec[FFD_HIST_FIELDS];
   while (done < max_iter) {
     const int32_t blk = std::min(check_every, max_iter - done);
     if (blk > 1) {
@@ -341,17 +339,16 @@ ffd_status ffd_iterate_until(ffd_handle h, int32_t max_iter, int32_t check_every
         st = ffd_iterate_graph(h, blk - 1, stream);
         if (st != FFD_OK) return st;
       } else {
-        for (int32_t it = 0; it < blk - 1; ++it) one_iteration(h, s, nullptr, true, false);
+        // the iteration before the check stores U^{k-1} for the Lambda-ratio proxy
+        for (int32_t it = 0; it < blk - 1; ++it) one_iteration(h, s, nullptr, true, it == blk - 2);
       }
     }
     one_iteration(h, s, nullptr, true, true, false, true);
     done += blk;
-    HIP_TRY(hipMemcpyAsync(rec, h->hist + (h->k - 1) * FFD_HIST_FIELDS, sizeof rec, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const bool prim = rec[0] < base + eps_rel * std::max(rec[7], rec[8]);
-    const bool dual = rec[1] < base + eps_rel * rec[9];
-    const bool flips = !require_flip_free || rec[5] == 0.0;
-    if (prim && dual && flips) {
+    bool ok = false;
+    st = check_termination(h, s, eps_abs, eps_rel, require_flip_free != 0, &ok);
+    if (st != FFD_OK) return st;
+    if (ok) {
       conv = 1;
       break;
     }
@@ -404,37 +401,35 @@ ffd_status ffd_run(ffd_handle h, int32_t max_iter, int32_t check_every, double e
       ++q;
     }
   };
-  const double base = eps_abs * std::sqrt(static_cast<double>(h->d) * static_cast<double>(h->m));
   int32_t done = 0, conv = 0, nres = 0;
-  double rec[FFD_HIST_FIELDS];
   auto plain = [&](int32_t n) -> ffd_status {
     if (n <= 0) return FFD_OK;
     if (use_graph) return ffd_iterate_graph(h, n, stream);
     for (int32_t it = 0; it < n; ++it) one_iteration(h, s, nullptr, true, it == n - 1);
     return FFD_OK;
   };
+  // Algorithm 2's loop body: the iteration, the rescaling block if the
+  // iteration is an event, then the termination test at check iterations on
+  // the state as it stands (after the event's new mu and Lambda)
   while (done < max_iter) {
     const int64_t ev = next_event(done);
     const int64_t ck = (static_cast<int64_t>(done) / check_every + 1) * check_every;
     const int32_t target = static_cast<int32_t>(std::min<int64_t>({ev, ck, static_cast<int64_t>(max_iter)}));
-    if (target == ev) {
-      st = plain(target - done);
-      if (st != FFD_OK) return st;
-      done = target;
-      st = do_rescale(h, rescale_rho, s);
-      if (st != FFD_OK) return st;
-      ++nres;
-      continue;
-    }
+    const bool is_check = target == ck, is_event = target == ev;
     st = plain(target - done - 1);
     if (st != FFD_OK) return st;
-    one_iteration(h, s, nullptr, true, true, false, target == ck);
+    one_iteration(h, s, nullptr, true, true, false, is_check);
     done = target;
-    if (target != ck) continue;
-    HIP_TRY(hipMemcpyAsync(rec, h->hist + (h->k - 1) * FFD_HIST_FIELDS, sizeof rec, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (rec[0] < base + eps_rel * std::max(rec[7], rec[8]) && rec[1] < base + eps_rel * rec[9] &&
-        (!require_flip_free || rec[5] == 0.0)) {
+    if (is_event) {
+      st = do_rescale(h, rescale_rho, s, is_check ? h->glam : nullptr);
+      if (st != FFD_OK) return st;
+      ++nres;
+    }
+    if (!is_check) continue;
+    bool ok = false;
+    st = check_termination(h, s, eps_abs, eps_rel, require_flip_free != 0, &ok);
+    if (st != FFD_OK) return st;
+    if (ok) {
       conv = 1;
       break;
     }
@@ -476,6 +471,77 @@ ffd_status ffd_iterate_profiled(ffd_handle h, int32_t n_iter, void* stream, doub
   float tot = 0.f;
   HIP_TRY(hipEventElapsedTime(&tot, h->events[0], h->events[need - 1]));
   phase_ms_host[5] = tot;
+  h->last_stream = s;
+  return FFD_OK;
+}
+
+ffd_status ffd_profile_solve_levels(ffd_handle h, int32_t n_rep, void* stream, double* out_host, int32_t cap_levels,
+                                   int32_t* n_levels) {
+  if (!h || !out_host || !n_levels) return fail(FFD_ERR_INVALID_ARG, "NULL argument");
+  if (n_rep <= 0) return fail(FFD_ERR_INVALID_ARG, "non-positive repetition count");
+  const int nlev = static_cast<int>(h->hlevels.size());
+  *n_levels = nlev;
+  if (cap_levels < nlev) return fail(FFD_ERR_INVALID_ARG, "output holds fewer levels than the schedule has");
+  if (h->solve_groups != 1) return fail(FFD_ERR_STATE, "per-level timing needs the single-stream schedule");
+  if (h->nF == 0) return fail(FFD_ERR_STATE, "no free vertices");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t need = 2 * static_cast<size_t>(nlev) + 1;
+  while (h->events.size() < need) {
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreate(&ev));
+    h->events.push_back(ev);
+  }
+  std::vector<double> ms(2 * nlev, 0.0);
+  double* xs = h->x[1 - h->cur];  // the next map buffer: overwritten by the next W-step anyway
+  const int top = h->solve_top;
+  for (int rep = 0; rep <= n_rep; ++rep) {  // the first repetition is not timed
+    HIP_TRY(hipEventRecord(h->events[0], s));
+    for (int l = 0; l < nlev; ++l) {
+      const LevelRun& r = l < top ? h->grun_fwd[0][l] : h->grun_fwd[1][l];
+      if (h->d == 2) launch_fwd_level<2>(h, r, h->b, s, r.reduce_now);
+      else launch_fwd_level<3>(h, r, h->b, s, r.reduce_now);
+      HIP_TRY(hipEventRecord(h->events[1 + l], s));
+    }
+    for (int l = nlev - 1; l >= 0; --l) {
+      const LevelRun& r = l >= top ? h->grun_bwd[1][l] : h->grun_bwd[0][l];
+      if (h->d == 2) launch_bwd_level<2>(h, r, xs, s);
+      else launch_bwd_level<3>(h, r, xs, s);
+      HIP_TRY(hipEventRecord(h->events[1 + nlev + (nlev - 1 - l)], s));
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventSynchronize(h->events[need - 1]));
+    if (rep == 0) continue;
+    for (int l = 0; l < nlev; ++l) {
+      float a = 0.f, b = 0.f;
+      HIP_TRY(hipEventElapsedTime(&a, h->events[l], h->events[1 + l]));
+      const int i = 1 + nlev + (nlev - 1 - l);
+      HIP_TRY(hipEventElapsedTime(&b, h->events[i - 1], h->events[i]));
+      ms[2 * l] += a;
+      ms[2 * l + 1] += b;
+    }
+  }
+  for (int l = 0; l < nlev; ++l) {
+    double nnz = 0.0, cmax = 0.0, rmax = 0.0;
+    for (int32_t i : h->hlevels[l]) {
+      const SolveNode& N = h->hnodes[i];
+      nnz += 0.5 * N.c * (N.c + 1.0) + static_cast<double>(N.c) * N.r;
+      cmax = std::max(cmax, static_cast<double>(N.c));
+      rmax = std::max(rmax, static_cast<double>(N.r));
+    }
+    const LevelRun& rf = l < top ? h->grun_fwd[0][l] : h->grun_fwd[1][l];
+    const LevelRun& rb = l >= top ? h->grun_bwd[1][l] : h->grun_bwd[0][l];
+    double* o = out_host + static_cast<size_t>(l) * FFD_LEVEL_FIELDS;
+    o[0] = ms[2 * l] / n_rep;
+    o[1] = ms[2 * l + 1] / n_rep;
+    o[2] = 8.0 * nnz;
+    o[3] = static_cast<double>(h->hlevels[l].size());
+    o[4] = cmax;
+    o[5] = rmax;
+    o[6] = rf.nt;
+    o[7] = rb.nt;
+    o[8] = rf.nr;
+    o[9] = rb.nr * (rb.reduce_now ? 1.0 : 0.0);
+  }
   h->last_stream = s;
   return FFD_OK;
 }

@@ -1270,7 +1270,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict pa
 // F_e of the Lipschitz lemma for B_e = sqrt(5 (1 + |grad f(P_e)|^2)) and F_e^2
 // capped at eps_m^(-1/4); the scaled dual Lambda_e is divided by the factor
 // and the next right-hand side's corner vectors are emitted again.  Decisions
-// in float64.  mu_out: the new mu_e in float64 (for the new factor).
+// in float64.  mu_out: the new mu_e in float64 (for the new factor); glam (may
+// be null): the corner vectors of the rescaled Lambda.
 template <int D, typename R, int ENERGY>
 __global__ __launch_bounds__(kBlock) void k_rescale(int64_t m, int64_t e0, int64_t e1, const int32_t* __restrict T,
                                                     const R* __restrict Bm_, const R* __restrict w,
@@ -1278,7 +1279,7 @@ __global__ __launch_bounds__(kBlock) void k_rescale(int64_t m, int64_t e0, int64
                                                     const double* __restrict xprev, const R* __restrict U,
                                                     const R* __restrict P, R* __restrict Lam,
                                                     const R* __restrict gnorm2, R* __restrict g, double rho_r,
-                                                    double* __restrict mu_out) {
+                                                    double* __restrict mu_out, R* __restrict glam) {
   const int64_t e = e0 + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (e >= e1) return;
   const double wd = static_cast<double>(w[e]);
@@ -1356,6 +1357,7 @@ __global__ __launch_bounds__(kBlock) void k_rescale(int64_t m, int64_t e0, int64
       r[a][k] = nmur * (up - L[a][k]);
     }
   store_g<D, R>(g, e, Bm, r);
+  if (glam) store_g<D, R>(glam, e, Bm, L);  // corner vectors of the rescaled Lambda (termination test)
 }
 
 // |G^T Lambda|^2 over all vertex rows (the dual threshold of eq.
@@ -1389,15 +1391,118 @@ __global__ __launch_bounds__(kBlock) void k_gtlam(int64_t n, const int32_t* __re
   block_reduce_store<1>(v, partials + blockIdx.x);
 }
 
-// history field 9 of one record: sqrt of the fixed-order sum of the partials
+// *out = sqrt of the fixed-order sum of the partials (history field 9)
 __global__ __launch_bounds__(kBlock) void k_gtlam_finalize(const double* __restrict partials, int64_t nb,
-                                                           double* __restrict rec) {
+                                                           double* __restrict out) {
   double v[1] = {0.0};
   for (int64_t bi = threadIdx.x; bi < nb; bi += kBlock) v[0] += partials[bi];
-  __shared__ double out[1];
-  block_reduce_store<1>(v, out);
+  __shared__ double red[1];
+  block_reduce_store<1>(v, red);
   __syncthreads();
-  if (threadIdx.x == 0) rec[9] = sqrt(out[0]);
+  if (threadIdx.x == 0) *out = sqrt(red[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Termination test of Algorithm 2 per problem (each mesh of a batch on its
+// own; a plain handle is one problem), from the state as it stands after the
+// iteration and any rescaling event of it: per problem, in float64, the sums
+//   0 e_prim^2 = sum |J_e - U_e P_e|^2, 1 e_dual^2 = sum mu_e^2 |J_e - J_e^prev|^2
+//   (eq. primaldualerror), 2 |G W|^2, 3 |P|^2, 4 flips (det J_e <= 0),
+//   5 |G^T Lambda|^2 over the problem's vertex rows (eq. primaldualthresholds).
+// A piece is a range of one problem's element list (kind 0) or vertex list
+// (kind 1); a null list is the identity.  Fixed-order sums.
+// ---------------------------------------------------------------------------
+constexpr int kDiagFields = 6;
+struct DiagPiece {
+  int32_t kind, q0, q1, pad;
+};
+
+template <int D, typename R>
+__global__ __launch_bounds__(kBlock) void k_diag_pieces(const DiagPiece* __restrict pieces,
+                                                        const int32_t* __restrict elist,
+                                                        const int32_t* __restrict vlist, int64_t m,
+                                                        const int32_t* __restrict T, const double* __restrict B64,
+                                                        const R* __restrict w, R rho_u, const R* __restrict rho_e,
+                                                        const double* __restrict x, const double* __restrict xprev,
+                                                        const R* __restrict U, const R* __restrict P,
+                                                        const R* __restrict glam, const int32_t* __restrict av_ptr,
+                                                        const int32_t* __restrict av_idx,
+                                                        double* __restrict part) {
+  const DiagPiece pc = pieces[blockIdx.x];
+  double v[kDiagFields] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (pc.kind == 0) {
+    for (int32_t q = pc.q0 + static_cast<int32_t>(threadIdx.x); q < pc.q1; q += kBlock) {
+      const int64_t e = elist ? elist[q] : q;
+      double E[D][D], dE[D][D];
+      const int64_t v0 = T[e];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const int64_t vj = T[(j + 1) * m + e];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          E[j][k] = x[vj * D + k] - x[v0 * D + k];
+          dE[j][k] = (x[vj * D + k] - xprev[vj * D + k]) - (x[v0 * D + k] - xprev[v0 * D + k]);
+        }
+      }
+      R Ur[D][D], Pm[D][D];
+      load_U<D, R>(U, m, e, Ur);
+      load_P<D, R>(P, m, e, Pm);
+      double J[D][D], ep = 0.0, ed = 0.0, gw = 0.0, p2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          double jv = 0.0, jd = 0.0, up = 0.0;
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
+            const double b = B64[(a * D + j) * m + e];
+            jv += b * E[j][k];
+            jd += b * dE[j][k];
+            up += static_cast<double>(Ur[a][j]) * static_cast<double>(Pm[j][k]);
+          }
+          J[a][k] = jv;
+          ep += (jv - up) * (jv - up);
+          ed += jd * jd;
+          gw += jv * jv;
+          p2 += static_cast<double>(Pm[a][k]) * static_cast<double>(Pm[a][k]);
+        }
+      const double mu = static_cast<double>(rho_e ? rho_e[e] : rho_u) * static_cast<double>(w[e]);
+      v[0] += ep;
+      v[1] += mu * mu * ed;
+      v[2] += gw;
+      v[3] += p2;
+      v[4] += det<D, double>(J) <= 0.0 ? 1.0 : 0.0;
+    }
+  } else {
+    for (int32_t q = pc.q0 + static_cast<int32_t>(threadIdx.x); q < pc.q1; q += kBlock) {
+      const int64_t j = vlist ? vlist[q] : q;
+      double acc[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc[k] = 0.0;
+      for (int32_t r = av_ptr[j]; r < av_ptr[j + 1]; ++r) {
+        const int64_t o = static_cast<int64_t>(av_idx[r]) * D;
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] += static_cast<double>(glam[o + k]);
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) v[5] += acc[k] * acc[k];
+    }
+  }
+  block_reduce_store<kDiagFields>(v, part + static_cast<int64_t>(blockIdx.x) * kDiagFields);
+}
+
+// per problem, its pieces' sums in piece order: out[c][f]
+__global__ __launch_bounds__(kBlock) void k_diag_problems(const int32_t* __restrict piece_ptr, int32_t nprob,
+                                                          const double* __restrict part, double* __restrict out) {
+  for (int32_t c = static_cast<int32_t>(blockIdx.x * kBlock + threadIdx.x); c < nprob;
+       c += static_cast<int32_t>(gridDim.x * kBlock)) {
+    double acc[kDiagFields] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int32_t p = piece_ptr[c]; p < piece_ptr[c + 1]; ++p)
+#pragma unroll
+      for (int f = 0; f < kDiagFields; ++f) acc[f] += part[static_cast<int64_t>(p) * kDiagFields + f];
+#pragma unroll
+    for (int f = 0; f < kDiagFields; ++f) out[static_cast<int64_t>(c) * kDiagFields + f] = acc[f];
+  }
 }
 
 // Several device-to-device copies in one launch (checkpoint slots of the

@@ -131,6 +131,14 @@ struct ffd_ctx {
   size_t n_pin_val = 0, n_lcf_val = 0;
   std::unique_ptr<Setup> hstruct;  // ordering and symbolic structure, reused by refactorisations
   double* gtl_part = nullptr;    // per-block partial sums of |G^T Lambda|^2
+  // termination test per problem (each mesh of a batch; a plain handle is one):
+  // pieces of the problems' element and vertex lists, their partial sums and
+  // the per-problem sums (k_diag_pieces / k_diag_problems); element count per problem
+  DiagPiece* diag_pieces = nullptr;
+  int32_t *diag_elist = nullptr, *diag_vlist = nullptr, *diag_piece_ptr = nullptr;
+  double *diag_part = nullptr, *diag_out = nullptr;
+  int32_t diag_npieces = 0, diag_nprob = 0;
+  std::vector<int64_t> diag_m;
   // general linear constraints A W = c: rows of A (device numbering; host and
   // device copies), the transposed free part over the rows it touches, the
   // right-hand sides c, per-iteration c', A y - c', lambda, the precomputed

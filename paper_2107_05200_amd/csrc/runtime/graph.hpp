@@ -20,7 +20,9 @@ ffd_status capture_graph(ffd_ctx* h) {
   const int cur0 = h->cur;
   const int64_t k0 = h->k;
   HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-  one_iteration(h, h->cap_stream, nullptr, true, true, true);
+  // the rotation (3D, h = 0: not read by the next iteration) is stored by the
+  // second iteration only, so U is current after every replay
+  one_iteration(h, h->cap_stream, nullptr, true, false, true);
   one_iteration(h, h->cap_stream, nullptr, true, true, true);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);

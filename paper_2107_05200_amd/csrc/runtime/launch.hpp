@@ -30,11 +30,12 @@ void launch_prepare(ffd_ctx* h, const ffd_ctx::Seg& g, hipStream_t s) {
 }
 
 template <int D, typename R, int E>
-void launch_rescale(ffd_ctx* h, const ffd_ctx::Seg& g, double rho_r, hipStream_t s) {
+void launch_rescale(ffd_ctx* h, const ffd_ctx::Seg& g, double rho_r, void* glam, hipStream_t s) {
   hipLaunchKernelGGL((k_rescale<D, R, E>), dim3(nblk(g.e1 - g.e0)), dim3(kBlock), 0, s, h->m, g.e0, g.e1, h->T,
                      static_cast<const R*>(h->B), static_cast<const R*>(h->w), static_cast<R*>(h->rho_e),
                      h->x[h->cur], h->x[1 - h->cur], static_cast<const R*>(h->U), static_cast<const R*>(h->P),
-                     static_cast<R*>(h->L), static_cast<const R*>(h->gn), static_cast<R*>(h->g), rho_r, h->mu_dev);
+                     static_cast<R*>(h->L), static_cast<const R*>(h->gn), static_cast<R*>(h->g), rho_r, h->mu_dev,
+                     static_cast<R*>(glam));
 }
 
 template <int D, typename R, int E, int BS>
@@ -390,7 +391,7 @@ void one_iteration(ffd_ctx* h, hipStream_t s, hipEvent_t* ev, bool record = true
         hipLaunchKernelGGL((k_gtlam<3, double>), dim3(nb), dim3(kBlock), 0, s, h->n, h->av_ptr, h->av_idx,
                            static_cast<const double*>(h->glam), h->gtl_part);
     }
-    hipLaunchKernelGGL(k_gtlam_finalize, dim3(1), dim3(kBlock), 0, s, h->gtl_part, nb, rec);
+    hipLaunchKernelGGL(k_gtlam_finalize, dim3(1), dim3(kBlock), 0, s, h->gtl_part, nb, rec + 9);
   }
   if (ev) (void)hipEventRecord(ev[4], s);
   h->cur = 1 - h->cur;

@@ -78,8 +78,9 @@ ffd_status refactor(ffd_ctx* h, const std::vector<double>* mu_dev_order, hipStre
   return FFD_OK;
 }
 
-// one rescaling event on the device, then the factor for the new penalties
-ffd_status do_rescale(ffd_ctx* h, double rho_r, hipStream_t s) {
+// one rescaling event on the device, then the factor for the new penalties;
+// glam (may be null): receives the corner vectors of the rescaled Lambda
+ffd_status do_rescale(ffd_ctx* h, double rho_r, hipStream_t s, void* glam = nullptr) {
   if (!h->rho_e) {
     HIP_TRY(h->alloc(reinterpret_cast<char**>(&h->rho_e), h->rsize() * h->m));
     HIP_TRY(h->alloc(&h->mu_dev, static_cast<size_t>(h->m)));
@@ -97,11 +98,104 @@ ffd_status do_rescale(ffd_ctx* h, double rho_r, hipStream_t s) {
     h->rescaled = true;
     h->graph_valid = false;
   }
-  for (const auto& g : h->segs) SEG_CASES(launch_rescale, h, g, rho_r, s)
+  for (const auto& g : h->segs) SEG_CASES(launch_rescale, h, g, rho_r, glam, s)
   std::vector<double> mu(h->m);
   HIP_TRY(hipMemcpyAsync(mu.data(), h->mu_dev, mu.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return refactor(h, &mu, s);
+}
+
+// Tables of the per-problem termination test (on first use): each problem's
+// element and vertex lists in device numbering (null lists for a plain
+// handle: the identity) cut into pieces of at most kDiagPiece entries.
+constexpr int32_t kDiagPiece = 4096;
+
+ffd_status build_diag(ffd_ctx* h) {
+  if (h->diag_pieces) return FFD_OK;
+  const int64_t nprob = h->voff.empty() ? 1 : static_cast<int64_t>(h->voff.size()) - 1;
+  std::vector<int32_t> elist, vlist, eptr(nprob + 1, 0), vptr(nprob + 1, 0);
+  if (nprob > 1) {
+    std::vector<int32_t> ep(h->m), vp(h->n);
+    for (int64_t e = 0; e < h->m; ++e)
+      ep[e] = static_cast<int32_t>(std::upper_bound(h->eoff.begin(), h->eoff.end(), h->enew2old_h[e]) - h->eoff.begin() - 1);
+    for (int64_t v = 0; v < h->n; ++v)
+      vp[v] = static_cast<int32_t>(std::upper_bound(h->voff.begin(), h->voff.end(), h->vnew2old[v]) - h->voff.begin() - 1);
+    for (int64_t e = 0; e < h->m; ++e) ++eptr[ep[e] + 1];
+    for (int64_t v = 0; v < h->n; ++v) ++vptr[vp[v] + 1];
+    for (int64_t c = 0; c < nprob; ++c) {
+      eptr[c + 1] += eptr[c];
+      vptr[c + 1] += vptr[c];
+    }
+    elist.resize(h->m);
+    vlist.resize(h->n);
+    std::vector<int32_t> fe(eptr.begin(), eptr.end() - 1), fv(vptr.begin(), vptr.end() - 1);
+    for (int64_t e = 0; e < h->m; ++e) elist[fe[ep[e]]++] = static_cast<int32_t>(e);
+    for (int64_t v = 0; v < h->n; ++v) vlist[fv[vp[v]]++] = static_cast<int32_t>(v);
+  } else {
+    eptr[1] = static_cast<int32_t>(h->m);
+    vptr[1] = static_cast<int32_t>(h->n);
+  }
+  std::vector<DiagPiece> pieces;
+  std::vector<int32_t> pptr{0};
+  h->diag_m.assign(nprob, 0);
+  for (int64_t c = 0; c < nprob; ++c) {
+    for (int32_t q = eptr[c]; q < eptr[c + 1]; q += kDiagPiece)
+      pieces.push_back(DiagPiece{0, q, std::min(q + kDiagPiece, eptr[c + 1]), 0});
+    for (int32_t q = vptr[c]; q < vptr[c + 1]; q += kDiagPiece)
+      pieces.push_back(DiagPiece{1, q, std::min(q + kDiagPiece, vptr[c + 1]), 0});
+    pptr.push_back(static_cast<int32_t>(pieces.size()));
+    h->diag_m[c] = eptr[c + 1] - eptr[c];
+  }
+  if (!elist.empty()) HIP_TRY(upload(h, &h->diag_elist, elist));
+  if (!vlist.empty()) HIP_TRY(upload(h, &h->diag_vlist, vlist));
+  HIP_TRY(upload(h, &h->diag_piece_ptr, pptr));
+  HIP_TRY(h->alloc(&h->diag_part, pieces.size() * kDiagFields));
+  HIP_TRY(h->alloc(&h->diag_out, static_cast<size_t>(nprob) * kDiagFields));
+  HIP_TRY(upload(h, &h->diag_pieces, pieces));
+  h->diag_npieces = static_cast<int32_t>(pieces.size());
+  h->diag_nprob = static_cast<int32_t>(nprob);
+  return FFD_OK;
+}
+
+template <int D, typename R>
+void launch_diag(ffd_ctx* h, hipStream_t s) {
+  hipLaunchKernelGGL((k_diag_pieces<D, R>), dim3(h->diag_npieces), dim3(kBlock), 0, s, h->diag_pieces,
+                     h->diag_elist, h->diag_vlist, h->m, h->T, h->B64, static_cast<const R*>(h->w),
+                     static_cast<R>(h->rho), static_cast<const R*>(h->rescaled ? h->rho_e : nullptr),
+                     h->x[h->cur], h->x[1 - h->cur], static_cast<const R*>(h->U), static_cast<const R*>(h->P),
+                     static_cast<const R*>(h->glam), h->av_ptr, h->av_idx, h->diag_part);
+}
+
+// Algorithm 2's termination test on the state as it stands (after the
+// iteration and any rescaling of it; U and the corner vectors of Lambda in
+// glam must be current): eq. primaldualthresholds and, with flip_free, no
+// flipped element, for every problem with its own sqrt(d m).  Synchronises.
+ffd_status check_termination(ffd_ctx* h, hipStream_t s, double eps_abs, double eps_rel, bool flip_free, bool* conv) {
+  ffd_status st = build_diag(h);
+  if (st != FFD_OK) return st;
+  if (h->d == 2) {
+    if (h->prec == 32) launch_diag<2, float>(h, s);
+    else launch_diag<2, double>(h, s);
+  } else {
+    if (h->prec == 32) launch_diag<3, float>(h, s);
+    else launch_diag<3, double>(h, s);
+  }
+  hipLaunchKernelGGL(k_diag_problems, dim3((h->diag_nprob + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                     h->diag_piece_ptr, h->diag_nprob, h->diag_part, h->diag_out);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> out(static_cast<size_t>(h->diag_nprob) * kDiagFields);
+  HIP_TRY(hipMemcpyAsync(out.data(), h->diag_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  bool all = true;
+  for (int32_t c = 0; c < h->diag_nprob && all; ++c) {
+    const double* v = out.data() + static_cast<size_t>(c) * kDiagFields;
+    const double base = eps_abs * std::sqrt(static_cast<double>(h->d) * static_cast<double>(h->diag_m[c]));
+    const bool prim = std::sqrt(v[0]) < base + eps_rel * std::max(std::sqrt(v[2]), std::sqrt(v[3]));
+    const bool dual = std::sqrt(v[1]) < base + eps_rel * std::sqrt(v[5]);
+    all = prim && dual && (!flip_free || v[4] == 0.0);
+  }
+  *conv = all;
+  return FFD_OK;
 }
 
 ffd_status ensure_hist(ffd_ctx* h, int64_t need, hipStream_t s) {

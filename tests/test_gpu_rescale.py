@@ -254,31 +254,85 @@ def test_device_refactorisation_matches_host(gpu_lib, case):
 
 
 def test_batch_run_stops_where_the_oracle_stops(gpu_lib):
-    """Algorithm 2 with rescaling on a batch of three SD charts: the
-    termination test and the events act on the whole batch, so the device run
-    stops where the oracle's run on the union of the charts (one mesh of
-    three components) stops, after the same number of events (float64)."""
+    """Algorithm 2 with rescaling on a batch of three SD charts: the events act
+    on every element, and the termination test is taken per chart (each with
+    its own m); the device run stops where the oracle's run on the union of
+    the charts (one mesh of three components, the test per component) stops,
+    after the same number of events (float64)."""
     import torch
     from paper_2107_05200_amd.binding import BatchSolver
     ws = mg.batched_charts(n_charts=6, seed_c=12, m_lo=200.0, m_hi=1200.0)[0::2]
     assert all(w.energy == ws[0].energy for w in ws)
     say(f"case: batch Algorithm 2, m = {[w.m for w in ws]}")
     voff = np.cumsum([0] + [w.n for w in ws])
+    eoff = np.cumsum([0] + [w.m for w in ws])
     V = np.vstack([w.V for w in ws])
     T = np.vstack([w.T + voff[i] for i, w in enumerate(ws)])
     pins = np.concatenate([w.pinned_idx + voff[i] for i, w in enumerate(ws)])
     ppos = np.vstack([w.pinned_pos for w in ws])
     x0 = np.vstack([w.x0 for w in ws])
-    r = O.OracleSolver(V, T, ws[0].energy, ws[0].rho, pins, ppos)
+    r = O.OracleSolver(V, T, ws[0].energy, ws[0].rho, pins, ppos).set_problems(eoff, voff)
     r.init(x0)
     expect = r.run(400, check_every=10, eps_abs=1e-6, eps_rel=1e-5, flip_free=True, rescale=True, rho_r=5.0)
     bs = BatchSolver(ws, precision=64)
     bs.init(x0)
     got = bs.run(400, check_every=10, eps_abs=1e-6, eps_rel=1e-5, flip_free=True, rescale_rho=5.0)
     say(f"  device (iterations, converged, events) {got}, oracle {expect}")
-    assert got == expect
+    assert got == expect and got[1]
     st = bs.get_state()
     torch.cuda.synchronize()
     ex = rel(host(st["map"]), r.x)
     say(f"  final map rel err {ex:.2e}")
     assert ex < 1e-7
+
+
+def test_batch_stops_when_every_chart_passes(gpu_lib):
+    """Without rescaling, a batch of two charts of very different size stops
+    at the first check where both charts meet their own test: the later of the
+    stops found by hand from each chart's own oracle history (float64)."""
+    from paper_2107_05200_amd.binding import BatchSolver
+    ws = [mg.height_field_uv(grid=8), mg.height_field_uv(grid=24, seed_c=7)]
+    say(f"case: batch per-chart termination, m = {[w.m for w in ws]}")
+    oks = []
+    for w in ws:
+        r = _oracle(w)
+        r.iterate(300)
+        H = r.history.array()
+        base = 1e-6 * np.sqrt(2.0 * w.m)
+        oks.append((H[:, 0] < base + 1e-5 * np.maximum(H[:, 7], H[:, 8]))
+                   & (H[:, 1] < base + 1e-5 * H[:, 9]) & (H[:, 5] == 0))
+    every = 5
+    ks = np.arange(1, 301)
+    both = ks[oks[0] & oks[1] & (ks % every == 0)]
+    one = [ks[o & (ks % every == 0)][0] for o in oks]
+    say(f"  oracle: chart stops {one}, both at {both[0]}")
+    assert one[0] != one[1]
+    bs = BatchSolver(ws, precision=64)
+    bs.init(np.vstack([w.x0 for w in ws]))
+    got = bs.iterate_until(300, check_every=every, eps_abs=1e-6, eps_rel=1e-5, flip_free=True)
+    say(f"  device {got}")
+    assert got == (both[0], True)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_run_tests_on_event_iterations(gpu_lib, graph):
+    """Algorithm 2 takes the termination test after the rescaling block of the
+    same iteration.  From the identity fixed point of a flat grid both
+    residuals vanish, so the run stops at iteration 1, itself an event; on
+    the height field with a check every iteration (events at 1..5 are checks)
+    the device stops where the oracle stops (float64)."""
+    f = mg.flat_grid(8)
+    say(f"case: run stops on an event iteration, graph={graph}")
+    g = _solver(f, 64)
+    g.init(f.x0)
+    got = g.run(20, check_every=1, eps_abs=1e-6, eps_rel=1e-5, flip_free=True, rescale_rho=5.0, graph=graph)
+    say(f"  flat grid: {got}")
+    assert got == (1, True, 1)
+    w = mg.height_field_uv()
+    r = _oracle(w)
+    expect = r.run(800, check_every=1, eps_abs=1e-6, eps_rel=1e-5, flip_free=True, rescale=True, rho_r=5.0)
+    g = _solver(w, 64)
+    g.init(w.x0)
+    got = g.run(800, check_every=1, eps_abs=1e-6, eps_rel=1e-5, flip_free=True, rescale_rho=5.0, graph=graph)
+    say(f"  height field: device {got}, oracle {expect}")
+    assert got == expect and got[1]

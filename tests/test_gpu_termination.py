@@ -83,15 +83,18 @@ def test_iterate_until_argument_errors(gpu_lib):
     assert done == 0 and not conv
 
 
-@pytest.mark.parametrize("case", ["height_field_fp64", "height_field_fp64_h1", "cube_fp64", "sphere_cap_sg_fp32"])
+@pytest.mark.parametrize("case", ["height_field_fp64", "height_field_fp64_h1", "cube_fp64", "cube_fp64_direct",
+                                  "sphere_cap_sg_fp32"])
 def test_bound_proxies_match_oracle(gpu_lib, case):
     """The two proxies of the figure with the UV-mapping bounds, recorded at
     the check iterations (NaN elsewhere): max |grad f(P_i)| (field 10) and
     the largest Lambda ratio (field 11), against the oracle's history.  Float64: 1e-9 and 1e-6 relative; float32: 1e-4 on the
-    gradient and a finite, positive ratio."""
+    gradient and a finite, positive ratio.  "direct": the iterations between
+    checks launched one by one instead of replaying the captured graph (the
+    iteration before each check must store U for the ratio)."""
     if case.startswith("height_field"):
         w, prec, h_mode = mg.height_field_uv(), 64, 1 if case.endswith("h1") else 0
-    elif case == "cube_fp64":
+    elif case.startswith("cube_fp64"):
         w, prec, h_mode = mg.twisted_cube(6), 64, 0
     else:
         w, prec, h_mode = mg.sphere_cap_uv(R=15), 32, 0
@@ -100,7 +103,7 @@ def test_bound_proxies_match_oracle(gpu_lib, case):
     from paper_2107_05200_amd.binding import Solver
     g = Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=prec, h_mode=h_mode)
     g.init(w.x0)
-    done, conv = g.iterate_until(K, check_every=every, eps_abs=0.0, eps_rel=0.0)
+    done, conv = g.iterate_until(K, check_every=every, eps_abs=0.0, eps_rel=0.0, graph=not case.endswith("direct"))
     assert done == K and not conv
     h = g.history()
     r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, h_mode=h_mode)

@@ -162,3 +162,43 @@ def test_batch_adjoint_matches_each_chart(gpu_lib):
     say(f"  worst rel err of the pin gradients {worst:.2e}")
     assert off == pb.shape[0]
     assert worst < 1e-9
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_full_batch_matches_oracle_on_sampled_charts(gpu_lib, prec):
+    """The full batch (256 charts, 2,259,662 triangles, mixed energies) for
+    200 iterations, autotuned and replayed as graphs: eight charts (the
+    largest, the smallest and six drawn by a seeded generator) against their
+    own oracle runs of 200 iterations: map and W_el <= 1e-5 and final E_P
+    <= 1e-4 per chart, with float64 and with float32 element steps."""
+    import torch
+    from paper_2107_05200_amd.binding import BatchSolver
+    ws = mg.batched_charts()
+    sizes = np.array([w.m for w in ws])
+    rng = np.random.default_rng(77)
+    pick = [int(np.argmax(sizes)), int(np.argmin(sizes))]
+    pick += [int(j) for j in rng.choice(np.setdiff1d(np.arange(len(ws)), pick), size=6, replace=False)]
+    say(f"case: full batch fp{prec} vs oracle on charts {pick} (m = {[int(sizes[j]) for j in pick]})")
+    bs = BatchSolver(ws, precision=prec)
+    vo, eo = bs.layout()
+    x0 = np.concatenate([w.x0 for w in ws])
+    bs.init(x0).autotune()
+    bs.init(x0).iterate(200, graph=True)
+    st = {k: v.cpu().numpy().astype(np.float64) for k, v in bs.get_state().items()}
+    torch.cuda.synchronize()
+    worst_x = worst_w = worst_e = 0.0
+    for j in pick:
+        w = ws[j]
+        r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+        r.init(w.x0)
+        r.iterate(200)
+        ex = rel(st["map"][vo[j]:vo[j + 1]], r.x)
+        ew = rel(st["Wel"][eo[j]:eo[j + 1]], r.wel())
+        P = st["P"][eo[j]:eo[j + 1]]
+        ev = np.linalg.eigvalsh(0.5 * (P + np.transpose(P, (0, 2, 1))))
+        E = float(np.sum(O.element_geometry(w.V, w.T)[1] * O.energy_of_spd_eigs(ev, w.energy)))
+        ee = abs(E - r.history.col("E_P")[-1]) / abs(r.history.col("E_P")[-1])
+        say(f"  chart {j} (m={w.m}, energy {w.energy}): map {ex:.2e} W_el {ew:.2e} E_P {ee:.2e}")
+        worst_x, worst_w, worst_e = max(worst_x, ex), max(worst_w, ew), max(worst_e, ee)
+    assert worst_e <= 1e-4
+    assert worst_x <= 1e-5 and worst_w <= 1e-5, (worst_x, worst_w)

@@ -43,6 +43,13 @@ def host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
+def per_element_max(a, b):
+    """largest relative Frobenius error over the elements (rows of d x d)"""
+    num = np.linalg.norm((a - b).reshape(len(b), -1), axis=1)
+    den = np.maximum(np.linalg.norm(b.reshape(len(b), -1), axis=1), 1e-300)
+    return float(np.max(num / den))
+
+
 # ---------------------------------------------------------------------------
 # the whole iteration, free-running, float64 (height-field chart, 200 iterations)
 # ---------------------------------------------------------------------------
@@ -122,13 +129,18 @@ def test_teacher_forced_steps(gpu_lib, name):
             ex = rel(host(st["map"]), t.x)
             ew = rel(host(st["Wel"]), t.wel())
             el = rel(host(st["Lam"]), t.Lam)
-            say(f"  k={k}: map {ex:.2e} Wel {ew:.2e} Lam {el:.2e}")
+            # per-element largest relative errors (reported, not gated: near-
+            # degenerate elements in float32 legitimately differ more)
+            pw = per_element_max(host(st["Wel"]), t.wel())
+            pl = per_element_max(host(st["Lam"]), t.Lam)
+            say(f"  k={k}: map {ex:.2e} Wel {ew:.2e} Lam {el:.2e}; per element: Wel {pw:.2e} Lam {pl:.2e}")
             assert ex < 1e-5 and ew < 1e-5, (k, ex, ew)
-            assert el < (1e-3 if prec == 32 else 1e-8), (k, el)
+            assert el < (1e-5 if prec == 32 else 1e-8), (k, el)
             hg = g.history(k - 1, 1)[0]
             ht = t.history.array()[-1]
             assert abs(hg[2] - ht[2]) <= 1e-5 * abs(ht[2])
-            assert abs(hg[0] - ht[0]) <= 1e-3 * ht[0] + 1e-6
+            # e_prim against the scale its threshold uses (eps_rel max(|GW|, |P|))
+            assert abs(hg[0] - ht[0]) <= 1e-5 * max(ht[7], ht[8]), (hg[0], ht[0])
             assert np.all(np.linalg.det(host(st["Wel"])) > 0)
         r.iterate(1)
 

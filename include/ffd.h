@@ -217,6 +217,21 @@ ffd_status ffd_set_pins(ffd_handle h, const double* pinned_pos_dev, void* stream
 /* Run n_iter iterations of Algorithm 1, appending n_iter history records. */
 ffd_status ffd_iterate(ffd_handle h, int32_t n_iter, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ffd_iterate
+ * without any allocation.  The local step's per-block partial sums go to a
+ * fixed 4 MiB scratch array of the library (one per GPU, kept until the
+ * process ends, looked up with hipGetSymbolAddress on the first call on a
+ * device) instead of the handle's buffer; results are bitwise those of
+ * ffd_iterate.  All calls on one GPU share that scratch, so calls that
+ * overlap on one GPU (other streams, other threads, other handles) race.
+ * Errors: FFD_ERR_INVALID_ARG when the handle's history cannot hold
+ * n_iter more records (ffd_iterate would grow it) or when the local step
+ * needs more than the scratch holds ((ceil(m / block) + blocks / 256) x 11
+ * float64: about 3M elements at the 64-element block); FFD_ERR_STATE
+ * before ffd_init. */
+ffd_status ffd_iterate_noalloc(ffd_handle h, int32_t n_iter, void* stream);
+
 /* As ffd_iterate, with the launches of two iterations captured once into a
  * HIP graph (on a stream of the handle's own) and replayed on `stream`
  * (Algorithm 1's loop body has a fixed launch sequence, so one capture serves

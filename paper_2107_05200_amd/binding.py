@@ -67,6 +67,7 @@ _PROTOS = {
     "ffd_set_pins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "ffd_iterate": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "ffd_iterate_graph": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "ffd_iterate_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "ffd_iterate_until": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
                                     C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ffd_rescale": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
@@ -258,6 +259,12 @@ class Solver:
         """n_iter iterations; graph=True replays a captured HIP graph (same results)."""
         fn = self.lib.ffd_iterate_graph if graph else self.lib.ffd_iterate
         _check(fn(self.h, int(n_iter), _stream(stream)))
+        return self
+
+    def iterate_noalloc(self, n_iter: int = 1, stream=None):
+        """n_iter iterations with no device allocation (ffd_iterate_noalloc):
+        the local step's partial sums use the library's fixed scratch."""
+        _check(self.lib.ffd_iterate_noalloc(self.h, int(n_iter), _stream(stream)))
         return self
 
     def iterate_until(self, max_iter: int, check_every: int = 10, eps_abs: float = 1e-6, eps_rel: float = 1e-5,

@@ -9,6 +9,39 @@
 // (handle set-up) -> graph (captured iterations) -> tune (autotuner timing).
 #include "runtime/tune.hpp"
 
+#include <mutex>
+
+// Fixed scratch of ffd_iterate_noalloc: the per-block partial sums of the
+// local step and their first-stage reduction live here instead of in the
+// handle's buffers.  One copy per GPU, held until the process ends; every call
+// on a GPU shares it (calls that overlap on one GPU race).  In host code the
+// name is only a stand-in: the device address comes from hipGetSymbolAddress.
+constexpr size_t kScratchDoubles = size_t(1) << 19;  // 4 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+double* g_scratch_ptr[kMaxScratchDevices] = {};
+std::mutex g_scratch_mutex;
+
+// the current device's copy of `scratch`, looked up once per device
+ffd_status scratch_for_current_device(double** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(FFD_ERR_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return FFD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* ffd_last_error(void) { return g_last_error.c_str(); }
@@ -279,6 +312,38 @@ ffd_status ffd_iterate(ffd_handle h, int32_t n_iter, void* stream) {
   ffd_status st = ensure_hist(h, h->k + n_iter, s);
   if (st != FFD_OK) return st;
   for (int32_t it = 0; it < n_iter; ++it) one_iteration(h, s, nullptr, true, it == n_iter - 1);
+  HIP_TRY(hipGetLastError());
+  h->last_stream = s;
+  return FFD_OK;
+}
+
+ffd_status ffd_iterate_noalloc(ffd_handle h, int32_t n_iter, void* stream) {
+  if (!h) return fail(FFD_ERR_INVALID_ARG, "NULL handle");
+  if (!h->initialized) return fail(FFD_ERR_STATE, "ffd_iterate_noalloc before ffd_init / ffd_set_state");
+  if (n_iter < 0) return fail(FFD_ERR_INVALID_ARG, "negative iteration count");
+  if (h->k + n_iter > h->hist_cap)
+    return fail(FFD_ERR_INVALID_ARG, "the history holds " + std::to_string(h->hist_cap) + " records; " +
+                                         std::to_string(h->k + n_iter) + " would need a larger one (allocation)");
+  const int64_t nb2 = h->nparts > 2 * kFinalizeRows ? (h->nparts + kFinalizeRows - 1) / kFinalizeRows : 0;
+  const size_t need = static_cast<size_t>(h->nparts + nb2) * kNumPartials;
+  if (need > kScratchDoubles)
+    return fail(FFD_ERR_INVALID_ARG, "the local step needs " + std::to_string(need) +
+                                         " float64 of scratch; the fixed scratch holds " +
+                                         std::to_string(kScratchDoubles));
+  double* sp = nullptr;
+  const ffd_status st = scratch_for_current_device(&sp);
+  if (st != FFD_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the launches of ffd_iterate with the partial sums redirected to the
+  // scratch (every block writes its partials before the reduction reads them,
+  // so nothing needs clearing)
+  double* const own = h->partials;
+  double* const own2 = h->partials2;
+  h->partials = sp;
+  h->partials2 = sp + static_cast<size_t>(h->nparts) * kNumPartials;
+  for (int32_t it = 0; it < n_iter; ++it) one_iteration(h, s, nullptr, true, it == n_iter - 1);
+  h->partials = own;
+  h->partials2 = own2;
   HIP_TRY(hipGetLastError());
   h->last_stream = s;
   return FFD_OK;

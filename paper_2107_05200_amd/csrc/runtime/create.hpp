@@ -167,6 +167,12 @@ ffd_status create_impl(const ffd_mesh& mesh_in, const ffd_options& opt, const st
   UP(upload(h, &h->lcf_val, S.lcf_val));
   UP(h->alloc(&h->hist_scratch, FFD_HIST_FIELDS));
   {
+    // the first history buffer comes with the handle, so iterations can run
+    // without allocating until it fills
+    const ffd_status hs = ensure_hist(h, 1, nullptr);
+    if (hs != FFD_OK) return cleanup(hs);
+  }
+  {
     std::vector<int64_t> poff;
     const int64_t ptot = device_panel_offsets(S, poff);
     UP(h->alloc(&h->Prow, static_cast<size_t>(ptot)));

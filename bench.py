@@ -22,15 +22,15 @@ if ROOT not in sys.path:
 
 METRIC = "ADMM iters/s + local-step elems/s at 1.5M tets; fwd+bwd s/iter vs plain"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 78.6  # no packed FP32: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak (packed / dual-issue)
+FP32_NONPACKED_TFLOPS = 78.6  # 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz, one FP32 op per lane per cycle
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (scaled by a plain copy of known size) on the benchmark workload, keyed by a
 # hash of the kernel sources they were measured on: a changed kernel reports
 # no traffic until it is measured again.
 MEASURED_TRAFFIC = {
-    "9c583d9179578b02": {"solve": 3187.4e6, "local": 522.3e6,
-                         "local_flop_per_elem": 2282.0, "local_valu_per_wave": 2666.4},
+    # (source hash, element-step precision): per-iteration bytes and counters
 }
 
 
@@ -53,16 +53,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def local_step_bytes_per_element(d: int, prec: int, n: int, m: int, h_mode: int = 0) -> float:
-    """Unique HBM bytes of one fused local step per element (implemented layout):
-    reads T (d+1 int32), B (d^2), w, U, P (sym), Lambda (d^2); writes U, P,
-    Lambda, corner vectors ((d+1) d) and |grad f(P)|^2; plus the two float64
+def local_step_bytes_per_element(d: int, prec: int, n: int, m: int, h_mode: int = 0, store_u: bool = False) -> float:
+    """Unique HBM bytes of one fused local step per element, for the branch
+    the kernel takes: reads T (d+1 int32), B (d^2), w, P (symmetric), Lambda
+    (d^2), and the rotation U only where it is an input (2D: the tie rule;
+    h_mode 1: the proximal term, which also reads |grad f(P)|^2); writes P,
+    Lambda and the next right-hand side's corner vectors ((d+1) d), and U and
+    |grad f(P)|^2 where they are stored (2D and h_mode 1 always, otherwise
+    only on iterations whose state is kept: store_u); plus the two float64
     maps (W^k, W^{k-1}) read once per vertex."""
     r = prec // 8
     nU = 2 if d == 2 else 9
     nP = 3 if d == 2 else 6
-    reads = 4 * (d + 1) + r * (d * d + 1 + nU + nP + d * d) + (r if h_mode else 0)
-    writes = r * (nU + nP + d * d + (d + 1) * d + 1)
+    u_in = d == 2 or h_mode == 1
+    u_out = u_in or store_u
+    reads = 4 * (d + 1) + r * (d * d + 1 + nP + d * d) + (r * nU if u_in else 0) + (r if h_mode else 0)
+    writes = r * (nP + d * d + (d + 1) * d) + (r * (nU + 1) if u_out else 0)
     maps = 2 * 8 * d * n / m
     return reads + writes + maps
 
@@ -208,6 +214,18 @@ def batched_leg(iters: int = 200):
     bs.iterate(iters, graph=True)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    # the solve of the block-diagonal factor against HBM: per-phase events of a
+    # profiled pass (each factor entry read once per pass)
+    ph = bs.iterate_profiled(iters)
+    info = bs.info()
+    solve_ms = (ph["solve_fwd"] + ph["solve_bwd"]) / iters
+    solve_bytes = 2.0 * 8.0 * info["factor_nnz"]
+    gbs = solve_bytes / (solve_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_solve_fwd* + k_solve_bwd* (block-diagonal factor of the 256 charts)",
+            "algorithmic_bytes": solve_bytes, "ms_per_launch": round(solve_ms, 5),
+            "phase_ms_per_iter": {k: round(v / iters, 5) for k, v in ph.items() if k != "total"}}
     bs.close()
     solvers = [binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32) for w in ws]
     for s_, w in zip(solvers, ws):
@@ -226,7 +244,7 @@ def batched_leg(iters: int = 200):
     return {"workload": f"{len(ws)} height-field charts, {m:,} triangles total, SD/SG mixed, {iters} iterations",
             "batched_elem_iters_per_s": m * iters / tb, "plain_elem_iters_per_s": m * iters / tp,
             "speedup": tp / tb, "batched_ms_per_iter": tb / iters * 1e3, "setup_s": setup,
-            "autotune_s": tune, "launch": launch}
+            "autotune_s": tune, "launch": launch, "factor_nnz": info["factor_nnz"], "roofline_solve": roof}
 
 
 def uv_pipeline_leg(max_iter: int = 1000):
@@ -299,6 +317,174 @@ def constraints_leg(iters: int = 200, rows: int = 48):
             **out, "ratio": out["constrained"]["ms_per_iter"] / out["plain"]["ms_per_iter"]}
 
 
+def cube_leg(w, precision: int, steps: int, warmup: int, tune_cache=None, no_graph=False, leaf_size=0,
+             keep=False):
+    """The tet cube at one element-step precision: set-up, autotune, `warmup`
+    replayed iterations, then `steps` iterations timed between two HIP events
+    on the solver's stream, a second pass of `steps` iterations with per-phase
+    events (the phase split and the kernels' average durations), and the
+    per-level timing of the solve.  Returns (results, solver or None)."""
+    import torch
+    from paper_2107_05200_amd import binding
+    t0 = time.perf_counter()
+    s = binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=precision,
+                       leaf_size=leaf_size)
+    setup_s = time.perf_counter() - t0
+    info = s.info()
+    log(f"[fp{precision}] setup {setup_s:.1f}s: factor nnz {info['factor_nnz']:.3e}, levels {info['n_levels']}, "
+        f"numeric {info['t_numeric']:.1f}s, device {info['device_bytes'] / 2**30:.2f} GiB")
+    stream = torch.cuda.current_stream()
+    s.init(w.x0)
+    t0 = time.perf_counter()
+    launch = s.autotune(tune_cache)
+    log(f"[fp{precision}] launch shapes {launch} ({time.perf_counter() - t0:.2f}s)")
+    s.iterate(warmup, stream, graph=not no_graph)
+    torch.cuda.synchronize()
+    # timed region: K iterations between two HIP events on the solver's
+    # stream (per-phase events add a few microseconds per phase, so the phase
+    # split comes from a separate profiled pass)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.iterate(steps, stream, graph=not no_graph)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    K = steps
+    total_ms = e0.elapsed_time(e1)
+    ms_per_step = total_ms / K
+    log(f"[fp{precision}] timed {K} iterations: {total_ms:.2f} ms events, {wall * 1e3:.2f} ms wall")
+    ph = s.iterate_profiled(K, stream)
+    torch.cuda.synchronize()
+    log(f"[fp{precision}] profiled pass of {K} iterations: phases {ph}")
+    levels = s.profile_solve_levels(10, stream)
+    log(f"[fp{precision}] solve levels (fwd ms, bwd ms, MB, TB/s fwd, TB/s bwd):")
+    for l, lv in enumerate(levels):
+        log(f"  {l:2d} {lv['fwd_ms']:.4f} {lv['bwd_ms']:.4f} {lv['bytes'] / 1e6:8.1f} "
+            f"{lv['bytes'] / lv['fwd_ms'] / 1e9:.2f} {lv['bytes'] / lv['bwd_ms'] / 1e9:.2f} nodes {int(lv['nodes'])}")
+    hist = s.history()
+    log(f"[fp{precision}] last history record: {dict(zip(binding.HIST_NAMES, hist[-1].tolist()))}")
+    d, m, n, nF = w.d, w.m, w.n, info["n_free"]
+    solve_ms = (ph["solve_fwd"] + ph["solve_bwd"]) / K
+    local_ms = ph["local"] / K
+    solve_bytes = 2.0 * 8.0 * info["factor_nnz"]  # each factor entry read once per pass
+    # the profiled pass stores U and |grad f|^2 on its last iteration only
+    lb = ((K - 1) * local_step_bytes_per_element(d, precision, n, m) +
+          local_step_bytes_per_element(d, precision, n, m, store_u=True)) / K
+    local_bytes = lb * m
+    solve_gbs = solve_bytes / (solve_ms * 1e-3) / 1e9
+    local_gbs = local_bytes / (local_ms * 1e-3) / 1e9
+    standard = (w.meta.get("k"), leaf_size) == (64, 0)
+    traffic = MEASURED_TRAFFIC.get((kernel_source_hash(), precision), {}) if standard else {}
+    timing = "HIP events around each phase of a second pass of K iterations on the same stream"
+    roof_solve = {"bound": "hbm", "achieved": round(solve_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(solve_gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get("solve"),
+                  "kernel": "k_solve_fwd* + k_solve_bwd* (one W-step solve, all levels)",
+                  "algorithmic_bytes": solve_bytes, "ms_per_launch": round(solve_ms, 5), "timing": timing}
+    roof_local = {"bound": "hbm", "achieved": round(local_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(local_gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get("local"), "kernel": "k_local",
+                  "algorithmic_bytes": local_bytes, "bytes_per_element": round(lb, 2),
+                  "ms_per_launch": round(local_ms, 5), "timing": timing}
+    roof_local_alu = None
+    if traffic.get("local_flop_per_elem"):
+        tf = traffic["local_flop_per_elem"] * m / (local_ms * 1e-3) / 1e12
+        roof_local_alu = {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": round(tf / FP32_PEAK_TFLOPS, 4),
+                          "frac_nonpacked": round(tf / FP32_NONPACKED_TFLOPS, 4), "kernel": "k_local",
+                          "flop_per_element": traffic["local_flop_per_elem"],
+                          "valu_instructions_per_wave": traffic["local_valu_per_wave"],
+                          "note": "flop = (ADD + MUL + 2 FMA + TRANS) x 64 from the SQ_INSTS_VALU_* counters; "
+                                  "frac against the published 157.3 TFLOP/s, frac_nonpacked against 78.6 "
+                                  "(one FP32 op per lane per cycle; packed FP32 is not generated)"}
+    res = {
+        "iters_per_s": round(1000.0 / ms_per_step, 2),
+        "ms_per_step": round(ms_per_step, 5),
+        "launch": launch,
+        "free_vertices": nF,
+        "local_step_elems_per_s": round(m / (local_ms * 1e-3), 1),
+        "phase_ms_per_iter": {k: round(v / K, 5) for k, v in ph.items() if k != "total"},
+        "setup_s": round(setup_s, 2),
+        "factor": {"nnz": info["factor_nnz"], "levels": info["n_levels"], "numeric_s": round(info["t_numeric"], 2)},
+        "roofline": roof_solve if solve_ms >= local_ms else roof_local,
+        "roofline_local_step": roof_local,
+        "roofline_local_step_alu": roof_local_alu,
+        "roofline_solve": roof_solve,
+        "wrhs_gbs": round(wrhs_bytes(d, precision, m, nF, n) / (ph["wrhs"] / K * 1e-3) / 1e9, 1),
+        "solve_levels": [{"fwd_ms": round(lv["fwd_ms"], 5), "bwd_ms": round(lv["bwd_ms"], 5),
+                          "MB": round(lv["bytes"] / 1e6, 2), "nodes": int(lv["nodes"]), "c_max": int(lv["c_max"]),
+                          "r_max": int(lv["r_max"])} for lv in levels],
+    }
+    if not keep:
+        s.close()
+        s = None
+    return res, s
+
+
+def precision64_leg(w, steps: int, warmup: int, tune_cache=None):
+    """The same cube with float64 element steps: the paper's arithmetic
+    (IEEE double throughout)."""
+    res, _ = cube_leg(w, 64, steps, warmup, tune_cache)
+    keep = ("iters_per_s", "ms_per_step", "local_step_elems_per_s", "phase_ms_per_iter", "roofline_solve",
+            "roofline_local_step", "launch")
+    return {"dtype": "f64", **{k: res[k] for k in keep}}
+
+
+def _oracle_fullsize_worker(k: int, iters: int, out_path: str):
+    """Child process: the oracle's set-up and whole iterations (W-step with its
+    factorised L_FF, element steps, diagnostics) on the k^3 tet cube, one
+    thread; writes a JSON object to out_path."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    from paper_2107_05200_amd import meshgen
+    w = meshgen.twisted_cube(k)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+        r.init(w.x0)
+        r.iterate(1)  # the first W-step factorises L_FF
+        t1 = time.perf_counter()
+        r.iterate(iters)
+        t2 = time.perf_counter()
+    res = {"oracle_setup_and_first_iteration_s": t1 - t0, "oracle_s_per_iter": (t2 - t1) / iters,
+           "oracle_iters_per_s": iters / (t2 - t1), "iterations_timed": iters, "threads": 1,
+           "workload": f"twisted tet cube {k}^3 ({w.m:,} tets)", "E_P_after": float(r.history.col("E_P")[-1])}
+    with open(out_path, "w") as f:
+        json.dump(res, f)
+
+
+def start_oracle_fullsize(k: int, iters: int = 2):
+    """Start the oracle's full-size iterations in a child process (one core)
+    so that its long factorisation overlaps the device legs."""
+    import subprocess
+    import tempfile
+    path = os.path.join(tempfile.gettempdir(), f"ffd_oracle_fullsize_{os.getpid()}.json")
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    proc = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker", str(k), str(iters), path],
+                            env=env, stdout=subprocess.DEVNULL, stderr=subprocess.PIPE)
+    log(f"oracle full-size iterations started (pid {proc.pid})")
+    return proc, path, time.perf_counter()
+
+
+def finish_oracle_fullsize(job, timeout_s: float):
+    proc, path, t0 = job
+    try:
+        _, err = proc.communicate(timeout=max(1.0, timeout_s))
+    except Exception:
+        proc.kill()
+        proc.communicate()
+        return {"error": f"not finished within {timeout_s:.0f} s of waiting"}
+    if proc.returncode != 0 or not os.path.exists(path):
+        return {"error": f"worker exited with {proc.returncode}: {err.decode(errors='replace')[-300:]}"}
+    with open(path) as f:
+        res = json.load(f)
+    os.remove(path)
+    res["wall_s_since_start"] = time.perf_counter() - t0
+    return res
+
+
 def _cpu_name():
     try:
         for ln in open("/proc/cpuinfo"):
@@ -324,11 +510,24 @@ def main():
     ap.add_argument("--leaf-size", type=int, default=0, help="nested-dissection leaf size (0: the library's default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain elementwise copy (negation) of MIB MiB ten times (counter calibration)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 element-step line")
+    ap.add_argument("--oracle-fullsize", action="store_true",
+                    help="also time the oracle's whole iterations on the full cube (a child process on one core "
+                         "started first; its factorisation takes minutes, so the run waits for it at the end)")
+    ap.add_argument("--oracle-worker", nargs=3, metavar=("K", "ITERS", "OUT"), help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_worker:
+        _oracle_fullsize_worker(int(args.oracle_worker[0]), int(args.oracle_worker[1]), args.oracle_worker[2])
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+
+    # the oracle's child process starts before this process touches the GPU
+    oracle_job = None
+    if args.oracle_fullsize and not args.no_cpu_baseline and not args.calibrate_copy:
+        oracle_job = start_oracle_fullsize(args.cube)
 
     import numpy as np
     import torch
@@ -350,80 +549,18 @@ def main():
     t0 = time.perf_counter()
     w = meshgen.twisted_cube(args.cube)
     log(f"workload {w.name}: m={w.m} n={w.n} pins={len(w.pinned_idx)} ({time.perf_counter() - t0:.1f}s)")
-    t0 = time.perf_counter()
-    s = binding.Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=args.precision,
-                       leaf_size=args.leaf_size)
-    setup_s = time.perf_counter() - t0
-    info = s.info()
-    log(f"setup {setup_s:.1f}s: factor nnz {info['factor_nnz']:.3e}, levels {info['n_levels']}, "
-        f"numeric {info['t_numeric']:.1f}s, device {info['device_bytes'] / 2**30:.2f} GiB")
-    stream = torch.cuda.current_stream()
-    s.init(w.x0)
-    t0 = time.perf_counter()
-    launch = s.autotune(args.tune_cache)
-    log(f"launch shapes {launch} ({time.perf_counter() - t0:.2f}s)")
-    s.iterate(args.warmup, stream, graph=not args.no_graph)
-    torch.cuda.synchronize()
-    log(f"warmup {args.warmup} done")
-
-    # timed region: K plain iterations between two HIP events on the solver's
-    # stream (the per-phase events of iterate_profiled add a few microseconds
-    # per phase, so the phase split comes from a separate profiled pass)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    s.iterate(args.steps, stream, graph=not args.no_graph)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    main_leg, s = cube_leg(w, args.precision, args.steps, args.warmup, args.tune_cache, args.no_graph,
+                           args.leaf_size, keep=True)
     K = args.steps
-    total_ms = e0.elapsed_time(e1)
-    ms_per_step = total_ms / K
-    log(f"timed {K} iterations: {total_ms:.2f} ms events, {wall * 1e3:.2f} ms wall")
-    ph = s.iterate_profiled(K, stream)
-    torch.cuda.synchronize()
-    log(f"profiled pass of {K} iterations: phases {ph}")
-    hist = s.history()
-    log(f"last history record: {dict(zip(binding.HIST_NAMES, hist[-1].tolist()))}")
-
-    d, m, n, nF = w.d, w.m, w.n, info["n_free"]
-    solve_ms = (ph["solve_fwd"] + ph["solve_bwd"]) / K
-    local_ms = ph["local"] / K
-    solve_bytes = 2.0 * 8.0 * info["factor_nnz"]  # each factor entry read once per pass
-    lb = local_step_bytes_per_element(d, args.precision, n, m)
-    local_bytes = lb * m
-    solve_gbs = solve_bytes / (solve_ms * 1e-3) / 1e9
-    local_gbs = local_bytes / (local_ms * 1e-3) / 1e9
-    dominant = "solve" if solve_ms >= local_ms else "local"
-    traffic = MEASURED_TRAFFIC.get(kernel_source_hash(), {}) if (args.cube, args.precision, args.leaf_size) == (64, 32, 0) else {}
-    roof_solve = {"bound": "hbm", "achieved": round(solve_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(solve_gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get("solve"),
-                  "kernel": "k_solve_fwd + k_solve_bwd (one W-step solve, all levels)",
-                  "algorithmic_bytes": solve_bytes, "ms_per_launch": round(solve_ms, 5),
-                  "timing": "HIP events around each phase of a second pass of K iterations on the same stream"}
-    roof_local = {"bound": "hbm", "achieved": round(local_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(local_gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get("local"), "kernel": "k_local",
-                  "algorithmic_bytes": local_bytes, "bytes_per_element": round(lb, 2),
-                  "ms_per_launch": round(local_ms, 5),
-                  "timing": "HIP events around each phase of a second pass of K iterations on the same stream"}
-    roof_local_alu = None
-    if traffic.get("local_flop_per_elem"):
-        tf = traffic["local_flop_per_elem"] * m / (local_ms * 1e-3) / 1e12
-        roof_local_alu = {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                          "frac": round(tf / FP32_PEAK_TFLOPS, 4), "kernel": "k_local",
-                          "flop_per_element": traffic["local_flop_per_elem"],
-                          "valu_instructions_per_wave": traffic["local_valu_per_wave"],
-                          "note": "flop = (ADD + MUL + 2 FMA + TRANS) x 64 from the SQ_INSTS_VALU_* counters"}
+    m, n, nF = w.m, w.n, main_leg["free_vertices"]
     out = {
         "metric": METRIC,
-        "value": round(1000.0 / ms_per_step, 2),
+        "value": main_leg["iters_per_s"],
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": main_leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -432,23 +569,21 @@ def main():
         "config": {"workload": f"twisted tet cube {args.cube}^3 x 6 Kuhn tets ({m:,} tets, {n:,} vertices), "
                                f"symmetric Dirichlet, rho=10, bottom fixed, top 45deg twist + 0.3 lift",
                    "elements": m, "vertices": n, "free_vertices": nF, "precision": args.precision,
-                   "launch": launch},
-        "local_step_elems_per_s": round(m / (local_ms * 1e-3), 1),
+                   "launch": main_leg["launch"]},
+        "local_step_elems_per_s": main_leg["local_step_elems_per_s"],
         "fwd_bwd_s_per_iter_vs_plain": None,
-        "phase_ms_per_iter": {k: round(v / K, 5) for k, v in ph.items() if k != "total"},
-        "setup_s": round(setup_s, 2),
-        "factor": {"nnz": info["factor_nnz"], "levels": info["n_levels"], "numeric_s": round(info["t_numeric"], 2)},
-        "roofline": roof_solve if dominant == "solve" else roof_local,
-        "roofline_local_step": roof_local,
-        "roofline_local_step_alu": roof_local_alu,
-        "roofline_solve": roof_solve,
-        "wrhs_gbs": round(wrhs_bytes(d, args.precision, m, nF, n) / (ph["wrhs"] / K * 1e-3) / 1e9, 1),
+        **{k: v for k, v in main_leg.items() if k not in ("iters_per_s", "ms_per_step", "launch", "free_vertices",
+                                                            "local_step_elems_per_s")},
     }
     st = None
     if not args.no_cpu_baseline:
         st = {k: v.cpu() for k, v in s.get_state().items()}
         torch.cuda.synchronize()
     s.close()
+    if not args.no_fp64:
+        t0 = time.perf_counter()
+        out["fp64"] = precision64_leg(w, K, args.warmup)
+        log(f"fp64 line: {out['fp64']['iters_per_s']} iters/s ({time.perf_counter() - t0:.1f}s)")
     if not args.no_extra:
         t0 = time.perf_counter()
         adj = adjoint_leg()
@@ -471,6 +606,14 @@ def main():
         t0 = time.perf_counter()
         out["cpu_baseline"]["oracle_iterations"] = oracle_iteration_rates()
         log(f"oracle iterations: {out['cpu_baseline']['oracle_iterations']} ({time.perf_counter() - t0:.1f}s)")
+    if oracle_job is not None:
+        t0 = time.perf_counter()
+        full = finish_oracle_fullsize(oracle_job, 1800.0)
+        full["device_s_per_iter"] = main_leg["ms_per_step"] * 1e-3
+        if "oracle_s_per_iter" in full:
+            full["ratio"] = full["oracle_s_per_iter"] / full["device_s_per_iter"]
+        out.setdefault("cpu_baseline", {})["oracle_iterations_fullsize"] = full
+        log(f"oracle full-size iterations: {full} (waited {time.perf_counter() - t0:.1f}s)")
     print(json.dumps(out), flush=True)
 
 

@@ -1021,17 +1021,23 @@ __global__ __launch_bounds__(kBlock, 5) void k_solve_bwd_wave(const SolveTask* _
 // next W-step's corner vectors; per-block partial sums (Algorithm 1 and eq.
 // primaldualerror).  Partials: 0 e_prim^2, 1 e_dual^2, 2 E_P, 3 E_map (over
 // det J > 0), 4 Phi, 5 flips, 6 non-finite Lambda, 7 |GW|^2, 8 |P|^2.
+// PROX: the proximal term of the U-step (h_mode 1); DIAG: a diagnostic
+// iteration (corner vectors of Lambda into glam, the two bound proxies) --
+// compile-time, so the common kernel keeps no registers for them.
 // ---------------------------------------------------------------------------
-template <int D, typename R, int ENERGY, int BS = kBlock>
+template <int D, typename R, int ENERGY, int BS, bool PROX, bool DIAG>
 __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1, const int32_t* __restrict T,
                                                   const R* __restrict Bm_,
                                                   const R* __restrict w, R rho_u, const R* __restrict rho_e,
-                                                  int h_mode, int store_u,
+                                                  int store_u,
                                                   const double* __restrict x, const double* __restrict xprev,
                                                   R* __restrict U, R* __restrict P, R* __restrict Lam,
                                                   R* __restrict gnorm2, R* __restrict g,
                                                   double* __restrict partials, R* __restrict glam) {
-  const int64_t e = e0 + static_cast<int64_t>(blockIdx.x) * BS + threadIdx.x;
+  // each XCD takes a contiguous eighth of the element blocks, so the vertex
+  // positions its elements gather are fetched into one L2
+  const int64_t blk = xcd_block();
+  const int64_t e = e0 + blk * BS + threadIdx.x;
   double part[kNumPartials];
   partials_init(part);
   if (e < e1) {
@@ -1039,7 +1045,7 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
     const R rho = rho_e ? rho_e[e] : rho_u;  // mu_e / w_e (per element after a rescaling)
     const R mu = rho * we;
     const double wd = static_cast<double>(we), mud = static_cast<double>(mu);
-    R J[D][D];
+    R J[D][D], Bm[D][D];  // B is kept for the corner vectors at the end
     {
       // edge differences in float64, then J = B E and the dual residual term
       double x0[D], d0[D];
@@ -1060,7 +1066,7 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
           dE[j][k] = static_cast<R>((xv - xprev[vj * D + k]) - d0[k]);
         }
       }
-      R Bm[D][D], Jd[D][D];
+      R Jd[D][D];
       load_B<D, R>(Bm_, m, e, Bm);
       matmul<D, R>(Bm, E, J);
       matmul<D, R>(Bm, dE, Jd);
@@ -1088,7 +1094,7 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
     R Ur[D][D], Pm[D][D], L[D][D], A[D][D];
     // the previous rotation is an input only through the proximal term (h > 0)
     // and the 2D tie rule; otherwise the rotation is recomputed from Q alone
-    if (D == 2 || h_mode == 1) {
+    if (D == 2 || PROX) {
       load_U<D, R>(U, m, e, Ur);
     } else {
 #pragma unroll
@@ -1101,8 +1107,8 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
     for (int i = 0; i < D * D; ++i) L[i / D][i % D] = Lam[i * m + e];
     // diagnostic iterations keep U^k and Lambda^k for the Lambda-ratio proxy
     R Uo[D][D], Lo[D][D];
-    if (glam) {
-      if (D == 2 || h_mode == 1) {
+    if (DIAG) {
+      if (D == 2 || PROX) {
 #pragma unroll
         for (int i = 0; i < D * D; ++i) Uo[i / D][i % D] = Ur[i / D][i % D];
       } else {
@@ -1119,7 +1125,7 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
       // U-step: Q = (J + Lambda) P + (h/mu) U_prev; h/mu = 20 (1 + |grad f(P_prev)|^2) / rho^2
       R Q[D][D];
       matmul<D, R>(A, Pm, Q);
-      if (h_mode == 1) {
+      if (PROX) {
         const R hm = R(20) * (R(1) + gnorm2[e]) / (rho * rho);
 #pragma unroll
         for (int a = 0; a < D; ++a)
@@ -1178,16 +1184,12 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
         res2 += static_cast<double>(dv + ln) * (dv + ln);
         finite = finite && (ln - ln == R(0));
       }
-    if (D == 2 || h_mode == 1 || store_u) store_U<D, R>(U, m, e, Ur);
+    if (D == 2 || PROX || store_u) store_U<D, R>(U, m, e, Ur);
     store_P<D, R>(P, m, e, Pm);
 #pragma unroll
     for (int i = 0; i < D * D; ++i) Lam[i * m + e] = L[i / D][i % D];
-    {
-      R Bm[D][D];
-      load_B<D, R>(Bm_, m, e, Bm);
-      store_g<D, R>(g, e, Bm, r);
-      if (glam) store_g<D, R>(glam, e, Bm, L);  // corner vectors of Lambda (|G^T Lambda|)
-    }
+    store_g<D, R>(g, e, Bm, r);
+    if (DIAG) store_g<D, R>(glam, e, Bm, L);  // corner vectors of Lambda (|G^T Lambda|)
     double fP = 0.0, p2 = 0.0;
     R gn = R(0);
 #pragma unroll
@@ -1197,8 +1199,8 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
       const R gj = ENERGY == 1 ? p[j] - R(1) / p[j] : p[j] - R(1) / (p[j] * p[j] * p[j]);
       gn += gj * gj;
     }
-    if (h_mode == 1 || store_u) gnorm2[e] = gn;
-    if (glam) {  // the bound proxies (diagnostic iterations)
+    if (PROX || store_u) gnorm2[e] = gn;
+    if (DIAG) {  // the bound proxies (diagnostic iterations)
       part[9] = static_cast<double>(gn);  // max |grad f(P)|^2 (proxy for B_i of Condition "gradf")
       part[10] = lambda_ratio<D, R>(Uo, Lo, Ur, L, ep);
     }
@@ -1208,9 +1210,10 @@ __global__ __launch_bounds__(BS) void k_local(int64_t m, int64_t e0, int64_t e1,
     part[6] = finite ? 0.0 : 1.0;
     part[8] = p2;
   }
-  // the maxima only on diagnostic iterations (their slots are not read otherwise)
-  double* out = partials + static_cast<int64_t>(blockIdx.x) * kNumPartials;
-  if (glam) block_reduce_store<kNumPartials, BS, kNumSums>(part, out);
+  // the maxima only on diagnostic iterations (their slots are not read
+  // otherwise); partials in element-block order (the reduction's order)
+  double* out = partials + blk * kNumPartials;
+  if (DIAG) block_reduce_store<kNumPartials, BS, kNumSums>(part, out);
   else block_reduce_store<kNumSums, BS, kNumSums>(*reinterpret_cast<double(*)[kNumSums]>(part), out);
 }
 

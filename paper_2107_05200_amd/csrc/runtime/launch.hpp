@@ -38,15 +38,27 @@ void launch_rescale(ffd_ctx* h, const ffd_ctx::Seg& g, double rho_r, void* glam,
                      static_cast<R*>(glam));
 }
 
+template <int D, typename R, int E, int BS, bool PROX, bool DIAG>
+void launch_local_k(ffd_ctx* h, const ffd_ctx::Seg& g, const double* xnew, const double* xold, int store_u,
+                    void* glam, hipStream_t s) {
+  hipLaunchKernelGGL((k_local<D, R, E, BS, PROX, DIAG>), dim3(static_cast<unsigned>((g.e1 - g.e0 + BS - 1) / BS)),
+                     dim3(BS), 0, s, h->m, g.e0, g.e1, h->T, static_cast<const R*>(h->B), static_cast<const R*>(h->w),
+                     static_cast<R>(h->rho), static_cast<const R*>(h->rescaled ? h->rho_e : nullptr), store_u, xnew,
+                     xold, static_cast<R*>(h->U), static_cast<R*>(h->P), static_cast<R*>(h->L),
+                     static_cast<R*>(h->gn), static_cast<R*>(h->g), h->partials + g.pb0 * kNumPartials,
+                     static_cast<R*>(glam));
+}
+
 template <int D, typename R, int E, int BS>
 void launch_local_bs(ffd_ctx* h, const ffd_ctx::Seg& g, const double* xnew, const double* xold, int store_u,
                      void* glam, hipStream_t s) {
-  hipLaunchKernelGGL((k_local<D, R, E, BS>), dim3(static_cast<unsigned>((g.e1 - g.e0 + BS - 1) / BS)), dim3(BS), 0, s,
-                     h->m, g.e0, g.e1, h->T, static_cast<const R*>(h->B), static_cast<const R*>(h->w),
-                     static_cast<R>(h->rho), static_cast<const R*>(h->rescaled ? h->rho_e : nullptr), h->h_mode, store_u, xnew, xold,
-                     static_cast<R*>(h->U),
-                     static_cast<R*>(h->P), static_cast<R*>(h->L), static_cast<R*>(h->gn), static_cast<R*>(h->g),
-                     h->partials + g.pb0 * kNumPartials, static_cast<R*>(glam));
+  if (h->h_mode == 1) {
+    if (glam) launch_local_k<D, R, E, BS, true, true>(h, g, xnew, xold, store_u, glam, s);
+    else launch_local_k<D, R, E, BS, true, false>(h, g, xnew, xold, store_u, glam, s);
+  } else {
+    if (glam) launch_local_k<D, R, E, BS, false, true>(h, g, xnew, xold, store_u, glam, s);
+    else launch_local_k<D, R, E, BS, false, false>(h, g, xnew, xold, store_u, glam, s);
+  }
 }
 
 template <int D, typename R, int E>

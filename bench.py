@@ -515,6 +515,8 @@ def main():
                     help="also time the oracle's whole iterations on the full cube (a child process on one core "
                          "started first; its factorisation takes minutes, so the run waits for it at the end)")
     ap.add_argument("--oracle-worker", nargs=3, metavar=("K", "ITERS", "OUT"), help=argparse.SUPPRESS)
+    ap.add_argument("--leg", choices=("adjoint", "batched", "constraints", "uv_pipeline"), default=None,
+                    help="run only this extra leg (no cube) and print its JSON (for profiling it alone)")
     args = ap.parse_args()
     if args.oracle_worker:
         _oracle_fullsize_worker(int(args.oracle_worker[0]), int(args.oracle_worker[1]), args.oracle_worker[2])
@@ -545,6 +547,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_read": nbytes, "calibrate_copy_bytes_written": nbytes,
                           "launches": 10}), flush=True)
+        return
+    if args.leg:
+        fn = {"adjoint": adjoint_leg, "batched": batched_leg, "constraints": constraints_leg,
+              "uv_pipeline": uv_pipeline_leg}[args.leg]
+        print(json.dumps({"leg": args.leg, **fn()}), flush=True)
         return
     t0 = time.perf_counter()
     w = meshgen.twisted_cube(args.cube)

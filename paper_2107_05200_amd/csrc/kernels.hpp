@@ -492,7 +492,9 @@ __global__ __launch_bounds__(kBlock) void k_wrhs(int64_t nF, int64_t n, const in
 // Streams are added in a fixed order.  Levels that still offer too few blocks
 // split the inner ranges into chunks whose partials are added in chunk order
 // (no atomics; bitwise reproducible) by a reduction kernel, or by waves of a
-// later launch (see fwd_y_reduce and bwd_entry).
+// later launch (see fwd_y_reduce and bwd_entry).  Panel entries are read with
+// non-temporal loads: each is used once per pass, and keeping them out of
+// the caches leaves L2 to the gathered inner vectors.
 // ---------------------------------------------------------------------------
 constexpr int kSolveOutMax = 64;  // outputs per task at most (partial slot stride)
 static_assert(kSolveOutMax == kPanelTile, "a task's outputs lie in one panel tile");
@@ -608,7 +610,7 @@ __device__ __forceinline__ void solve_stream(const double* __restrict base, int6
 #pragma unroll
     for (int u = 0; u < kSolveBatch; ++u) {
       const int jj = st + u * NS;
-      pv[u] = (live && jj < jn) ? p0[static_cast<int64_t>(jj) * ld] : 0.0;
+      pv[u] = (live && jj < jn) ? __builtin_nontemporal_load(p0 + static_cast<int64_t>(jj) * ld) : 0.0;
     }
     stage(j0, jn);
     __syncthreads();
@@ -617,7 +619,7 @@ __device__ __forceinline__ void solve_stream(const double* __restrict base, int6
 #pragma unroll
       for (int u = 0; u < kSolveBatch; ++u) {
         const int jj = jb + kSolveBatch * NS + st + u * NS;
-        pn[u] = (live && jj < jn) ? p0[static_cast<int64_t>(jj) * ld] : 0.0;
+        pn[u] = (live && jj < jn) ? __builtin_nontemporal_load(p0 + static_cast<int64_t>(jj) * ld) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < kSolveBatch; ++u) {
@@ -910,7 +912,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_solve_fwd_wave(const SolveTask* _
 #pragma unroll
     for (int u = 0; u < kWavePFf; ++u) {
       const int jj = st + u * IS;
-      pf[u] = (live && jj < jn) ? col[static_cast<int64_t>(j0 + jj) * tk.ld] : 0.0;
+      pf[u] = (live && jj < jn) ? __builtin_nontemporal_load(col + static_cast<int64_t>(j0 + jj) * tk.ld) : 0.0;
     }
     {  // stage the chunk; the carried part of the output row rides along
       const bool sg = lane < jn;
@@ -936,7 +938,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_solve_fwd_wave(const SolveTask* _
       }
 #pragma unroll 8
       for (int jj = st + kWavePFf * IS; jj < jn; jj += IS) {
-        const double pv = col[static_cast<int64_t>(j0 + jj) * tk.ld];
+        const double pv = __builtin_nontemporal_load(col + static_cast<int64_t>(j0 + jj) * tk.ld);
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] += pv * vs[wave][jj][k];
       }
@@ -983,7 +985,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_solve_bwd_wave(const SolveTask* _
 #pragma unroll
     for (int u = 0; u < kWavePF; ++u) {
       const int pp = st + u * IS;
-      pf[u] = (live && pp < pn) ? rowp[static_cast<int64_t>(p0 + pp) * tk.ld] : 0.0;
+      pf[u] = (live && pp < pn) ? __builtin_nontemporal_load(rowp + static_cast<int64_t>(p0 + pp) * tk.ld) : 0.0;
     }
     if (lane < pn) {
       double v[D];
@@ -1003,7 +1005,7 @@ __global__ __launch_bounds__(kBlock, 5) void k_solve_bwd_wave(const SolveTask* _
       }
 #pragma unroll 8
       for (int pp = st + kWavePF * IS; pp < pn; pp += IS) {
-        const double pv = rowp[static_cast<int64_t>(p0 + pp) * tk.ld];
+        const double pv = __builtin_nontemporal_load(rowp + static_cast<int64_t>(p0 + pp) * tk.ld);
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] += pv * vs[wave][pp][k];
       }

@@ -186,10 +186,26 @@ def adjoint_leg(K: int = 100, every: int = 10, reps: int = 3):
         pb, vb = s.adjoint_backward(energy_loss=True)
         torch.cuda.synchronize()
         fb.append((time.perf_counter() - t0) / K)
+    # The dominant kernels of fwd+bwd are the triangular solves: one per
+    # iteration of the forward pass, one per recomputed iteration and one per
+    # adjoint W-step (the same symmetric factor).  Their duration per solve
+    # comes from the per-phase events of a profiled plain pass on this handle.
+    ph = s.init(w.V).iterate_profiled(K)
+    info = s.info()
     s.close()
+    solve_ms = (ph["solve_fwd"] + ph["solve_bwd"]) / K
+    solve_bytes = 2.0 * 8.0 * info["factor_nnz"]
+    gbs = solve_bytes / (solve_ms * 1e-3) / 1e9
+    solves_per_iter = 3.0
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_solve_fwd* + k_solve_bwd* (one solve of the disk's factor; fwd+bwd runs 3 per iteration)",
+            "algorithmic_bytes": solve_bytes, "ms_per_launch": round(solve_ms, 5),
+            "solve_share_of_fwd_bwd": round(solves_per_iter * solve_ms * 1e-3 / min(fb), 4),
+            "phase_ms_per_iter": {k: round(v / K, 5) for k, v in ph.items() if k != "total"}}
     return {"workload": f"disk deformation, {w.m:,} triangles, 16 handles, K={K}, checkpoint every {every}",
             "plain_s_per_iter": min(plain), "fwd_bwd_s_per_iter": min(fb), "ratio": min(fb) / min(plain),
-            "autotune_s": tune, "launch": launch}
+            "autotune_s": tune, "launch": launch, "factor_nnz": info["factor_nnz"], "roofline_solve": roof}
 
 
 def batched_leg(iters: int = 200):

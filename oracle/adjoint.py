@@ -113,9 +113,14 @@ def _setup(V, T, rho):
     return B, w, rho * w
 
 
-def run_jvp(V, T, energy, rho, pinned_idx, pins, K, dV, dpins):
+def run_jvp(V, T, energy, rho, pinned_idx, pins, K, dV, dpins, factor=None):
     """Loss L = sum_i w_i f(P_i^K) and its directional derivative along
-    (dV, dpins), with W^0 = V.  Returns (L, dL)."""
+    (dV, dpins), with W^0 = V.  Returns (L, dL).
+
+    factor(L_FF) -> object with .solve(b) factorises the free-vertex block;
+    the default is SciPy's sparse LU.  Two factorisations agree in exact
+    arithmetic, so the spread of their results measures how strongly the K
+    iterations amplify rounding."""
     V = np.asarray(V, dtype=np.float64)
     T = np.asarray(T, dtype=np.int64)
     n, d = V.shape
@@ -134,7 +139,7 @@ def run_jvp(V, T, energy, rho, pinned_idx, pins, K, dV, dpins):
     G = A.gradient_operator(B, T, n)
     dG = A.gradient_operator(dB, T, n)
     L = A.global_matrix(G, mu, d)
-    lu = spla.splu(L[free][:, free].tocsc())
+    lu = (factor or spla.splu)(L[free][:, free].tocsc())
     Mrep = np.repeat(mu, d)
     dMrep = np.repeat(dmu, d)
     # initial state W^0 = V: J^0 = I, so U^0 = P^0 = I, Lambda^0 = 0, no tangent

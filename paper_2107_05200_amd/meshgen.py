@@ -33,7 +33,9 @@ class Workload:
     V : (n, d_in) float64 source vertices.
     T : (m, d+1) int32 elements, positively oriented.
     pinned_idx : (p,) int32, pinned_pos : (p, d) float64 pinned targets.
-    x0 : (n, d) float64 initial map (pinned rows equal ``pinned_pos``).
+    x0 : (n, d) float64 initial map.  Its pinned rows need not equal
+         ``pinned_pos`` (the deformation workloads start from x0 = V);
+         the first W-step puts them there.
     """
     name: str
     V: np.ndarray
@@ -380,3 +382,18 @@ WORKLOADS = {
     "twisted_cube": lambda: twisted_cube(),
     "disk_deformation": lambda: disk_deformation(),
 }
+
+
+def unit_tangents(w: Workload, count: int, seed_c: int = 21):
+    """``count`` random unit directions over (rest vertices, pinned targets):
+    for each, dV ~ N(0, 1) of V's shape, then dp ~ N(0, 1) of the targets'
+    shape, both divided by the joint Euclidean norm.  Returns a list of
+    (dV, dp)."""
+    rng = rng_for(seed_c)
+    out = []
+    for _ in range(count):
+        dV = rng.normal(size=w.V.shape)
+        dp = rng.normal(size=w.pinned_pos.shape)
+        nrm = math.sqrt(float((dV ** 2).sum() + (dp ** 2).sum()))
+        out.append((dV / nrm, dp / nrm))
+    return out

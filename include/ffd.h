@@ -20,8 +20,10 @@
  *    hold the documented number of elements.  The handle owns its own device
  *    and host memory and frees it in ffd_destroy.
  *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
- *    stream).  Every call after ffd_create only enqueues work on that stream
- *    (no host synchronisation) except ffd_get_history, which synchronises.
+ *    stream).  A call after ffd_create only enqueues work on that stream
+ *    (no host synchronisation) unless its comment says that it synchronises
+ *    (ffd_get_history, the loops with a termination test, rescaling, the
+ *    timing and tuning calls).
  *  - Layouts: the map (W of the paper) is n x d row-major float64 in the
  *    caller's vertex order.  Element arrays (U, P, Lambda, W_el = U P) are
  *    m x d x d row-major in the caller's element order, float32 when the

@@ -546,7 +546,7 @@ def main():
         _oracle_fullsize_worker(int(args.oracle_worker[0]), int(args.oracle_worker[1]), args.oracle_worker[2])
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU (the multi-GPU path is a design, not code); --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 

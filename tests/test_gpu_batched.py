@@ -186,7 +186,7 @@ def test_full_batch_matches_oracle_on_sampled_charts(gpu_lib, prec):
     bs.init(x0).iterate(200, graph=True)
     st = {k: v.cpu().numpy().astype(np.float64) for k, v in bs.get_state().items()}
     torch.cuda.synchronize()
-    worst_x = worst_w = worst_e = 0.0
+    worst_x = worst_w = worst_e = worst_l = 0.0
     for j in pick:
         w = ws[j]
         r = O.OracleSolver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos)
@@ -198,7 +198,13 @@ def test_full_batch_matches_oracle_on_sampled_charts(gpu_lib, prec):
         ev = np.linalg.eigvalsh(0.5 * (P + np.transpose(P, (0, 2, 1))))
         E = float(np.sum(O.element_geometry(w.V, w.T)[1] * O.energy_of_spd_eigs(ev, w.energy)))
         ee = abs(E - r.history.col("E_P")[-1]) / abs(r.history.col("E_P")[-1])
-        say(f"  chart {j} (m={w.m}, energy {w.energy}): map {ex:.2e} W_el {ew:.2e} E_P {ee:.2e}")
+        el = rel(st["Lam"][eo[j]:eo[j + 1]], r.Lam)
+        say(f"  chart {j} (m={w.m}, energy {w.energy}): map {ex:.2e} W_el {ew:.2e} Lambda {el:.2e} E_P {ee:.2e}")
         worst_x, worst_w, worst_e = max(worst_x, ex), max(worst_w, ew), max(worst_e, ee)
+        worst_l = max(worst_l, el)
     assert worst_e <= 1e-4
+    # Lambda adds the float32 rounding of J - U P every iteration while its
+    # own norm is small against |J|: 1e-4 in float32 (measured <= 4.2e-5),
+    # 1e-5 in float64 (measured <= 2e-10)
     assert worst_x <= 1e-5 and worst_w <= 1e-5, (worst_x, worst_w)
+    assert worst_l <= (1e-5 if prec == 64 else 1e-4), worst_l

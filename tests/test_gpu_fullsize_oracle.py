@@ -12,7 +12,9 @@ curves (e_prim, e_dual, E_P) at every iteration.  Gates (the per-iteration
 relative bar of 1e-5 on W_el and the map, 1e-4 on the final energy):
   float64: map and W_el <= 1e-5 at every sampled iteration, final E_P <= 1e-4;
   float32: the same (the float32 element steps stay within 1e-5 of the
-  float64 oracle over the whole run); all errors printed.  e_prim of a
+  float64 oracle over the whole run); the scaled dual Lambda over the
+  sampled elements within 1e-5 (float64) and 1e-4 (float32, measured 4e-6);
+  all errors printed.  e_prim of a
   float32 run stops decreasing at the float32 rounding level of |J - U P|,
   so its curve is printed, not gated."""
 import os
@@ -67,7 +69,7 @@ def test_free_running_against_oracle_fixture(gpu_lib, name, prec):
     g.init(w.x0).autotune()
     g.init(w.x0)
     done = 0
-    worst = {"map": 0.0, "wel": 0.0}
+    worst = {"map": 0.0, "wel": 0.0, "lam": 0.0}
     for k in fx["iters"]:
         g.iterate(k - done, graph=True)
         done = k
@@ -82,6 +84,7 @@ def test_free_running_against_oracle_fixture(gpu_lib, name, prec):
             f"largest per row: map {m['map']:.2e} W_el {m['wel']:.2e} Lambda {m['lam']:.2e}")
         worst["map"] = max(worst["map"], e["map"])
         worst["wel"] = max(worst["wel"], e["wel"])
+        worst["lam"] = max(worst["lam"], e["lam"])
     h = g.history()
     H = fx["hist"]
     assert h.shape[0] == H.shape[0] == iters
@@ -95,4 +98,7 @@ def test_free_running_against_oracle_fixture(gpu_lib, name, prec):
     assert eP[-1] <= 1e-4
     assert h[-1, 5] == H[-1, 5]
     bound = 1e-5 if prec == 64 else FP32_BOUND[name]
+    # Lambda adds the float32 rounding of J - U P every iteration while its own
+    # norm is small against |J|: 1e-4 in float32, 1e-5 in float64
     assert worst["map"] <= bound and worst["wel"] <= bound, worst
+    assert worst["lam"] <= (1e-5 if prec == 64 else 1e-4), worst

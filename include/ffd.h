@@ -356,7 +356,11 @@ ffd_status ffd_get_vertex_order(ffd_handle h, int32_t* order_host);
 /* Adjoint, forward part: run n_iter iterations of Algorithm 1 from the
  * current state (as ffd_iterate, appending history) and keep a device
  * checkpoint of the state every checkpoint_every iterations, for
- * ffd_adjoint_backward.  The adjoint differentiates the iteration with
+ * ffd_adjoint_backward, which recomputes checkpoint_every - 1 iterations per
+ * checkpoint.  Memory: ceil(n_iter / checkpoint_every) + checkpoint_every + 1
+ * copies of the element state and map (U, P, Lambda, |grad f|^2, corner
+ * vectors, map); checkpoint_every = 1 keeps every state and recomputes
+ * nothing.  The adjoint differentiates the iteration with
  * mu_i = rho w_i, no general constraints and no proximal term: a rescaled
  * handle, a constrained one and one with h_mode 1 give FFD_ERR_STATE. */
 ffd_status ffd_adjoint_forward(ffd_handle h, int32_t n_iter, int32_t checkpoint_every, void* stream);
@@ -375,7 +379,8 @@ ffd_status ffd_adjoint_forward(ffd_handle h, int32_t n_iter, int32_t checkpoint_
  *  V_bar_dev: optional device n x dim_in float64 output (rest vertices; needs
  *    dim_in == simplex_dim and assumes W^0 = V, for which the initial state
  *    does not depend on V).
- * The handle's state is left as it was after the forward part. */
+ * The gradients do not depend on checkpoint_every (bitwise).  The handle's
+ * state is left as it was after the forward part. */
 ffd_status ffd_adjoint_backward(ffd_handle h, const void* Pbar_dev, int32_t energy_loss, double* pins_bar_dev,
                                 double* V_bar_dev, void* stream);
 

@@ -727,7 +727,7 @@ ffd_status ffd_adjoint_forward(ffd_handle h, int32_t n_iter, int32_t checkpoint_
         *pp = nullptr;
       }
     HIP_TRY(h->alloc(&h->adj_ck, sb * nslots));
-    HIP_TRY(h->alloc(&h->adj_seg, sb * (checkpoint_every + 1)));
+    HIP_TRY(h->alloc(&h->adj_seg, sb * checkpoint_every));  // recomputed states 1 .. every - 1
     HIP_TRY(h->alloc(&h->adj_fin, sb));
     h->adj_nslots = nslots;
   }
@@ -774,14 +774,22 @@ ffd_status ffd_adjoint_backward(ffd_handle h, const void* Pbar_dev, int32_t ener
   const int64_t nseg = (K + every - 1) / every;
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t start = seg * every, len = std::min(every, K - start);
-    HIP_TRY(copy_state3(h, h->adj_ck + sb * seg, nullptr, h->adj_seg, s));  // live state and slot 0
-    for (int64_t t = 1; t <= len; ++t) {
+    // states of the segment: t = 0 is its checkpoint; 1 .. len - 1 are
+    // recomputed from it; of the state after the segment only the map is read,
+    // and it is the next checkpoint's (the final state's for the last
+    // segment), bitwise what a recomputation would give.  With a checkpoint
+    // every iteration nothing is recomputed.
+    char* const ck = h->adj_ck + sb * seg;
+    const double* const xlast = slot_view(h, seg + 1 < nseg ? h->adj_ck + sb * (seg + 1) : h->adj_fin).x;
+    auto state = [&](int64_t t) { return slot_view(h, t == 0 ? ck : h->adj_seg + sb * t); };
+    if (len > 1) HIP_TRY(load_state(h, ck, s));
+    for (int64_t t = 1; t < len; ++t) {
       one_iteration(h, s, nullptr, false);
       HIP_TRY(save_state(h, h->adj_seg + sb * t, s));
     }
     for (int64_t t = len; t >= 1; --t) {
-      const SlotView prev = slot_view(h, h->adj_seg + sb * (t - 1));
-      const double* xk = slot_view(h, h->adj_seg + sb * t).x;
+      const SlotView prev = state(t - 1);
+      const double* xk = t == len ? xlast : state(t).x;
       for (const auto& g : h->segs) SEG_CASES(launch_adj_local, h, g, prev, xk, s)
       hipLaunchKernelGGL((d == 2 ? k_adj_gather<2> : k_adj_gather<3>), dim3(nblk(n)), dim3(kBlock), 0, s, h->nF, n,
                          h->av_ptr, h->av_idx, h->gadj, h->xbar, h->pinsbar, 1.0);

@@ -78,7 +78,7 @@ def test_adjoint_checkpoint_spacing_is_invisible(gpu_lib):
     w = mg.disk_deformation(R=7)
     say("case: adjoint checkpoint spacing")
     outs = []
-    for every in (1, 4, 11):
+    for every in (1, 4, 11, 20):  # 20 > K: one segment
         s, loss, pb, vb = _gpu_grads(w, 32, 11, every)
         st = s.get_state()
         torch.cuda.synchronize()

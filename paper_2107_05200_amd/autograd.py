@@ -4,7 +4,8 @@
 from the identity map W^0 = V with the handles pinned at ``pins`` and returns
 the final energy sum_i w_i f(P_i^K).  Its backward pass is the library's
 hand-written adjoint (ffd_adjoint_backward), which recomputes the iterations
-from device checkpoints taken every ``checkpoint_every`` iterations.
+between device checkpoints taken every ``checkpoint_every`` iterations
+(``checkpoint_every=1`` keeps every state and recomputes nothing).
 """
 from __future__ import annotations
 

@@ -32,7 +32,7 @@ FP32_NONPACKED_TFLOPS = 78.6  # 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz, one
 MEASURED_TRAFFIC = {
     # (source hash, element-step precision): per-iteration bytes and counters
     # (profiles/twisted_cube_64_hbm_traffic.md, profiles/twisted_cube_64_local_step_valu.md)
-    ("d0a337a9858853da", 32): {"solve": 3155.5e6, "local": 407.4e6, "local_flop_per_elem": 2258.3,
+    ("599c8a08c6153d73", 32): {"solve": 3173.0e6, "local": 407.3e6, "local_flop_per_elem": 2258.2,
                            "local_valu_per_wave": 2628.1},
 }
 

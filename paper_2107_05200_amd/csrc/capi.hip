@@ -40,6 +40,23 @@ ffd_status scratch_for_current_device(double** out) {
   return FFD_OK;
 }
 
+// Checks every creating entry point shares, made before any array of the
+// caller is read: the mesh's dimensions, the option values, the pinned list
+// and the finiteness of the pinned positions.
+ffd_status check_mesh_options(const ffd_mesh& M, const ffd_options& O) {
+  const int d = M.simplex_dim, din = M.dim_in;
+  if (!(d == 2 || d == 3) || !(din == d || (d == 2 && din == 3)))
+    return fail(FFD_ERR_INVALID_ARG, "unsupported (simplex_dim, dim_in)");
+  if (!(O.energy == 0 || O.energy == 1)) return fail(FFD_ERR_INVALID_ARG, "energy must be 0 or 1");
+  if (!(O.precision == 32 || O.precision == 64)) return fail(FFD_ERR_INVALID_ARG, "precision must be 32 or 64");
+  if (!(O.h_mode == 0 || O.h_mode == 1)) return fail(FFD_ERR_INVALID_ARG, "h_mode must be 0 or 1");
+  if (O.n_pinned < 0 || (O.n_pinned > 0 && !O.pinned_idx)) return fail(FFD_ERR_INVALID_ARG, "bad pinned vertex list");
+  if (O.n_pinned > 0 && O.pinned_pos)
+    for (int64_t i = 0; i < O.n_pinned * d; ++i)
+      if (!std::isfinite(O.pinned_pos[i])) return fail(FFD_ERR_NOT_FINITE, "non-finite pinned position");
+  return FFD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -53,20 +70,13 @@ extern "C" {
 ffd_status ffd_create(const ffd_mesh* mesh, const ffd_options* opt, ffd_handle* out) {
   if (!mesh || !opt || !out) return fail(FFD_ERR_INVALID_ARG, "NULL argument");
   *out = nullptr;
-  if (!(opt->energy == 0 || opt->energy == 1)) return fail(FFD_ERR_INVALID_ARG, "energy must be 0 or 1");
-  if (!(opt->precision == 32 || opt->precision == 64)) return fail(FFD_ERR_INVALID_ARG, "precision must be 32 or 64");
-  if (!(opt->h_mode == 0 || opt->h_mode == 1)) return fail(FFD_ERR_INVALID_ARG, "h_mode must be 0 or 1");
-
-  if (opt->n_pinned < 0 || (opt->n_pinned > 0 && !opt->pinned_idx))
-    return fail(FFD_ERR_INVALID_ARG, "bad pinned vertex list");
+  const ffd_status chk = check_mesh_options(*mesh, *opt);
+  if (chk != FFD_OK) return chk;
   const int d = mesh->simplex_dim;
   std::vector<int32_t> pins;
   bool auto_pinned = false;
   if (opt->n_pinned > 0) {
     pins.assign(opt->pinned_idx, opt->pinned_idx + opt->n_pinned);
-    if (opt->pinned_pos)
-      for (int64_t i = 0; i < opt->n_pinned * d; ++i)
-        if (!std::isfinite(opt->pinned_pos[i])) return fail(FFD_ERR_NOT_FINITE, "non-finite pinned position");
   } else if (opt->auto_pin) {
     pins.push_back(0);
     auto_pinned = true;
@@ -82,24 +92,16 @@ ffd_status ffd_create_constrained(const ffd_mesh* mesh, const ffd_options* opt, 
   *out = nullptr;
   if (con->n_rows <= 0 || con->n_rows > kMaxConstraints || !con->row_ptr || !con->col_idx || !con->val || !con->rhs)
     return fail(FFD_ERR_INVALID_ARG, "constraints: 1 to 1024 rows with row_ptr, col_idx, val and rhs required");
-  if (!(opt->energy == 0 || opt->energy == 1)) return fail(FFD_ERR_INVALID_ARG, "energy must be 0 or 1");
-  if (!(opt->precision == 32 || opt->precision == 64)) return fail(FFD_ERR_INVALID_ARG, "precision must be 32 or 64");
-  if (!(opt->h_mode == 0 || opt->h_mode == 1)) return fail(FFD_ERR_INVALID_ARG, "h_mode must be 0 or 1");
-  if (opt->n_pinned < 0 || (opt->n_pinned > 0 && !opt->pinned_idx))
-    return fail(FFD_ERR_INVALID_ARG, "bad pinned vertex list");
+  const ffd_status chk = check_mesh_options(*mesh, *opt);
+  if (chk != FFD_OK) return chk;
   const int d = mesh->simplex_dim;
-  if (!(d == 2 || d == 3)) return fail(FFD_ERR_INVALID_ARG, "unsupported simplex_dim");
   for (int64_t i = 0; i < con->n_rows * d; ++i)
     if (!std::isfinite(con->rhs[i])) return fail(FFD_ERR_NOT_FINITE, "non-finite constraint right-hand side");
   std::vector<int32_t> pins;
   std::vector<double> ppos;
   if (opt->n_pinned > 0) {
     pins.assign(opt->pinned_idx, opt->pinned_idx + opt->n_pinned);
-    if (opt->pinned_pos) {
-      for (int64_t i = 0; i < opt->n_pinned * d; ++i)
-        if (!std::isfinite(opt->pinned_pos[i])) return fail(FFD_ERR_NOT_FINITE, "non-finite pinned position");
-      ppos.assign(opt->pinned_pos, opt->pinned_pos + opt->n_pinned * d);
-    }
+    if (opt->pinned_pos) ppos.assign(opt->pinned_pos, opt->pinned_pos + opt->n_pinned * d);
   }
   // with constraints no vertex is fixed automatically (the W-step text fixes
   // the first vertex only when there are no constraints)
@@ -155,8 +157,10 @@ ffd_status ffd_batch_create(const ffd_mesh* meshes, const ffd_options* opts, int
   *out = nullptr;
   const ffd_options& o0 = opts[0];
   const int d = meshes[0].simplex_dim, din = meshes[0].dim_in;
-  if (!(o0.precision == 32 || o0.precision == 64)) return fail(FFD_ERR_INVALID_ARG, "precision must be 32 or 64");
-  if (!(o0.h_mode == 0 || o0.h_mode == 1)) return fail(FFD_ERR_INVALID_ARG, "h_mode must be 0 or 1");
+  for (int32_t b = 0; b < n_meshes; ++b) {
+    const ffd_status chk = check_mesh_options(meshes[b], opts[b]);
+    if (chk != FFD_OK) return chk;
+  }
   const bool with_pos = o0.n_pinned > 0 && o0.pinned_pos != nullptr;
   std::vector<double> V;
   std::vector<int32_t> T, pins;
@@ -169,9 +173,7 @@ ffd_status ffd_batch_create(const ffd_mesh* meshes, const ffd_options* opts, int
     if (M.simplex_dim != d || M.dim_in != din) return fail(FFD_ERR_INVALID_ARG, "meshes of a batch share d and dim_in");
     if (O.precision != o0.precision || O.h_mode != o0.h_mode || O.rho != o0.rho)
       return fail(FFD_ERR_INVALID_ARG, "meshes of a batch share precision, h_mode and rho");
-    if (!(O.energy == 0 || O.energy == 1)) return fail(FFD_ERR_INVALID_ARG, "energy must be 0 or 1");
     if (!M.V || !M.T || M.n_vertices <= 0 || M.n_elements <= 0) return fail(FFD_ERR_INVALID_ARG, "empty mesh");
-    if (O.n_pinned < 0 || (O.n_pinned > 0 && !O.pinned_idx)) return fail(FFD_ERR_INVALID_ARG, "bad pinned vertex list");
     const int64_t vb = voff.back();
     if (vb + M.n_vertices > INT32_MAX / 2) return fail(FFD_ERR_INVALID_ARG, "batch too large");
     V.insert(V.end(), M.V, M.V + M.n_vertices * din);
@@ -188,11 +190,7 @@ ffd_status ffd_batch_create(const ffd_mesh* meshes, const ffd_options* opts, int
           return fail(FFD_ERR_INVALID_ARG, "pinned index out of range");
         pins.push_back(static_cast<int32_t>(O.pinned_idx[i] + vb));
       }
-      if (with_pos) {
-        for (int64_t i = 0; i < O.n_pinned * d; ++i)
-          if (!std::isfinite(O.pinned_pos[i])) return fail(FFD_ERR_NOT_FINITE, "non-finite pinned position");
-        ppos.insert(ppos.end(), O.pinned_pos, O.pinned_pos + O.n_pinned * d);
-      }
+      if (with_pos) ppos.insert(ppos.end(), O.pinned_pos, O.pinned_pos + O.n_pinned * d);
     } else if (O.auto_pin) {
       if (with_pos) return fail(FFD_ERR_INVALID_ARG, "an auto-pinned mesh in a batch with given pin positions");
       pins.push_back(static_cast<int32_t>(vb));
@@ -225,8 +223,8 @@ ffd_status ffd_batch_layout(ffd_handle h, int64_t* vertex_offsets, int64_t* elem
 
 ffd_status ffd_analyze(const ffd_mesh* mesh, const ffd_options* opt, ffd_info* info, double* selfcheck_residual) {
   if (!mesh || !opt || !info) return fail(FFD_ERR_INVALID_ARG, "NULL argument");
-  if (opt->n_pinned < 0 || (opt->n_pinned > 0 && !opt->pinned_idx))
-    return fail(FFD_ERR_INVALID_ARG, "bad pinned vertex list");
+  const ffd_status chk = check_mesh_options(*mesh, *opt);
+  if (chk != FFD_OK) return chk;
   std::vector<int32_t> pins;
   if (opt->n_pinned > 0) pins.assign(opt->pinned_idx, opt->pinned_idx + opt->n_pinned);
   else if (opt->auto_pin) pins.push_back(0);

@@ -84,6 +84,28 @@ def test_error_codes():
     with pytest.raises(binding.FFDError) as e:
         binding.analyze(w.V, w.T, w.energy, w.rho, np.array([0, 0]), None)
     assert e.value.status == -1
+    # option values and pinned positions are checked as ffd_create checks them
+    with pytest.raises(binding.FFDError) as e:
+        binding.analyze(w.V, w.T, 7, w.rho, w.pinned_idx, w.pinned_pos)
+    assert e.value.status == -1
+    with pytest.raises(binding.FFDError) as e:
+        binding.analyze(w.V, w.T, w.energy, w.rho, w.pinned_idx, np.full_like(w.pinned_pos, np.inf))
+    assert e.value.status == -4
+    for bad in (0.0, -1.0, float("nan")):
+        with pytest.raises(binding.FFDError) as e:
+            binding.analyze(w.V, w.T, w.energy, bad, w.pinned_idx, w.pinned_pos)
+        assert e.value.status == -1
+    # empty mesh; a simplex dimension or input dimension the solver has no form for
+    with pytest.raises(binding.FFDError) as e:
+        binding.analyze(w.V, w.T[:0], w.energy, w.rho, w.pinned_idx, w.pinned_pos)
+    assert e.value.status == -1
+    T4 = np.concatenate([w.T, w.T[:, :2]], axis=1)  # 5 vertices per element
+    with pytest.raises(binding.FFDError) as e:
+        binding.analyze(np.concatenate([w.V, w.V[:, :2]], axis=1), T4, w.energy, w.rho, w.pinned_idx, None)
+    assert e.value.status == -1
+    with pytest.raises(binding.FFDError) as e:  # triangles with 4-D source vertices
+        binding.analyze(np.concatenate([w.V, w.V[:, :1]], axis=1), w.T, w.energy, w.rho, w.pinned_idx, None)
+    assert e.value.status == -1
 
 
 def test_factor_matches_oracle_matrix_on_two_components():

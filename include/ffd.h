@@ -230,7 +230,8 @@ ffd_status ffd_iterate(ffd_handle h, int32_t n_iter, void* stream);
  * Errors: FFD_ERR_INVALID_ARG when the handle's history cannot hold
  * n_iter more records (ffd_iterate would grow it) or when the local step
  * needs more than the scratch holds ((ceil(m / block) + blocks / 256) x 11
- * float64: about 3M elements at the 64-element block); FFD_ERR_STATE
+ * float64: about 12M elements at the default 256-element block, 3M at the
+ * 64-element block the autotuner picks for the tet cube); FFD_ERR_STATE
  * before ffd_init. */
 ffd_status ffd_iterate_noalloc(ffd_handle h, int32_t n_iter, void* stream);
 

@@ -58,3 +58,22 @@ def test_noalloc_refuses_to_grow_the_history(gpu_lib):
     s.iterate_noalloc(3)
     assert s.iteration() == 3
     s.close()
+
+
+def test_noalloc_refuses_a_mesh_beyond_the_scratch(gpu_lib):
+    """A local step whose partial sums exceed the fixed scratch (4 MiB:
+    (ceil(m / block) + blocks / 256) x 11 float64, so about 12M elements at
+    the default block of 256) is refused before anything runs; the handle
+    still iterates with ffd_iterate."""
+    from paper_2107_05200_amd.binding import FFDError, Solver
+    w = mg.flat_grid(grid=2500)  # 12,490,002 triangles
+    say(f"case: ffd_iterate_noalloc refusal on {w.name} (m={w.m})")
+    s = Solver(w.V, w.T, w.energy, w.rho, w.pinned_idx, w.pinned_pos, precision=32)
+    s.init(w.x0)
+    with pytest.raises(FFDError) as e:
+        s.iterate_noalloc(1)
+    assert "scratch" in str(e.value)
+    assert s.iteration() == 0
+    s.iterate(1)
+    assert s.iteration() == 1
+    s.close()
